@@ -1,0 +1,213 @@
+/*
+ * hlu.h -- C-ABI of the MI355X (gfx950) hierarchical-matrix LU library.
+ *
+ * The library builds an H-matrix for the d=3 Laplace kernel of the paper's
+ * BEM problems (Sec. 5.1) from surface points, an admissibility parameter
+ * eta and a leaf size (cluster tree: Algorithm 1; block tree: Algorithm 2),
+ * factors it with the recursive H-LU (the O1.1-O5.5 sequence of Sec. 3.1,
+ * with low-rank arithmetic of Sec. 3.1 "Low-rank blocks"), and solves with
+ * the factors, optionally refining the solution against an accurate H-matrix
+ * copy of the operator.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (hipMalloc / torch CUDA
+ *    tensors on the current device); every other pointer is host memory.
+ *  - Device calls take a hipStream_t (passed as void*) and are asynchronous
+ *    on that stream.  Errors the device detects (zero pivots, refinement
+ *    that does not converge) surface at hlu_sync.
+ *  - Matrices and vectors are FP64, column-major, in the caller's original
+ *    point order, with a leading dimension `ld` >= n.
+ *  - No exception crosses the ABI; every call returns an hlu_status and
+ *    hlu_last_error() gives a thread-local message for the last failure.
+ *  - Ownership: host inputs are copied at plan time; the device buffer
+ *    passed to hlu_bind belongs to the caller, must stay alive until
+ *    hlu_destroy, and is never freed by the library.
+ *  - One handle may be used by one host thread at a time; distinct handles
+ *    are independent.
+ */
+#ifndef HLU_H
+#define HLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hlu_handle_s* hlu_handle;
+
+typedef enum {
+    HLU_OK = 0,
+    HLU_ERR_ARG = 1,            /* invalid argument (NULL, n<1, NaN input, ...) */
+    HLU_ERR_NOMEM = 2,          /* bound buffer smaller than hlu_required_bytes */
+    HLU_ERR_DEVICE = 3,         /* a HIP runtime call failed */
+    HLU_ERR_SINGULAR = 4,       /* zero pivot in a diagonal leaf (info = row) */
+    HLU_ERR_NOT_CONVERGED = 5,  /* refinement stopped above refine_tol */
+    HLU_ERR_STATE = 6           /* call out of order (e.g. solve before factor) */
+} hlu_status;
+
+/* Entries of the collocation matrix for the d=3 Laplace kernel
+ * g(x,y) = 1/(4 pi |x-y|) (Sec. 5.1) between panel centroids x_i:
+ *   WEIGHTED: A_ij = area_j / (4 pi |x_i - x_j|)   (one-point quadrature)
+ *   POINT:    A_ij = 1 / (4 pi |x_i - x_j|)
+ * and in both A_ii = 2 sqrt(area_i/pi)/(4 pi) sqrt(pi) + 1. */
+typedef enum { HLU_KERNEL_LAPLACE3D_WEIGHTED = 0, HLU_KERNEL_LAPLACE3D_POINT = 1 } hlu_kernel;
+
+/* FP64: all factors FP64.  MIXED: low-rank factors stored in FP32 and their
+ * triangular solves and products computed in FP32; dense leaves, pivoting,
+ * the truncation cores and the refinement residual stay FP64. */
+typedef enum { HLU_PREC_FP64 = 0, HLU_PREC_MIXED = 1 } hlu_precision;
+
+typedef struct {
+    hlu_kernel kernel;
+    double eta;               /* admissibility: min(diam) <= eta * dist (Sec. 2) */
+    int leaf_size;            /* C_lf of Algorithm 1: split while size > C_lf   */
+    int fixed_rank;           /* > 0: every truncation keeps this rank          */
+    double eps_factor;        /* truncation tolerance of the factored copy      */
+    int rank_cap_factor;      /* rank capacity of the factored copy (<= 32)     */
+    double eps_matvec;        /* tolerance of the refinement operator copy      */
+    int rank_cap_matvec;      /* rank capacity of that copy (<= 64)             */
+    hlu_precision precision;
+    double refine_tol;        /* backward-error target of hlu_solve (0: no IR)  */
+    int refine_max_iter;      /* at most this many refinement steps              */
+    int max_nrhs;             /* largest nrhs hlu_solve / hlu_matvec will see   */
+    uint64_t seed;            /* reserved for randomised construction           */
+} hlu_params;
+
+typedef struct {
+    int64_t info;             /* first zero pivot (1-based, original order) or 0 */
+    int iters;                /* refinement steps taken by the last solve        */
+    double eta_hist[16];      /* backward error per refinement step              */
+    double eta_final;
+    int64_t cap_hits;         /* truncations that hit the rank capacity          */
+    int64_t max_rank;         /* largest rank in the factored copy               */
+} hlu_info;
+
+/* Plan statistics (host side, available right after hlu_plan). */
+typedef struct {
+    int64_t n, leaves, dense_blocks, lowrank_blocks;
+    int64_t ops_factor, waves_factor, ops_solve, waves_solve;
+    double flops_factor_model;   /* model flops at capacity ranks (upper bound) */
+    int64_t bytes_factor_region, bytes_matvec_region, bytes_scratch, bytes_total;
+} hlu_plan_stats;
+
+/* Build the cluster tree and block tree for n points (xyz: n x 3 row-major,
+ * area: n, host), assemble all blocks on the host (dense near field exactly;
+ * far-field blocks by adaptive cross approximation followed by QR + SVD
+ * recompression to eps_factor and eps_matvec), and build the static op
+ * schedule of the factorisation, the solve and the matvec.
+ * Returns HLU_ERR_ARG for NULL pointers, n < 1, non-finite input, leaf < 1,
+ * eta < 0, caps outside [1,32] / [1,64] or max_nrhs outside [1,64]. */
+hlu_status hlu_plan(const double* xyz, const double* area, int64_t n,
+                    const hlu_params* p, hlu_handle* out);
+
+/* Device bytes the handle needs (factor copy, pristine copy, matvec copy,
+ * scratch, schedules and solve workspace).  0 for a NULL handle. */
+size_t hlu_required_bytes(hlu_handle h);
+
+/* Bind a caller-owned device buffer of at least hlu_required_bytes bytes
+ * (256-byte aligned) and upload the schedules.  HLU_ERR_NOMEM if too small. */
+hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes);
+
+/* Copy the assembled H-matrix (factor copy, its pristine copy and the matvec
+ * copy) into the bound buffer on `stream`.  Requires hlu_bind. */
+hlu_status hlu_assemble(hlu_handle h, void* stream);
+
+/* Restore the factor copy from the pristine copy (device-to-device). */
+hlu_status hlu_reset(hlu_handle h, void* stream);
+
+/* H-LU of the factor copy in place (Sec. 3.1 sequence, recursive), one
+ * launch per kernel type per wave of the static schedule.  Zero pivots are
+ * recorded on the device and reported by hlu_sync. */
+hlu_status hlu_factor(hlu_handle h, void* stream);
+
+/* hlu_factor with a HIP event pair around every launch on `stream`;
+ * returns the summed launch durations (ms) and launch counts per op type
+ * (arrays of 8).  Synchronises the stream; used for roofline figures. */
+hlu_status hlu_factor_profile(hlu_handle h, void* stream, double* ms_per_type,
+                              int64_t* launches_per_type);
+
+/* Factor `count` handles with their schedules merged wave by wave, so ops
+ * of every matrix in a wave share one launch per kernel type. */
+hlu_status hlu_factor_batched(hlu_handle* hs, int count, void* stream);
+
+/* x = A^{-1} b for nrhs right-hand sides (b_dev, x_dev: n x nrhs, leading
+ * dimension ld, original order; they may alias).  With refine_tol > 0 the
+ * solution is refined with FP64 residuals of the matvec copy until the
+ * backward error max_j |r_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf) <=
+ * refine_tol (this call then synchronises the stream once per step).
+ * HLU_ERR_STATE before hlu_factor; HLU_ERR_ARG if nrhs > max_nrhs. */
+hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
+                     int64_t ld, void* stream);
+
+/* y = A_mv x with the matvec copy (original order, n x nrhs). */
+hlu_status hlu_matvec(hlu_handle h, const double* x_dev, double* y_dev, int nrhs,
+                      int64_t ld, void* stream);
+
+/* Wait for the stream work of this handle and report device-side status:
+ * HLU_ERR_SINGULAR (info set) or HLU_ERR_NOT_CONVERGED from the last solve. */
+hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out);
+
+/* Host-side check of the schedules and matvec tables (every panel inside
+ * the buffer at full capacity, operand shapes consistent).  hlu_bind runs
+ * it too and refuses to bind an invalid plan.  HLU_ERR_ARG on failure. */
+hlu_status hlu_validate(hlu_handle h);
+
+/* Plan statistics. */
+hlu_status hlu_get_stats(hlu_handle h, hlu_plan_stats* out);
+
+/* Per-op-type totals of the last factorisation (arrays of 8, indexed by op
+ * type: 0 getrf, 1-3 leaf solves, 4 panel products, 5 truncations, 6 dense
+ * updates, 7 zero fills): model flops, algorithmic bytes and op counts,
+ * summed from the records each kernel writes.  Synchronous. */
+hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* counts);
+
+/* Number of kernel launches per op type in the factor schedule (8 int64). */
+hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches);
+
+/* Cluster-order permutation: perm[p] = original index of position p (host
+ * array of n int64). */
+hlu_status hlu_get_perm(hlu_handle h, int64_t* perm);
+
+/* Export the factor copy (after hlu_factor, or the assembled one before) as
+ * a dense n x n column-major FP64 host array in cluster order: the lower
+ * part holds Lhat (diagonal leaf blocks P^T L), the upper part U, so
+ * A_H ~= Lhat * U.  For n <= 8192 only; synchronises the stream. */
+hlu_status hlu_export_factors(hlu_handle h, double* lhat, double* u, void* stream);
+
+/* Export the diagonal leaf pivots (n int32, 0-based row within the leaf,
+ * LAPACK order) after hlu_factor; synchronises the stream. */
+hlu_status hlu_export_pivots(hlu_handle h, int32_t* piv, void* stream);
+
+/* Release host-side state.  Never frees the caller's device buffer. */
+void hlu_destroy(hlu_handle h);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* hlu_last_error(void);
+
+/* ---- single-kernel entry points used by the kernel parity tests -------- */
+
+/* Batched LU with partial pivoting of `count` dense b x b column-major FP64
+ * blocks stored back to back (a_dev: count*b*b), pivots to piv_dev
+ * (count*b int32, 0-based LAPACK order) and the first zero pivot of each
+ * block (1-based, 0 if none) to info_dev (count int32).  b in [1, 64]. */
+hlu_status hlu_getrf_batched(double* a_dev, int32_t* piv_dev, int32_t* info_dev,
+                             int b, int count, void* stream);
+
+/* Best low-rank approximation of C - X Y^T (Sec. 3.1, truncated addition):
+ * U (m x kc), V (n x kc) hold C = U V^T on entry (kc <= 32); X (m x kx),
+ * Y (n x ky=kx) the update, kc + kx <= 64.  On exit U, V (capacity cap
+ * columns, leading dimensions m and n) hold the truncated result and
+ * *rank_dev its rank; fixed_rank > 0 keeps that rank, otherwise the
+ * smallest rank whose discarded singular values have Frobenius norm <=
+ * eps times the norm of the sum, capped at cap.  All FP64. */
+hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev,
+                            const double* X_dev, const double* Y_dev, int m, int n,
+                            int kc, int kx, int cap, double eps, int fixed_rank,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLU_H */

@@ -43,6 +43,15 @@ FOUR_PI = 4.0 * math.pi
 READING_WEIGHTED = 0   # A_ij = area_j / (4 pi |x_i - x_j|)
 READING_POINT = 1      # A_ij = 1 / (4 pi |x_i - x_j|)
 
+# model flop count of the executed operations (getrf 2b^3/3 - b^2/2 + 5b/6,
+# triangular solve m^2 n, product 2 m n k, truncation as in `truncate`);
+# reset by the caller, used only to express timings as GFLOP/s
+FLOPS = [0.0]
+
+
+def _count(f):
+    FLOPS[0] += f
+
 
 # ---------------------------------------------------------------------------
 # kernel entries (Sec. 5.1, d = 3 Laplace kernel g(x,y) = 1/(4 pi |x-y|))
@@ -257,6 +266,9 @@ def truncate(X, Y, rule):
     k = rule.choose(sig)
     U = Qx @ (u[:, :k] * sig[:k])
     V = Qy @ vt[:k].T
+    # QR of both stacks, core product, SVD (Golub-Van Loan count), recombination
+    _count(2.0 * (m + n) * K * K - 4.0 * K ** 3 / 3.0 + 2.0 * K ** 3 + 21.0 * K ** 3
+           + 2.0 * (m + n) * K * k)
     return U, V
 
 
@@ -333,8 +345,10 @@ class HMatrix:
 def mul(M, X):
     """M X for a block of any kind; X has |s| rows."""
     if M.kind == "F":
+        _count(2.0 * M.F.shape[0] * M.F.shape[1] * X.shape[1])
         return M.F @ X
     if M.kind == "R":
+        _count(2.0 * M.U.shape[1] * X.shape[1] * (M.U.shape[0] + M.V.shape[0]))
         return M.U @ (M.V.T @ X)
     out = np.zeros((M.t.size, X.shape[1]))
     for i, ti in enumerate(M.t.sons):
@@ -348,8 +362,10 @@ def mul(M, X):
 def mulT(M, X):
     """M^T X for a block of any kind; X has |t| rows."""
     if M.kind == "F":
+        _count(2.0 * M.F.shape[0] * M.F.shape[1] * X.shape[1])
         return M.F.T @ X
     if M.kind == "R":
+        _count(2.0 * M.U.shape[1] * X.shape[1] * (M.U.shape[0] + M.V.shape[0]))
         return M.V @ (M.U.T @ X)
     out = np.zeros((M.s.size, X.shape[1]))
     for i, ti in enumerate(M.t.sons):
@@ -386,6 +402,7 @@ def getrf(a):
         elif info == 0:
             info = k + 1
         a[k + 1:, k + 1:] -= np.outer(a[k + 1:, k], a[k, k + 1:])
+    _count(getrf_flops(b))
     return piv, info
 
 
@@ -405,6 +422,7 @@ def fwd(Lb, Y):
         apply_piv(Lb.piv, Y)
         Y[:] = sla.solve_triangular(Lb.F, Y, lower=True, unit_diagonal=True,
                                     check_finite=False)
+        _count(float(Y.shape[0]) ** 2 * Y.shape[1])
         return
     t0, t1 = Lb.t.sons
     Y0, Y1 = Y[_rows(Lb.t, t0)], Y[_rows(Lb.t, t1)]
@@ -418,6 +436,7 @@ def bwdT(Ub, Y):
     if Ub.kind == "F":
         Y[:] = sla.solve_triangular(Ub.F, Y, lower=False, trans="T",
                                     check_finite=False)
+        _count(float(Y.shape[0]) ** 2 * Y.shape[1])
         return
     t0, t1 = Ub.t.sons
     Y0, Y1 = Y[_rows(Ub.t, t0)], Y[_rows(Ub.t, t1)]
@@ -430,6 +449,7 @@ def bwd(Ub, Y):
     """Y := U^{-1} Y (backward substitution), rows of Y = t."""
     if Ub.kind == "F":
         Y[:] = sla.solve_triangular(Ub.F, Y, lower=False, check_finite=False)
+        _count(float(Y.shape[0]) ** 2 * Y.shape[1])
         return
     t0, t1 = Ub.t.sons
     Y0, Y1 = Y[_rows(Ub.t, t0)], Y[_rows(Ub.t, t1)]
@@ -476,6 +496,7 @@ def trsm_u(B, Ub, rule):
 def add_lr(C, X, Y, rule):
     """C := C - X Y^T, C of any kind; truncated when C is low-rank."""
     if C.kind == "F":
+        _count(2.0 * X.shape[0] * Y.shape[0] * X.shape[1])
         C.F -= X @ Y.T
     elif C.kind == "R":
         C.U, C.V = truncate(np.hstack([C.U, -X]), np.hstack([C.V, Y]), rule)
@@ -506,6 +527,7 @@ def gemm(C, A, B, rule):
             add_lr(C, A.F, B.F.T, rule)          # rank |r| product
         else:
             D = A.F @ B.F                          # t and s are leaves
+            _count(2.0 * A.F.shape[0] * A.F.shape[1] * B.F.shape[1])
             if C.kind == "F":
                 C.F -= D
             else:

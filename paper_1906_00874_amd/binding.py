@@ -1,0 +1,273 @@
+"""ctypes binding of include/hlu.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loaded first so that libhlu.so shares torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+build_lib_path = os.path.join(HERE, "libhlu.so")
+
+if not os.path.exists(build_lib_path):
+    raise ImportError(
+        f"{build_lib_path} is missing: build it with `python -c 'import __graft_entry__ as g; "
+        "g.build()'` (no CPU fallback exists)")
+
+lib = C.CDLL(build_lib_path)
+
+KERNEL_WEIGHTED, KERNEL_POINT = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+HLU_OK, HLU_ERR_ARG, HLU_ERR_NOMEM, HLU_ERR_DEVICE = 0, 1, 2, 3
+HLU_ERR_SINGULAR, HLU_ERR_NOT_CONVERGED, HLU_ERR_STATE = 4, 5, 6
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_DEVICE", 4: "ERR_SINGULAR",
+                5: "ERR_NOT_CONVERGED", 6: "ERR_STATE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("eta", C.c_double), ("leaf_size", C.c_int),
+                ("fixed_rank", C.c_int), ("eps_factor", C.c_double),
+                ("rank_cap_factor", C.c_int), ("eps_matvec", C.c_double),
+                ("rank_cap_matvec", C.c_int), ("precision", C.c_int),
+                ("refine_tol", C.c_double), ("refine_max_iter", C.c_int),
+                ("max_nrhs", C.c_int), ("seed", C.c_uint64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("info", C.c_int64), ("iters", C.c_int), ("eta_hist", C.c_double * 16),
+                ("eta_final", C.c_double), ("cap_hits", C.c_int64), ("max_rank", C.c_int64)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("leaves", C.c_int64), ("dense_blocks", C.c_int64),
+                ("lowrank_blocks", C.c_int64), ("ops_factor", C.c_int64),
+                ("waves_factor", C.c_int64), ("ops_solve", C.c_int64),
+                ("waves_solve", C.c_int64), ("flops_factor_model", C.c_double),
+                ("bytes_factor_region", C.c_int64), ("bytes_matvec_region", C.c_int64),
+                ("bytes_scratch", C.c_int64), ("bytes_total", C.c_int64)]
+
+
+_P = C.c_void_p
+_sig = {
+    "hlu_plan": (C.c_int, [_P, _P, C.c_int64, C.POINTER(Params), C.POINTER(_P)]),
+    "hlu_required_bytes": (C.c_size_t, [_P]),
+    "hlu_validate": (C.c_int, [_P]),
+    "hlu_bind": (C.c_int, [_P, _P, C.c_size_t]),
+    "hlu_assemble": (C.c_int, [_P, _P]),
+    "hlu_reset": (C.c_int, [_P, _P]),
+    "hlu_factor": (C.c_int, [_P, _P]),
+    "hlu_factor_batched": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "hlu_factor_profile": (C.c_int, [_P, _P, _P, _P]),
+    "hlu_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
+    "hlu_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
+    "hlu_sync": (C.c_int, [_P, _P, C.POINTER(Info)]),
+    "hlu_get_stats": (C.c_int, [_P, C.POINTER(PlanStats)]),
+    "hlu_factor_cost": (C.c_int, [_P, _P, _P, _P]),
+    "hlu_factor_batches": (C.c_int, [_P, _P]),
+    "hlu_get_perm": (C.c_int, [_P, _P]),
+    "hlu_export_factors": (C.c_int, [_P, _P, _P, _P]),
+    "hlu_export_pivots": (C.c_int, [_P, _P, _P]),
+    "hlu_destroy": (None, [_P]),
+    "hlu_last_error": (C.c_char_p, []),
+    "hlu_getrf_batched": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
+    "hlu_truncate_add": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_double, C.c_int, _P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class HLUError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != HLU_OK:
+        raise HLUError(st, lib.hlu_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def make_params(kernel=KERNEL_WEIGHTED, eta=2.0, leaf=32, fixed_rank=0, eps=1e-6, cap=32,
+                eps_mv=1e-12, cap_mv=64, precision=PREC_FP64, refine_tol=0.0,
+                refine_max_iter=10, max_nrhs=32, seed=0):
+    return Params(kernel, eta, leaf, fixed_rank, eps, cap, eps_mv, cap_mv, precision,
+                  refine_tol, refine_max_iter, max_nrhs, seed)
+
+
+class HLU:
+    """One H-matrix on one device: plan on construction; `bind_and_assemble`
+    allocates the device buffer through torch and uploads the blocks."""
+
+    def __init__(self, xyz, area, device="cuda", assemble=True, **kw):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        area = np.ascontiguousarray(area, dtype=np.float64)
+        self.n = xyz.shape[0]
+        self.params = make_params(**kw)
+        h = C.c_void_p()
+        _check(lib.hlu_plan(xyz.ctypes.data_as(_P), area.ctypes.data_as(_P), self.n,
+                            C.byref(self.params), C.byref(h)))
+        self.h = h
+        self.device = device
+        self.buf = None
+        if assemble:
+            self.bind_and_assemble()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.hlu_destroy(h)
+            self.h = None
+
+    # -- host-side queries ------------------------------------------------
+    @property
+    def required_bytes(self):
+        return int(lib.hlu_required_bytes(self.h))
+
+    def stats(self):
+        s = PlanStats()
+        _check(lib.hlu_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in PlanStats._fields_}
+
+    def perm(self):
+        p = np.empty(self.n, dtype=np.int64)
+        _check(lib.hlu_get_perm(self.h, p.ctypes.data_as(_P)))
+        return p
+
+    def validate(self):
+        _check(lib.hlu_validate(self.h))
+
+    def batches(self):
+        b = np.zeros(8, dtype=np.int64)
+        _check(lib.hlu_factor_batches(self.h, b.ctypes.data_as(_P)))
+        return b
+
+    # -- device ------------------------------------------------------------
+    def bind(self, buf=None):
+        nbytes = self.required_bytes
+        if buf is None:
+            buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        self.buf = buf
+        _check(lib.hlu_bind(self.h, C.c_void_p(buf.data_ptr() + off), nbytes))
+
+    def bind_and_assemble(self, stream=None):
+        self.bind()
+        _check(lib.hlu_assemble(self.h, _stream(stream)))
+
+    def reset(self, stream=None):
+        _check(lib.hlu_reset(self.h, _stream(stream)))
+
+    def factor(self, stream=None):
+        _check(lib.hlu_factor(self.h, _stream(stream)))
+
+    def factor_profile(self, stream=None):
+        """Factor with per-launch events; returns (ms per op type, launches)."""
+        ms = np.zeros(8)
+        ln = np.zeros(8, dtype=np.int64)
+        _check(lib.hlu_factor_profile(self.h, _stream(stream), ms.ctypes.data_as(_P),
+                                      ln.ctypes.data_as(_P)))
+        return ms, ln
+
+    def sync(self, stream=None, check=True):
+        inf = Info()
+        st = lib.hlu_sync(self.h, _stream(stream), C.byref(inf))
+        if check:
+            _check(st)
+        return st, inf
+
+    @staticmethod
+    def _cm(b):
+        """(n,) or (n, k) tensor -> column-major (k, n) contiguous FP64."""
+        if b.dim() == 1:
+            b = b[:, None]
+        return b.t().contiguous().to(torch.float64)
+
+    def solve(self, b, stream=None):
+        """x = A^{-1} b; b: CUDA tensor (n,) or (n, nrhs), original order."""
+        one = b.dim() == 1
+        bc = self._cm(b)
+        xc = torch.empty_like(bc)
+        nrhs = bc.shape[0]
+        _check(lib.hlu_solve(self.h, _ptr(bc), _ptr(xc), nrhs, self.n, _stream(stream)))
+        x = xc.t()
+        return x[:, 0] if one else x
+
+    def solve_cm(self, bc, xc, stream=None):
+        """Column-major solve on preallocated (nrhs, n) tensors."""
+        _check(lib.hlu_solve(self.h, _ptr(bc), _ptr(xc), bc.shape[0], self.n, _stream(stream)))
+
+    def matvec(self, x, stream=None):
+        one = x.dim() == 1
+        xc = self._cm(x)
+        yc = torch.empty_like(xc)
+        _check(lib.hlu_matvec(self.h, _ptr(xc), _ptr(yc), xc.shape[0], self.n, _stream(stream)))
+        y = yc.t()
+        return y[:, 0] if one else y
+
+    def factor_cost(self):
+        f = np.zeros(8)
+        b = np.zeros(8)
+        c = np.zeros(8, dtype=np.int64)
+        _check(lib.hlu_factor_cost(self.h, f.ctypes.data_as(_P), b.ctypes.data_as(_P),
+                                   c.ctypes.data_as(_P)))
+        return f, b, c
+
+    def export_factors(self, stream=None):
+        """(Lhat, U) dense in cluster order (numpy, n <= 8192)."""
+        L = np.zeros((self.n, self.n), order="F")
+        U = np.zeros((self.n, self.n), order="F")
+        _check(lib.hlu_export_factors(self.h, L.ctypes.data_as(_P), U.ctypes.data_as(_P),
+                                      _stream(stream)))
+        return L, U
+
+    def export_pivots(self, stream=None):
+        p = np.zeros(self.n, dtype=np.int32)
+        _check(lib.hlu_export_pivots(self.h, p.ctypes.data_as(_P), _stream(stream)))
+        return p
+
+
+def factor_batched(hs, stream=None):
+    arr = (C.c_void_p * len(hs))(*[h.h.value for h in hs])
+    _check(lib.hlu_factor_batched(arr, len(hs), _stream(stream)))
+
+
+def getrf_batched(a, stream=None):
+    """a: CUDA FP64 tensor (count, b, b) holding column-major blocks (i.e.
+    a[q] is the transpose of block q).  In place; returns (piv, info)."""
+    count, b, _ = a.shape
+    if not a.is_contiguous() or a.dtype != torch.float64:
+        raise ValueError("a must be a contiguous float64 tensor")
+    piv = torch.empty((count, b), dtype=torch.int32, device=a.device)
+    info = torch.empty((count,), dtype=torch.int32, device=a.device)
+    _check(lib.hlu_getrf_batched(_ptr(a), _ptr(piv), _ptr(info), b, count, _stream(stream)))
+    return piv, info
+
+
+def truncate_add(U, V, kc, X, Y, cap, eps, fixed_rank=0, stream=None):
+    """U: (cap, m) and V: (cap, n) column-major FP64 tensors (rows = columns
+    of the factor); X: (kx, m), Y: (kx, n).  In place; returns the rank."""
+    m, n = U.shape[1], V.shape[1]
+    kx = X.shape[0] if X is not None else 0
+    for t in (U, V) + ((X, Y) if kx else ()):
+        if not t.is_contiguous() or t.dtype != torch.float64:
+            raise ValueError("factors must be contiguous float64 tensors")
+    rank = torch.empty((1,), dtype=torch.int32, device=U.device)
+    _check(lib.hlu_truncate_add(_ptr(U), _ptr(V), _ptr(rank),
+                                _ptr(X) if kx else None, _ptr(Y) if kx else None,
+                                m, n, kc, kx, cap, eps, fixed_rank, _stream(stream)))
+    return int(rank.item())

@@ -1,0 +1,738 @@
+// C-ABI of the H-LU library: planning, binding, assembly upload, the
+// wave-by-wave executor of the static schedules, solve with iterative
+// refinement, matvec and the single-kernel test entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hlu.h"
+#include "plan.hpp"
+
+extern "C" hipError_t hlu_launch_ops(int type, const void* ops, int count, hipStream_t s);
+extern "C" hipError_t hlu_launch_mv(const void* lr, int nlr, const void* rows, int nrows,
+                                    const void* terms, const double* X, int ldx, const double* B,
+                                    double beta, double alpha, double* Y, int nrhs,
+                                    hipStream_t s);
+extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, double* y, int ldy,
+                                     const int64_t* perm, int n, int nrhs, hipStream_t s);
+extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
+                                        int n, int nrhs, double* out, hipStream_t s);
+extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s);
+
+namespace {
+
+thread_local std::string g_err;
+
+hlu_status fail(hlu_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(HLU_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void relocate(hlu::PRef& r, uint64_t base) {
+  if (r.ptr && r.kind != hlu::PK_IDENT) r.ptr += base;
+  if (r.rankp) r.rankp += base;
+}
+
+void relocate(hlu::Op& op, uint64_t base) {
+  for (auto& r : op.p) relocate(r, base);
+  if (op.cost) op.cost += base;
+}
+
+// Host-side check of a schedule before anything is launched: every panel a
+// kernel may touch (at full capacity) lies inside the buffer, dynamic column
+// counts point at an int inside the buffer, and operand shapes agree with
+// what each kernel assumes.  Offsets are relative to the buffer start.
+bool panel_ok(const hlu::PRef& r, uint64_t total, std::string& why) {
+  if (r.kind == hlu::PK_IDENT) return r.rows >= 0 && r.cols >= 0;
+  if (r.rows < 0 || r.cols < 0 || r.ld < 1) { why = "bad panel dims"; return false; }
+  if (r.rows == 0 || r.cols == 0) return true;
+  uint64_t es = r.dt == hlu::DT_F64 ? 8 : 4;
+  uint64_t last = r.trans ? (uint64_t)(r.cols - 1) + (uint64_t)(r.rows - 1) * r.ld
+                          : (uint64_t)(r.rows - 1) + (uint64_t)(r.cols - 1) * r.ld;
+  if (!r.trans && r.ld < r.rows) { why = "ld < rows"; return false; }
+  if (r.trans && r.ld < r.cols) { why = "ld < cols (transposed)"; return false; }
+  if (r.ptr < 512 || r.ptr + (last + 1) * es > total) { why = "panel outside buffer"; return false; }
+  if (r.rankp && (r.rankp < 256 || r.rankp + 4 > total)) { why = "rank pointer outside buffer"; return false; }
+  return true;
+}
+
+bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
+  const uint64_t T = p.total;
+  for (size_t i = 0; i < sc.ops.size(); ++i) {
+    const hlu::Op& o = sc.ops[i];
+    auto bad = [&](const char* w) {
+      why = "op " + std::to_string(i) + " (type " + std::to_string(o.type) + "): " + w;
+      return false;
+    };
+    if (o.cost && o.cost + 32 > T) return bad("cost record outside buffer");
+    switch (o.type) {
+      case hlu::OP_GETRF:
+        if (!panel_ok(o.p[0], T, why)) return bad(why.c_str());
+        if (o.p[0].rows != o.p[0].cols || o.p[0].rows < 1 || o.p[0].rows > 64) return bad("leaf size");
+        if (o.p[1].ptr < 512 || o.p[1].ptr + 4 * o.p[0].rows > T) return bad("pivots");
+        break;
+      case hlu::OP_TRSM_L:
+      case hlu::OP_TRSM_UT:
+      case hlu::OP_TRSM_U:
+        if (!panel_ok(o.p[0], T, why) || !panel_ok(o.p[1], T, why)) return bad(why.c_str());
+        if (o.p[0].rows != o.p[0].cols || o.p[0].rows > 64 || o.p[1].rows != o.p[0].rows)
+          return bad("leaf solve shapes");
+        if (o.type == hlu::OP_TRSM_L && (o.p[2].ptr < 512 || o.p[2].ptr + 4 * o.p[0].rows > T))
+          return bad("pivots");
+        break;
+      case hlu::OP_PGEMM: {
+        const hlu::PRef &X = o.p[2], &Y = o.p[3];
+        if (!panel_ok(X, T, why) || !panel_ok(Y, T, why)) return bad(why.c_str());
+        bool tr = o.i1 != 0;
+        if (o.i0 == 0) {
+          const hlu::PRef& M = o.p[0];
+          if (!panel_ok(M, T, why)) return bad(why.c_str());
+          int mr = tr ? M.cols : M.rows, mc = tr ? M.rows : M.cols;
+          if (mr != Y.rows || mc != X.rows) return bad("dense product shapes");
+        } else {
+          const hlu::PRef &U = o.p[0], &V = o.p[1];
+          if (!panel_ok(U, T, why) || !panel_ok(V, T, why)) return bad(why.c_str());
+          const hlu::PRef& A = tr ? V : U;
+          const hlu::PRef& B = tr ? U : V;
+          if (A.rows != Y.rows || B.rows != X.rows) return bad("low-rank product shapes");
+          if (U.cols > 64 || !U.rankp) return bad("low-rank operand rank");
+        }
+        if (X.cols != Y.cols && !(X.rankp && X.rankp == Y.rankp)) {
+          // static / dynamic mix: the kernel uses the smaller live count
+          if (!X.rankp && !Y.rankp) return bad("panel column counts differ");
+        }
+        break;
+      }
+      case hlu::OP_TRUNC: {
+        const hlu::PRef &U = o.p[0], &V = o.p[1], &X = o.p[2], &Y = o.p[3];
+        for (int q = 0; q < 4; ++q)
+          if (!panel_ok(o.p[q], T, why)) return bad(why.c_str());
+        int cap = o.i2 & 0xffff;
+        if (!U.rankp || U.rankp != V.rankp || U.cols != cap || V.cols != cap || cap > 32)
+          return bad("truncation target");
+        if (o.i0 < 0 || o.i1 < 0 || o.i0 + X.rows > U.rows || o.i1 + Y.rows > V.rows)
+          return bad("truncation term placement");
+        if (X.cols != Y.cols) return bad("truncation term widths");
+        if (cap + X.cols > 64) return bad("stack wider than 64");
+        break;
+      }
+      case hlu::OP_ADDD: {
+        const hlu::PRef &Cm = o.p[0], &X = o.p[1], &Y = o.p[2];
+        for (int q = 0; q < 3; ++q)
+          if (!panel_ok(o.p[q], T, why)) return bad(why.c_str());
+        if (X.rows != Cm.rows || Y.rows != Cm.cols || X.cols != Y.cols) return bad("dense update shapes");
+        if (Cm.dt != hlu::DT_F64 || Cm.trans || Cm.rankp) return bad("dense update target");
+        break;
+      }
+      case hlu::OP_ZERO:
+        if (!panel_ok(o.p[0], T, why) || o.p[0].rankp) return bad(why.c_str());
+        break;
+      default:
+        return bad("unknown op type");
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+struct hlu_handle_s {
+  hlu::Plan plan;
+  char* base = nullptr;
+  size_t bytes = 0;
+  bool assembled = false;
+  bool factored = false;
+  double anorm = 0.0;
+  int iters = 0;
+  double eta_hist[16] = {0};
+  double eta_final = 0.0;
+  bool not_converged = false;
+  hlu_params params;
+};
+
+extern "C" {
+
+const char* hlu_last_error(void) { return g_err.c_str(); }
+
+hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_params* p,
+                    hlu_handle* out) {
+  g_err.clear();
+  if (!xyz || !area || !p || !out) return fail(HLU_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (n < 1 || n > (1LL << 30)) return fail(HLU_ERR_ARG, "n out of range");
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) return fail(HLU_ERR_ARG, "non-finite coordinate");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(area[i]) || area[i] < 0) return fail(HLU_ERR_ARG, "bad area");
+  if (p->leaf_size < 1 || p->leaf_size > 64) return fail(HLU_ERR_ARG, "leaf_size must be in [1, 64]");
+  if (!(p->eta >= 0) || !std::isfinite(p->eta)) return fail(HLU_ERR_ARG, "eta must be >= 0");
+  if (p->rank_cap_factor < 1 || p->rank_cap_factor > 32)
+    return fail(HLU_ERR_ARG, "rank_cap_factor must be in [1, 32]");
+  if (p->rank_cap_matvec < 1 || p->rank_cap_matvec > 64)
+    return fail(HLU_ERR_ARG, "rank_cap_matvec must be in [1, 64]");
+  if (p->fixed_rank < 0 || p->fixed_rank > p->rank_cap_factor)
+    return fail(HLU_ERR_ARG, "fixed_rank must be in [0, rank_cap_factor]");
+  if (p->fixed_rank == 0 && !(p->eps_factor > 0 && p->eps_factor < 1))
+    return fail(HLU_ERR_ARG, "eps_factor must be in (0, 1)");
+  if (!(p->eps_matvec > 0 && p->eps_matvec < 1)) return fail(HLU_ERR_ARG, "eps_matvec must be in (0, 1)");
+  if (p->max_nrhs < 1 || p->max_nrhs > 64) return fail(HLU_ERR_ARG, "max_nrhs must be in [1, 64]");
+  if (p->kernel != HLU_KERNEL_LAPLACE3D_WEIGHTED && p->kernel != HLU_KERNEL_LAPLACE3D_POINT)
+    return fail(HLU_ERR_ARG, "unknown kernel");
+  if (p->precision != HLU_PREC_FP64 && p->precision != HLU_PREC_MIXED)
+    return fail(HLU_ERR_ARG, "unknown precision");
+  if (p->refine_max_iter < 0 || p->refine_max_iter > 15)
+    return fail(HLU_ERR_ARG, "refine_max_iter must be in [0, 15]");
+  hlu_handle h = new (std::nothrow) hlu_handle_s;
+  if (!h) return fail(HLU_ERR_NOMEM, "host allocation failed");
+  h->params = *p;
+  hlu::Params prm;
+  prm.kernel = p->kernel;
+  prm.eta = p->eta;
+  prm.leaf = p->leaf_size;
+  prm.fixed_rank = p->fixed_rank;
+  prm.eps_f = p->fixed_rank > 0 ? 0.0 : p->eps_factor;
+  prm.cap_f = p->rank_cap_factor;
+  prm.eps_mv = p->eps_matvec;
+  prm.cap_mv = p->rank_cap_matvec;
+  prm.mixed = p->precision == HLU_PREC_MIXED;
+  prm.refine_tol = p->refine_tol;
+  prm.refine_max_iter = p->refine_max_iter;
+  prm.max_nrhs = p->max_nrhs;
+  try {
+    if (!hlu::build_plan(h->plan, xyz, area, n, prm)) {
+      std::string e = h->plan.err;
+      delete h;
+      return fail(HLU_ERR_ARG, "planning failed: " + e);
+    }
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return fail(HLU_ERR_NOMEM, "host allocation failed while planning");
+  }
+  *out = h;
+  return HLU_OK;
+}
+
+size_t hlu_required_bytes(hlu_handle h) { return h ? (size_t)h->plan.total : 0; }
+
+hlu_status hlu_validate(hlu_handle h) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  std::string why;
+  if (!validate(h->plan, h->plan.fsched, why)) return fail(HLU_ERR_ARG, "factor schedule: " + why);
+  if (!validate(h->plan, h->plan.ssched, why)) return fail(HLU_ERR_ARG, "solve schedule: " + why);
+  // matvec tables
+  const hlu::Plan& p = h->plan;
+  for (const auto& e : p.mv_lr) {
+    if (e.k > 0 && (e.U < 512 || e.U + (uint64_t)e.m * e.k * 8 > p.total ||
+                    e.V + (uint64_t)e.n * e.k * 8 > p.total ||
+                    e.T + (uint64_t)e.kcap * p.prm.max_nrhs * 8 > p.total ||
+                    e.c0 + e.n > p.n || e.r0 + e.m > p.n))
+      return fail(HLU_ERR_ARG, "matvec low-rank table");
+  }
+  for (const auto& r : p.mv_rows) {
+    if (r.r0 < 0 || r.r0 + r.rows > p.n || r.t0 + r.nt > (int64_t)p.mv_terms.size())
+      return fail(HLU_ERR_ARG, "matvec row table");
+    for (int q = 0; q < r.nt; ++q) {
+      const auto& t = p.mv_terms[r.t0 + q];
+      if (t.roff < 0 || t.roff + r.rows > t.lda) return fail(HLU_ERR_ARG, "matvec term rows");
+      if (t.A + ((uint64_t)t.lda * t.ncol) * 8 > p.total) return fail(HLU_ERR_ARG, "matvec term extent");
+      if (t.T == 0 && t.c0 + t.ncol > p.n) return fail(HLU_ERR_ARG, "matvec term columns");
+    }
+  }
+  return HLU_OK;
+}
+
+hlu_status hlu_get_stats(hlu_handle h, hlu_plan_stats* o) {
+  if (!h || !o) return fail(HLU_ERR_ARG, "NULL argument");
+  const hlu::Plan& p = h->plan;
+  std::memset(o, 0, sizeof(*o));
+  o->n = p.n;
+  o->leaves = (int64_t)p.leaves.size();
+  for (auto& b : p.blk) (b.kind == 'F' ? o->dense_blocks : o->lowrank_blocks)++;
+  o->ops_factor = (int64_t)p.fsched.ops.size();
+  o->waves_factor = p.fsched.waves;
+  o->ops_solve = (int64_t)p.ssched.ops.size();
+  o->waves_solve = p.ssched.waves;
+  o->bytes_factor_region = (int64_t)p.size_work;
+  o->bytes_matvec_region = (int64_t)p.size_mv;
+  o->bytes_scratch = (int64_t)p.size_scratch;
+  o->bytes_total = (int64_t)p.total;
+  return HLU_OK;
+}
+
+hlu_status hlu_get_perm(hlu_handle h, int64_t* perm) {
+  if (!h || !perm) return fail(HLU_ERR_ARG, "NULL argument");
+  std::memcpy(perm, h->plan.perm.data(), sizeof(int64_t) * h->plan.n);
+  return HLU_OK;
+}
+
+hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
+  if (!h || !dev_ptr) return fail(HLU_ERR_ARG, "NULL argument");
+  if (((uintptr_t)dev_ptr) & 255) return fail(HLU_ERR_ARG, "buffer must be 256-byte aligned");
+  if (bytes < h->plan.total) return fail(HLU_ERR_NOMEM, "bound buffer smaller than required bytes");
+  hlu::Plan& p = h->plan;
+  {
+    hlu_status vs = hlu_validate(h);
+    if (vs != HLU_OK) return vs;
+  }
+  uint64_t base = (uint64_t)dev_ptr;
+  // relocated copies of the schedules and the matvec tables
+  std::vector<hlu::Op> f = p.fsched.ops, s = p.ssched.ops;
+  for (auto& op : f) relocate(op, base);
+  for (auto& op : s) relocate(op, base);
+  std::vector<hlu::MvLR> lr = p.mv_lr;
+  for (auto& e : lr) {
+    if (e.U) e.U += base;
+    if (e.V) e.V += base;
+    if (e.T) e.T += base;
+  }
+  std::vector<hlu::MvTerm> tm = p.mv_terms;
+  for (auto& t : tm) {
+    if (t.A) t.A += base;
+    if (t.T) t.T += base;
+  }
+  char* b = (char*)dev_ptr;
+  if (!f.empty()) HIPCHK(hipMemcpy(b + p.off_ops_f, f.data(), f.size() * sizeof(hlu::Op), hipMemcpyHostToDevice));
+  if (!s.empty()) HIPCHK(hipMemcpy(b + p.off_ops_s, s.data(), s.size() * sizeof(hlu::Op), hipMemcpyHostToDevice));
+  if (!lr.empty()) HIPCHK(hipMemcpy(b + p.off_mv_lr, lr.data(), lr.size() * sizeof(hlu::MvLR), hipMemcpyHostToDevice));
+  if (!tm.empty()) HIPCHK(hipMemcpy(b + p.off_mv_terms, tm.data(), tm.size() * sizeof(hlu::MvTerm), hipMemcpyHostToDevice));
+  if (!p.mv_rows.empty())
+    HIPCHK(hipMemcpy(b + p.off_mv_rows, p.mv_rows.data(), p.mv_rows.size() * sizeof(hlu::MvRow), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b + p.off_perm, p.perm.data(), sizeof(int64_t) * p.n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(b + p.off_status, 0, 256));
+  h->base = b;
+  h->bytes = bytes;
+  h->assembled = false;
+  h->factored = false;
+  return HLU_OK;
+}
+
+static hlu_status run_mv(hlu_handle h, const double* X, const double* B, double beta, double alpha,
+                         double* Y, int nrhs, hipStream_t s) {
+  hlu::Plan& p = h->plan;
+  HIPCHK(hlu_launch_mv(h->base + p.off_mv_lr, (int)p.mv_lr.size(), h->base + p.off_mv_rows,
+                       (int)p.mv_rows.size(), h->base + p.off_mv_terms, X, p.n, B, beta, alpha,
+                       Y, nrhs, s));
+  return HLU_OK;
+}
+
+hlu_status hlu_assemble(hlu_handle h, void* stream) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  hipStream_t s = (hipStream_t)stream;
+  hlu::Plan& p = h->plan;
+  char* b = h->base;
+  HIPCHK(hipMemcpyAsync(b + p.off_work, p.img_work.data(), p.size_work, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(b + p.off_pristine, p.img_work.data(), p.size_work, hipMemcpyHostToDevice, s));
+  if (p.size_mv)
+    HIPCHK(hipMemcpyAsync(b + p.off_mv, p.img_mv.data(), p.size_mv, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(b + p.off_status, 0, 256, s));
+  // |A|_inf: all entries of both kernels are positive, so it is the
+  // largest entry of A * ones (with the accurate matvec copy)
+  std::vector<double> ones(p.n, 1.0);
+  double* X = (double*)(b + p.off_X);
+  double* Y = (double*)(b + p.off_Y);
+  HIPCHK(hipMemcpyAsync(X, ones.data(), sizeof(double) * p.n, hipMemcpyHostToDevice, s));
+  hlu_status st = run_mv(h, X, nullptr, 0.0, 1.0, Y, 1, s);
+  if (st != HLU_OK) return st;
+  double* out = (double*)(b + p.off_eta);
+  HIPCHK(hlu_launch_colmax(Y, X, X, p.n, p.n, 1, out, s));
+  double mx[3];
+  HIPCHK(hipMemcpyAsync(mx, out, sizeof(mx), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h->anorm = mx[0];
+  h->assembled = true;
+  h->factored = false;
+  return HLU_OK;
+}
+
+hlu_status hlu_reset(hlu_handle h, void* stream) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
+  hipStream_t s = (hipStream_t)stream;
+  hlu::Plan& p = h->plan;
+  HIPCHK(hipMemcpyAsync(h->base + p.off_work, h->base + p.off_pristine, p.size_work,
+                        hipMemcpyDeviceToDevice, s));
+  HIPCHK(hlu_launch_set_int((int32_t*)(h->base + p.off_status), 0, s));
+  h->factored = false;
+  return HLU_OK;
+}
+
+static hlu_status run_schedule(hlu_handle h, const hlu::Schedule& sc, uint64_t off_ops,
+                               hipStream_t s) {
+  const char* ops = h->base + off_ops;
+  for (const hlu::Batch& bt : sc.batches) {
+    hipError_t e = hlu_launch_ops(bt.type, ops + (size_t)bt.start * sizeof(hlu::Op), bt.count, s);
+    if (e != hipSuccess) return fail(HLU_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  }
+  return HLU_OK;
+}
+
+hlu_status hlu_factor(hlu_handle h, void* stream) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
+  if (h->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
+  hlu_status st = run_schedule(h, h->plan.fsched, h->plan.off_ops_f, s);
+  if (st != HLU_OK) return st;
+  h->factored = true;
+  return HLU_OK;
+}
+
+hlu_status hlu_factor_profile(hlu_handle h, void* stream, double* ms_per_type,
+                              int64_t* launches_per_type) {
+  if (!h || !ms_per_type || !launches_per_type) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
+  if (h->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
+  hipStream_t s = (hipStream_t)stream;
+  const hlu::Schedule& sc = h->plan.fsched;
+  const char* ops = h->base + h->plan.off_ops_f;
+  std::vector<hipEvent_t> ev(2 * sc.batches.size());
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
+  hipError_t err = hipSuccess;
+  for (size_t i = 0; i < sc.batches.size() && err == hipSuccess; ++i) {
+    const hlu::Batch& bt = sc.batches[i];
+    err = hipEventRecord(ev[2 * i], s);
+    if (err == hipSuccess)
+      err = hlu_launch_ops(bt.type, ops + (size_t)bt.start * sizeof(hlu::Op), bt.count, s);
+    if (err == hipSuccess) err = hipEventRecord(ev[2 * i + 1], s);
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  for (int t = 0; t < 8; ++t) { ms_per_type[t] = 0.0; launches_per_type[t] = 0; }
+  for (size_t i = 0; i < sc.batches.size() && err == hipSuccess; ++i) {
+    float ms = 0.f;
+    err = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+    ms_per_type[sc.batches[i].type] += ms;
+    launches_per_type[sc.batches[i].type]++;
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  if (err != hipSuccess) return fail(HLU_ERR_DEVICE, hipGetErrorString(err));
+  h->factored = true;
+  return HLU_OK;
+}
+
+hlu_status hlu_factor_batched(hlu_handle* hs, int count, void* stream) {
+  if (!hs || count < 1) return fail(HLU_ERR_ARG, "bad handle list");
+  // schedules of different handles live in different buffers, so the merged
+  // execution interleaves their batches wave by wave on the stream
+  int maxw = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i]) return fail(HLU_ERR_ARG, "NULL handle");
+    if (!hs[i]->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
+    if (hs[i]->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
+    maxw = std::max(maxw, hs[i]->plan.fsched.waves);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<size_t> cur(count, 0);
+  for (int i = 0; i < count; ++i)
+    HIPCHK(hlu_launch_set_int((int32_t*)(hs[i]->base + hs[i]->plan.off_status), 0, s));
+  for (int w = 0; w < maxw; ++w)
+    for (int i = 0; i < count; ++i) {
+      const hlu::Schedule& sc = hs[i]->plan.fsched;
+      const char* ops = hs[i]->base + hs[i]->plan.off_ops_f;
+      while (cur[i] < sc.batches.size() && sc.batches[cur[i]].wave == w) {
+        const hlu::Batch& bt = sc.batches[cur[i]++];
+        HIPCHK(hlu_launch_ops(bt.type, ops + (size_t)bt.start * sizeof(hlu::Op), bt.count, s));
+      }
+    }
+  for (int i = 0; i < count; ++i) hs[i]->factored = true;
+  return HLU_OK;
+}
+
+hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs, int64_t ld,
+                     void* stream) {
+  if (!h || !b_dev || !x_dev) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->factored) return fail(HLU_ERR_STATE, "hlu_factor first");
+  hlu::Plan& p = h->plan;
+  if (nrhs < 1 || nrhs > p.prm.max_nrhs) return fail(HLU_ERR_ARG, "nrhs out of range");
+  if (ld < p.n) return fail(HLU_ERR_ARG, "ld < n");
+  hipStream_t s = (hipStream_t)stream;
+  char* b = h->base;
+  const int n = p.n;
+  double* Y = (double*)(b + p.off_Y);
+  double* X = (double*)(b + p.off_X);
+  double* B = (double*)(b + p.off_B);
+  const int64_t* perm = (const int64_t*)(b + p.off_perm);
+  HIPCHK(hlu_launch_set_int((int32_t*)(b + p.off_nrhs), nrhs, s));
+  HIPCHK(hlu_launch_vec(0, b_dev, ld, B, n, perm, n, nrhs, s));        // B = P b
+  HIPCHK(hlu_launch_vec(3, B, n, Y, n, nullptr, n, nrhs, s));          // Y = B
+  hlu_status st = run_schedule(h, p.ssched, p.off_ops_s, s);
+  if (st != HLU_OK) return st;
+  HIPCHK(hlu_launch_vec(3, Y, n, X, n, nullptr, n, nrhs, s));          // X = Y
+  h->iters = 0;
+  h->not_converged = false;
+  h->eta_final = 0.0;
+  const double tol = p.prm.refine_tol;
+  if (tol > 0.0) {
+    double* out = (double*)(b + p.off_eta);
+    std::vector<double> mx(3 * nrhs);
+    double best = INFINITY;
+    for (int it = 0;; ++it) {
+      st = run_mv(h, X, B, 1.0, -1.0, Y, nrhs, s);                       // Y = B - A X
+      if (st != HLU_OK) return st;
+      HIPCHK(hlu_launch_colmax(Y, X, B, n, n, nrhs, out, s));
+      HIPCHK(hipMemcpyAsync(mx.data(), out, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double eta = 0.0;
+      for (int j = 0; j < nrhs; ++j) {
+        double den = h->anorm * mx[3 * j + 1] + mx[3 * j + 2];
+        double e = den > 0 ? mx[3 * j] / den : (mx[3 * j] > 0 ? INFINITY : 0.0);
+        if (!(e <= INFINITY)) e = INFINITY;  // NaN
+        eta = std::max(eta, e);
+      }
+      if (it < 16) h->eta_hist[it] = eta;
+      h->eta_final = eta;
+      best = std::min(best, eta);
+      if (eta <= tol) break;
+      if (it >= p.prm.refine_max_iter) { h->not_converged = true; break; }
+      st = run_schedule(h, p.ssched, p.off_ops_s, s);                    // Y = A_H^{-1} Y
+      if (st != HLU_OK) return st;
+      HIPCHK(hlu_launch_vec(2, Y, n, X, n, nullptr, n, nrhs, s));        // X += Y
+      h->iters = it + 1;
+    }
+  }
+  HIPCHK(hlu_launch_vec(1, X, ld, x_dev, n, perm, n, nrhs, s));        // x = P^T X
+  return HLU_OK;
+}
+
+hlu_status hlu_matvec(hlu_handle h, const double* x_dev, double* y_dev, int nrhs, int64_t ld,
+                      void* stream) {
+  if (!h || !x_dev || !y_dev) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
+  hlu::Plan& p = h->plan;
+  if (nrhs < 1 || nrhs > p.prm.max_nrhs) return fail(HLU_ERR_ARG, "nrhs out of range");
+  if (ld < p.n) return fail(HLU_ERR_ARG, "ld < n");
+  hipStream_t s = (hipStream_t)stream;
+  char* b = h->base;
+  const int n = p.n;
+  double* X = (double*)(b + p.off_B);
+  double* Y = (double*)(b + p.off_Y);
+  const int64_t* perm = (const int64_t*)(b + p.off_perm);
+  HIPCHK(hlu_launch_vec(0, x_dev, ld, X, n, perm, n, nrhs, s));
+  hlu_status st = run_mv(h, X, nullptr, 0.0, 1.0, Y, nrhs, s);
+  if (st != HLU_OK) return st;
+  HIPCHK(hlu_launch_vec(1, Y, ld, y_dev, n, perm, n, nrhs, s));
+  return HLU_OK;
+}
+
+hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipStreamSynchronize(s));
+  hlu_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  if (h->base) {
+    int32_t st = 0;
+    HIPCHK(hipMemcpy(&st, h->base + h->plan.off_status, 4, hipMemcpyDeviceToHost));
+    if (st > 0) inf.info = h->plan.perm[st - 1] + 1;
+  }
+  inf.iters = h->iters;
+  for (int i = 0; i < 16; ++i) inf.eta_hist[i] = h->eta_hist[i];
+  inf.eta_final = h->eta_final;
+  if (h->factored && h->base && !h->plan.fsched.ops.empty()) {
+    size_t no = h->plan.fsched.ops.size();
+    std::vector<double> c(no * 4);
+    HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * 32, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < no; ++i) inf.cap_hits += (int64_t)c[4 * i + 2];
+    // ranks of the low-rank blocks live at the start of the work region
+    size_t nr = 0;
+    for (const auto& b : h->plan.blk) nr += b.kind == 'R';
+    std::vector<int32_t> rk(nr);
+    if (nr) HIPCHK(hipMemcpy(rk.data(), h->base + h->plan.off_work, nr * 4, hipMemcpyDeviceToHost));
+    int64_t mr = 0;
+    for (int32_t r : rk) mr = std::max<int64_t>(mr, r);
+    inf.max_rank = mr;
+  }
+  if (out) *out = inf;
+  if (inf.info) return fail(HLU_ERR_SINGULAR, "zero pivot");
+  if (h->not_converged) return fail(HLU_ERR_NOT_CONVERGED, "refinement did not converge");
+  return HLU_OK;
+}
+
+// Sum of the per-op records of the last factorisation: flops, algorithmic
+// bytes and capacity hits, per op type (arrays of length 8).
+hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* counts) {
+  if (!h || !flops || !bytes || !counts) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  size_t no = h->plan.fsched.ops.size();
+  std::vector<double> c(no * 4);
+  if (no) HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * 32, hipMemcpyDeviceToHost));
+  for (int t = 0; t < 8; ++t) { flops[t] = 0; bytes[t] = 0; counts[t] = 0; }
+  for (size_t i = 0; i < no; ++i) {
+    int t = h->plan.fsched.ops[i].type;
+    flops[t] += c[4 * i];
+    bytes[t] += c[4 * i + 1];
+    counts[t]++;
+  }
+  return HLU_OK;
+}
+
+// Number of launches per op type in the factor schedule (array of 8).
+hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches) {
+  if (!h || !launches) return fail(HLU_ERR_ARG, "NULL argument");
+  for (int t = 0; t < 8; ++t) launches[t] = 0;
+  for (const auto& b : h->plan.fsched.batches) launches[b.type]++;
+  return HLU_OK;
+}
+
+hlu_status hlu_export_pivots(hlu_handle h, int32_t* piv, void* stream) {
+  if (!h || !piv) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  HIPCHK(hipMemcpy(piv, h->base + h->plan.off_piv, sizeof(int32_t) * h->plan.n, hipMemcpyDeviceToHost));
+  return HLU_OK;
+}
+
+hlu_status hlu_export_factors(hlu_handle h, double* lhat, double* u, void* stream) {
+  if (!h || !lhat || !u) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  const hlu::Plan& p = h->plan;
+  const int n = p.n;
+  if (n > 8192) return fail(HLU_ERR_ARG, "n too large for a dense export");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<char> w(p.size_work);
+  HIPCHK(hipMemcpy(w.data(), h->base + p.off_work, p.size_work, hipMemcpyDeviceToHost));
+  std::vector<int32_t> piv(n);
+  HIPCHK(hipMemcpy(piv.data(), h->base + p.off_piv, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  std::memset(lhat, 0, sizeof(double) * (size_t)n * n);
+  std::memset(u, 0, sizeof(double) * (size_t)n * n);
+  const bool mixed = p.prm.mixed;
+  for (const auto& b : p.blk) {
+    const hlu::Cluster &ct = p.cl[b.t], &cs = p.cl[b.s];
+    std::vector<double> M((size_t)b.m * b.n, 0.0);
+    if (b.kind == 'F') {
+      const double* F = (const double*)(w.data() + (b.offF - p.off_work));
+      std::memcpy(M.data(), F, sizeof(double) * M.size());
+    } else {
+      int k = *(const int32_t*)(w.data() + (b.offRank - p.off_work));
+      for (int j = 0; j < b.n; ++j)
+        for (int i = 0; i < b.m; ++i) {
+          double s = 0;
+          for (int l = 0; l < k; ++l) {
+            double uu, vv;
+            if (mixed) {
+              uu = ((const float*)(w.data() + (b.offU - p.off_work)))[i + (size_t)l * b.m];
+              vv = ((const float*)(w.data() + (b.offV - p.off_work)))[j + (size_t)l * b.n];
+            } else {
+              uu = ((const double*)(w.data() + (b.offU - p.off_work)))[i + (size_t)l * b.m];
+              vv = ((const double*)(w.data() + (b.offV - p.off_work)))[j + (size_t)l * b.n];
+            }
+            s += uu * vv;
+          }
+          M[i + (size_t)j * b.m] = s;
+        }
+    }
+    if (b.t == b.s) {
+      // Lhat leaf = P^T L: undo the leaf's row swaps on the unit lower part
+      std::vector<double> L((size_t)b.m * b.m, 0.0);
+      for (int j = 0; j < b.m; ++j)
+        for (int i = 0; i < b.m; ++i) {
+          L[i + (size_t)j * b.m] = i > j ? M[i + (size_t)j * b.m] : (i == j ? 1.0 : 0.0);
+          u[(ct.off + i) + (size_t)(cs.off + j) * n] = i <= j ? M[i + (size_t)j * b.m] : 0.0;
+        }
+      // rows of P L: P applies swaps k <-> piv[k] in order; P^T L undoes
+      // them in reverse order
+      for (int k = b.m - 1; k >= 0; --k) {
+        int q = piv[ct.off + k];
+        if (q != k)
+          for (int j = 0; j < b.m; ++j) std::swap(L[k + (size_t)j * b.m], L[q + (size_t)j * b.m]);
+      }
+      for (int j = 0; j < b.m; ++j)
+        for (int i = 0; i < b.m; ++i) lhat[(ct.off + i) + (size_t)(cs.off + j) * n] = L[i + (size_t)j * b.m];
+    } else {
+      double* dst = ct.off > cs.off ? lhat : u;
+      for (int j = 0; j < b.n; ++j)
+        for (int i = 0; i < b.m; ++i) dst[(ct.off + i) + (size_t)(cs.off + j) * n] = M[i + (size_t)j * b.m];
+    }
+  }
+  return HLU_OK;
+}
+
+void hlu_destroy(hlu_handle h) { delete h; }
+
+// ---------------------------------------------------------------- test entry points
+static hlu_status run_single(const std::vector<hlu::Op>& ops, int type, hipStream_t s) {
+  void* d = nullptr;
+  HIPCHK(hipMalloc(&d, ops.size() * sizeof(hlu::Op)));
+  hipError_t e = hipMemcpyAsync(d, ops.data(), ops.size() * sizeof(hlu::Op), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hlu_launch_ops(type, d, (int)ops.size(), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(d);
+  if (e != hipSuccess) return fail(HLU_ERR_DEVICE, hipGetErrorString(e));
+  return HLU_OK;
+}
+
+hlu_status hlu_getrf_batched(double* a_dev, int32_t* piv_dev, int32_t* info_dev, int b, int count,
+                             void* stream) {
+  if (!a_dev || !piv_dev || !info_dev) return fail(HLU_ERR_ARG, "NULL argument");
+  if (b < 1 || b > 64 || count < 0) return fail(HLU_ERR_ARG, "b must be in [1, 64]");
+  if (count == 0) return HLU_OK;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(info_dev, 0, sizeof(int32_t) * count, s));
+  std::vector<hlu::Op> ops(count);
+  for (int i = 0; i < count; ++i) {
+    hlu::Op& o = ops[i];
+    std::memset(&o, 0, sizeof(o));
+    o.type = hlu::OP_GETRF;
+    o.p[0].ptr = (uint64_t)(a_dev + (size_t)i * b * b);
+    o.p[0].ld = b;
+    o.p[0].rows = b;
+    o.p[0].cols = b;
+    o.p[1].ptr = (uint64_t)(piv_dev + (size_t)i * b);
+    o.p[1].rankp = (uint64_t)(info_dev + i);
+    o.i0 = 0;
+  }
+  return run_single(ops, hlu::OP_GETRF, s);
+}
+
+hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev, const double* X_dev,
+                            const double* Y_dev, int m, int n, int kc, int kx, int cap, double eps,
+                            int fixed_rank, void* stream) {
+  if (!U_dev || !V_dev || !rank_dev || (kx > 0 && (!X_dev || !Y_dev)))
+    return fail(HLU_ERR_ARG, "NULL argument");
+  if (m < 1 || n < 1 || kc < 0 || kx < 0 || kc > cap || kc + kx > 64 || cap < 1 || cap > 32 ||
+      fixed_rank < 0 || fixed_rank > cap)
+    return fail(HLU_ERR_ARG, "sizes out of range");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hlu_launch_set_int(rank_dev, kc, s));
+  std::vector<hlu::Op> ops(1);
+  hlu::Op& o = ops[0];
+  std::memset(&o, 0, sizeof(o));
+  o.type = hlu::OP_TRUNC;
+  o.p[0].ptr = (uint64_t)U_dev;
+  o.p[0].rankp = (uint64_t)rank_dev;
+  o.p[0].ld = m;
+  o.p[0].rows = m;
+  o.p[0].cols = cap;
+  o.p[1].ptr = (uint64_t)V_dev;
+  o.p[1].rankp = (uint64_t)rank_dev;
+  o.p[1].ld = n;
+  o.p[1].rows = n;
+  o.p[1].cols = cap;
+  o.p[2].ptr = (uint64_t)X_dev;
+  o.p[2].ld = m;
+  o.p[2].rows = m;
+  o.p[2].cols = kx;
+  o.p[3].ptr = (uint64_t)Y_dev;
+  o.p[3].ld = n;
+  o.p[3].rows = n;
+  o.p[3].cols = kx;
+  o.i2 = cap | (fixed_rank << 16);
+  o.d0 = eps;
+  return run_single(ops, hlu::OP_TRUNC, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,988 @@
+// HIP kernels of the H-LU library (gfx950).
+//
+// Every kernel of the factorisation schedule processes one descriptor per
+// workgroup (256 threads = four 64-wide wavefronts); a launch covers one
+// batch (all descriptors of one type in one wave of the schedule).  Small
+// tiles are staged through LDS; low-rank panels are streamed in row chunks.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ops.h"
+
+namespace hlu {
+
+#define NT 256
+
+__device__ __forceinline__ int pcols(const PRef& r) {
+  return r.rankp ? *reinterpret_cast<const int32_t*>(r.rankp) : r.cols;
+}
+
+__device__ __forceinline__ double pget(const PRef& r, int i, int j) {
+  if (r.kind == PK_IDENT) return (j == i + r.ld) ? 1.0 : 0.0;
+  size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
+  return r.dt == DT_F64 ? reinterpret_cast<const double*>(r.ptr)[k]
+                        : (double)reinterpret_cast<const float*>(r.ptr)[k];
+}
+
+__device__ __forceinline__ void pset(const PRef& r, int i, int j, double v) {
+  size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
+  if (r.dt == DT_F64) reinterpret_cast<double*>(r.ptr)[k] = v;
+  else reinterpret_cast<float*>(r.ptr)[k] = (float)v;
+}
+
+// per-op record {model flops, algorithmic bytes, rank-capacity hit, rank}
+__device__ __forceinline__ void put_cost(const Op& op, double flops, double bytes,
+                                         double cap_hit = 0.0, double rank = 0.0) {
+  if (op.cost && threadIdx.x == 0) {
+    double* c = reinterpret_cast<double*>(op.cost);
+    c[0] = flops;
+    c[1] = bytes;
+    c[2] = cap_hit;
+    c[3] = rank;
+  }
+}
+
+// ---------------------------------------------------------------- getrf
+// Right-looking unblocked LU with partial pivoting of one b x b leaf
+// (b <= 64) held in LDS; pivot = first row of the largest |a_ik|.
+// Contraction is disabled so that the elimination rounds exactly like the
+// textbook update a - l*u.
+__global__ void __launch_bounds__(NT) k_getrf(const Op* __restrict__ ops) {
+#pragma clang fp contract(off)
+  const Op& op = ops[blockIdx.x];
+  const PRef A = op.p[0];
+  const int b = A.rows;
+  __shared__ double a[64][65];
+  __shared__ int s_piv;
+  __shared__ int s_info;
+  const int tid = threadIdx.x;
+  double* g = reinterpret_cast<double*>(A.ptr);
+  for (int e = tid; e < b * b; e += NT) {
+    int i = e % b, j = e / b;
+    a[i][j] = g[i + (size_t)j * A.ld];
+  }
+  if (tid == 0) s_info = 0;
+  int32_t* piv = reinterpret_cast<int32_t*>(op.p[1].ptr);
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    if (tid < 64) {
+      double v = (tid >= k && tid < b) ? fabs(a[tid][k]) : -1.0;
+      int ix = tid;
+      for (int o = 32; o > 0; o >>= 1) {
+        double v2 = __shfl_xor(v, o);
+        int i2 = __shfl_xor(ix, o);
+        if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
+      }
+      if (tid == 0) {
+        s_piv = ix;
+        piv[k] = ix;
+        if (a[ix][k] == 0.0 && s_info == 0) s_info = k + 1;
+      }
+    }
+    __syncthreads();
+    const int p = s_piv;
+    const bool nz = a[p][k] != 0.0;
+    if (nz && p != k) {
+      for (int j = tid; j < b; j += NT) {
+        double t = a[k][j];
+        a[k][j] = a[p][j];
+        a[p][j] = t;
+      }
+    }
+    __syncthreads();
+    if (nz) {
+      const double d = a[k][k];
+      for (int i = k + 1 + tid; i < b; i += NT) a[i][k] = a[i][k] / d;
+    }
+    __syncthreads();
+    const int r = b - k - 1;
+    for (int e = tid; e < r * r; e += NT) {
+      int i = k + 1 + e % r, j = k + 1 + e / r;
+      double prod = a[i][k] * a[k][j];
+      a[i][j] = a[i][j] - prod;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < b * b; e += NT) {
+    int i = e % b, j = e / b;
+    g[i + (size_t)j * A.ld] = a[i][j];
+  }
+  if (tid == 0 && s_info != 0 && op.p[1].rankp) {
+    int32_t* st = reinterpret_cast<int32_t*>(op.p[1].rankp);
+    atomicCAS(st, 0, op.i0 + s_info);
+  }
+  put_cost(op, 2.0 * b * b * b / 3.0 - b * b / 2.0 + 5.0 * b / 6.0, 16.0 * b * b);
+}
+
+// ---------------------------------------------------------------- leaf solves
+// p1 := L^{-1} P p1 (OP_TRSM_L), U^{-T} p1 (OP_TRSM_UT) or U^{-1} p1
+// (OP_TRSM_U) with the factored b x b leaf p0 (b <= 64); the panel is
+// processed in chunks of 64 columns.
+__global__ void __launch_bounds__(NT) k_trsm(const Op* __restrict__ ops) {
+  const Op& op = ops[blockIdx.x];
+  const PRef L = op.p[0];
+  const PRef Y = op.p[1];
+  const int b = L.rows;
+  const int c = pcols(Y);
+  const int type = op.type;
+  __shared__ double l[64][65];
+  __shared__ double y[64][65];
+  __shared__ int pv[64];
+  const int tid = threadIdx.x;
+  const double* g = reinterpret_cast<const double*>(L.ptr);
+  for (int e = tid; e < b * b; e += NT) {
+    int i = e % b, j = e / b;
+    l[i][j] = g[i + (size_t)j * L.ld];
+  }
+  if (type == OP_TRSM_L) {
+    const int32_t* piv = reinterpret_cast<const int32_t*>(op.p[2].ptr);
+    for (int i = tid; i < b; i += NT) pv[i] = piv[i];
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < c; c0 += 64) {
+    const int w = min(64, c - c0);
+    for (int e = tid; e < b * w; e += NT) {
+      int i = e % b, j = e / b;
+      y[i][j] = pget(Y, i, c0 + j);
+    }
+    __syncthreads();
+    if (type == OP_TRSM_L) {
+      if (tid < w) {
+        for (int k = 0; k < b; ++k) {
+          int p = pv[k];
+          if (p != k) {
+            double t = y[k][tid];
+            y[k][tid] = y[p][tid];
+            y[p][tid] = t;
+          }
+        }
+      }
+      __syncthreads();
+      for (int k = 0; k < b - 1; ++k) {
+        const int r = b - k - 1;
+        for (int e = tid; e < r * w; e += NT) {
+          int i = k + 1 + e % r, j = e / r;
+          y[i][j] -= l[i][k] * y[k][j];
+        }
+        __syncthreads();
+      }
+    } else if (type == OP_TRSM_UT) {
+      for (int k = 0; k < b; ++k) {
+        if (tid < w) y[k][tid] = y[k][tid] / l[k][k];
+        __syncthreads();
+        const int r = b - k - 1;
+        for (int e = tid; e < r * w; e += NT) {
+          int i = k + 1 + e % r, j = e / r;
+          y[i][j] -= l[k][i] * y[k][j];
+        }
+        __syncthreads();
+      }
+    } else {
+      for (int k = b - 1; k >= 0; --k) {
+        if (tid < w) y[k][tid] = y[k][tid] / l[k][k];
+        __syncthreads();
+        for (int e = tid; e < k * w; e += NT) {
+          int i = e % k, j = e / k;
+          y[i][j] -= l[i][k] * y[k][j];
+        }
+        __syncthreads();
+      }
+    }
+    for (int e = tid; e < b * w; e += NT) {
+      int i = e % b, j = e / b;
+      pset(Y, i, c0 + j, y[i][j]);
+    }
+    __syncthreads();
+  }
+  const double es = Y.dt == DT_F64 ? 8.0 : 4.0;
+  put_cost(op, (double)b * b * c, 8.0 * b * b / 2 + 2.0 * es * b * c);
+}
+
+// ---------------------------------------------------------------- panel products
+// p3 += d0 * op(M) p2.  Dense M: tiles of 64 x 64 outputs with 32-deep LDS
+// slabs.  Low-rank M = A B^T: T = B^T X (k x c) in LDS, then Y += d0 A T.
+__global__ void __launch_bounds__(NT) k_pgemm(const Op* __restrict__ ops) {
+  const Op& op = ops[blockIdx.x];
+  const PRef X = op.p[2];
+  const PRef Y = op.p[3];
+  const double sg = op.d0;
+  const int tid = threadIdx.x;
+  const int c = pcols(Y) < pcols(X) ? pcols(Y) : pcols(X);
+  const int m = Y.rows;
+  __shared__ double sa[64][33];
+  __shared__ double sb[32][65];
+  __shared__ double st[64][65];
+  const int ti = tid % 16, tj = tid / 16;   // 16 x 16 threads, 4 x 4 outputs each
+  const double esx = X.dt == DT_F64 ? 8.0 : 4.0;
+  const double esy = Y.dt == DT_F64 ? 8.0 : 4.0;
+  if (op.i0 == 0) {
+    PRef M = op.p[0];
+    const bool tr = op.i1 != 0;
+    const int r = X.rows;   // inner dimension
+    for (int c0 = 0; c0 < c; c0 += 64) {
+      const int w = min(64, c - c0);
+      for (int r0 = 0; r0 < m; r0 += 64) {
+        const int h = min(64, m - r0);
+        double acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int k0 = 0; k0 < r; k0 += 32) {
+          const int d = min(32, r - k0);
+          for (int e = tid; e < 64 * 32; e += NT) {
+            int i = e % 64, kk = e / 64;
+            double v = 0.0;
+            if (i < h && kk < d) v = tr ? pget(M, k0 + kk, r0 + i) : pget(M, r0 + i, k0 + kk);
+            sa[i][kk] = v;
+          }
+          for (int e = tid; e < 32 * 64; e += NT) {
+            int kk = e % 32, j = e / 32;
+            sb[kk][j] = (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
+          }
+          __syncthreads();
+          for (int kk = 0; kk < d; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = sa[ti + 16 * u][kk];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bv[v] = sb[kk][tj + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int i = ti + 16 * u, j = tj + 16 * v;
+            if (i < h && j < w) pset(Y, r0 + i, c0 + j, pget(Y, r0 + i, c0 + j) + sg * acc[u][v]);
+          }
+      }
+    }
+    put_cost(op, 2.0 * m * r * c, 8.0 * m * r + esx * r * c + 2.0 * esy * m * c);
+    return;
+  }
+  // low-rank M: (A, B) = (U, V) or (V, U) when transposed
+  const PRef U = op.p[0], V = op.p[1];
+  const bool tr = op.i1 != 0;
+  const PRef A = tr ? V : U;
+  const PRef B = tr ? U : V;
+  const int k = pcols(U);
+  const int r = X.rows;
+  const double esm = U.dt == DT_F64 ? 8.0 : 4.0;
+  for (int c0 = 0; c0 < c; c0 += 64) {
+    const int w = min(64, c - c0);
+    // T = B^T X  (k x w), k <= 64
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int k0 = 0; k0 < r; k0 += 32) {
+      const int d = min(32, r - k0);
+      for (int e = tid; e < 64 * 32; e += NT) {
+        int i = e % 64, kk = e / 64;   // i: rank index, kk: row of B
+        sa[i][kk] = (i < k && kk < d) ? pget(B, k0 + kk, i) : 0.0;
+      }
+      for (int e = tid; e < 32 * 64; e += NT) {
+        int kk = e % 32, j = e / 32;
+        sb[kk][j] = (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
+      }
+      __syncthreads();
+      for (int kk = 0; kk < d; ++kk) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = sa[ti + 16 * u][kk];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bv[v] = sb[kk][tj + 16 * v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st[ti + 16 * u][tj + 16 * v] = acc[u][v];
+    __syncthreads();
+    // Y += sg * A T
+    for (int r0 = 0; r0 < m; r0 += 64) {
+      const int h = min(64, m - r0);
+      for (int e = tid; e < 64 * 32; e += NT) {
+        int i = e % 64, kk = e / 64;
+        sa[i][kk] = (i < h && kk < k && kk < 32) ? pget(A, r0 + i, kk) : 0.0;
+      }
+      __syncthreads();
+      double o[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[u][v] = 0.0;
+      const int kk_end = min(k, 32);
+      for (int kk = 0; kk < kk_end; ++kk) {
+        double av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = sa[ti + 16 * u][kk];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[u][v] += av[u] * st[kk][tj + 16 * v];
+      }
+      __syncthreads();
+      if (k > 32) {
+        for (int e = tid; e < 64 * 32; e += NT) {
+          int i = e % 64, kk = e / 64;
+          sa[i][kk] = (i < h && 32 + kk < k) ? pget(A, r0 + i, 32 + kk) : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < k - 32; ++kk) {
+          double av[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[u] = sa[ti + 16 * u][kk];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[u][v] += av[u] * st[32 + kk][tj + 16 * v];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int i = ti + 16 * u, j = tj + 16 * v;
+          if (i < h && j < w) pset(Y, r0 + i, c0 + j, pget(Y, r0 + i, c0 + j) + sg * o[u][v]);
+        }
+    }
+    __syncthreads();
+  }
+  put_cost(op, 2.0 * (double)k * c * (r + m),
+           esm * (double)k * (r + m) + esx * r * c + 2.0 * esy * m * c);
+}
+
+// ---------------------------------------------------------------- dense update
+// p0 (FP64 dense, m x n) -= p1 p2^T
+__global__ void __launch_bounds__(NT) k_addd(const Op* __restrict__ ops) {
+  const Op& op = ops[blockIdx.x];
+  const PRef C = op.p[0], X = op.p[1], Y = op.p[2];
+  const int m = C.rows, n = C.cols;
+  const int k = pcols(X);
+  __shared__ double sa[64][33];
+  __shared__ double sb[32][65];
+  const int tid = threadIdx.x;
+  const int ti = tid % 16, tj = tid / 16;
+  double* g = reinterpret_cast<double*>(C.ptr);
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int w = min(64, n - c0);
+    for (int r0 = 0; r0 < m; r0 += 64) {
+      const int h = min(64, m - r0);
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      for (int k0 = 0; k0 < k; k0 += 32) {
+        const int d = min(32, k - k0);
+        for (int e = tid; e < 64 * 32; e += NT) {
+          int i = e % 64, kk = e / 64;
+          sa[i][kk] = (i < h && kk < d) ? pget(X, r0 + i, k0 + kk) : 0.0;
+        }
+        for (int e = tid; e < 32 * 64; e += NT) {
+          int kk = e % 32, j = e / 32;
+          sb[kk][j] = (kk < d && j < w) ? pget(Y, c0 + j, k0 + kk) : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < d; ++kk) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[u] = sa[ti + 16 * u][kk];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bv[v] = sb[kk][tj + 16 * v];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int i = ti + 16 * u, j = tj + 16 * v;
+          if (i < h && j < w) g[(r0 + i) + (size_t)(c0 + j) * C.ld] -= acc[u][v];
+        }
+    }
+  }
+  const double es = X.dt == DT_F64 ? 8.0 : 4.0;
+  put_cost(op, 2.0 * m * n * k, 16.0 * m * n + es * (double)k * (m + n));
+}
+
+// ---------------------------------------------------------------- zero
+__global__ void __launch_bounds__(NT) k_zero(const Op* __restrict__ ops) {
+  const Op& op = ops[blockIdx.x];
+  const PRef Z = op.p[0];
+  const int tot = Z.rows * Z.cols;
+  for (int e = threadIdx.x; e < tot; e += NT) {
+    int i = e % Z.rows, j = e / Z.rows;
+    pset(Z, i, j, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------- truncation
+// C = U V^T (rank kc) and the term X Y^T (kx columns, X at row xo of C,
+// Y at row yo) are stacked as Xs = [U, -X], Ys = [V, Y] (K = kc + kx <= 64).
+//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys (FP64, streamed rows);
+//   2. column balancing so that |x_j| = |y_j|;
+//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T, Gy = Pi_y S^T S Pi_y^T,
+//      stopping at pivots below 1e-28 of the largest (rank revealing);
+//   4. M = R Pi_x^T Pi_y S^T and its one-sided Jacobi SVD M = W Sig Z^T;
+//   5. rank choice (fixed, or the smallest k with discarded Frobenius norm
+//      <= eps |Sig|, capped);
+//   6. U := Xs Tx, V := Ys Ty with Tx = D Pi_x R11^{-1} W_k Sig_k and
+//      Ty = D^{-1} Pi_y S11^{-1} Z_k, streamed row by row (in place).
+#define KM 64
+struct TruncShared {
+  double gx[KM][KM + 1];
+  double gy[KM][KM + 1];
+  double m[KM][KM + 1];     // chunk buffer / M / W
+  double z[KM][KM + 1];     // Z (right singular vectors) / Tx, Ty
+  double dsc[KM];
+  double sig[KM];
+  int px[KM], py[KM], ord[KM];
+  int rx, ry, k, K, kc, rot, capped;
+  double red[NT / 64];
+};
+
+__device__ __forceinline__ double xs_get(const PRef& U, const PRef& X, int kc, int xo, int i,
+                                         int j) {
+  if (j < kc) return pget(U, i, j);
+  int ii = i - xo;
+  if (ii < 0 || ii >= X.rows) return 0.0;
+  return pget(X, ii, j - kc);
+}
+
+// G (K x K) = S^T S where S rows are produced by xs_get; rows streamed in
+// chunks of 64 through sh.m
+__device__ void gram(TruncShared& sh, double (*G)[KM + 1], const PRef& U, const PRef& X, int kc,
+                     int xo, int rows, int K, double xsign) {
+  const int tid = threadIdx.x;
+  // each thread owns up to 16 entries (i, j) of the K x K result
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    const int h = min(64, rows - r0);
+    for (int e = tid; e < 64 * K; e += NT) {
+      int i = e % 64, j = e / 64;
+      double v = 0.0;
+      if (i < h) {
+        v = xs_get(U, X, kc, xo, r0 + i, j);
+        if (j >= kc) v *= xsign;
+      }
+      sh.m[i][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      int e = tid + q * NT;
+      if (e < K * K) {
+        int a = e % K, b = e / K;
+        double s = 0.0;
+        for (int i = 0; i < h; ++i) s += sh.m[i][a] * sh.m[i][b];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    int e = tid + q * NT;
+    if (e < K * K) G[e % K][e / K] = acc[q];
+  }
+  __syncthreads();
+}
+
+// In-place pivoted Cholesky of G (K x K): on exit rows 0..r-1 of G hold R
+// (in pivot order: R[i][j] for pivot-ordered column j), piv holds the
+// column order and r the numerical rank.
+__device__ void pchol(TruncShared& sh, double (*G)[KM + 1], int* piv, int K, int* r_out) {
+  const int tid = threadIdx.x;
+  __shared__ double s_dmax;
+  __shared__ int s_p;
+  for (int j = tid; j < K; j += NT) piv[j] = j;
+  __syncthreads();
+  // permute physically: we keep G in original indexing and track piv
+  double dmax0 = 0.0;
+  for (int j = 0; j < K; ++j) dmax0 = fmax(dmax0, G[j][j]);
+  int r = 0;
+  for (int step = 0; step < K; ++step) {
+    if (tid == 0) {
+      double best = -1.0;
+      int bp = step;
+      for (int q = step; q < K; ++q) {
+        double d = G[piv[q]][piv[q]];
+        if (d > best) { best = d; bp = q; }
+      }
+      int t = piv[step];
+      piv[step] = piv[bp];
+      piv[bp] = t;
+      s_dmax = best;
+      s_p = piv[step];
+    }
+    __syncthreads();
+    if (!(s_dmax > 1e-14 * dmax0) || dmax0 <= 0.0) break;
+    const int p = s_p;
+    const double rp = sqrt(s_dmax);
+    // row p of R over the remaining columns (pivot order q >= step)
+    __syncthreads();
+    for (int q = step + tid; q < K; q += NT) {
+      int c = piv[q];
+      G[p][c] = (q == step) ? rp : G[p][c] / rp;
+    }
+    __syncthreads();
+    // Schur update of the remaining block
+    const int rem = K - step - 1;
+    for (int e = tid; e < rem * rem; e += NT) {
+      int a = piv[step + 1 + e % rem], b = piv[step + 1 + e / rem];
+      G[a][b] -= G[p][a] * G[p][b];
+    }
+    __syncthreads();
+    ++r;
+  }
+  if (tid == 0) *r_out = r;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
+  const Op& op = ops[blockIdx.x];
+  const PRef U = op.p[0], V = op.p[1], X = op.p[2], Y = op.p[3];
+  const int xo = op.i0, yo = op.i1;
+  const int cap = op.i2 & 0xffff, fixed = op.i2 >> 16;
+  const double eps = op.d0;
+  const int m = U.rows, n = V.rows;
+  __shared__ TruncShared sh;
+  const int tid = threadIdx.x;
+  const int kc = pcols(U);
+  const int kx = pcols(X);
+  const int K = kc + kx;
+  if (tid == 0) { sh.kc = kc; sh.K = K; sh.capped = 0; }
+  // 1. Gram matrices
+  gram(sh, sh.gx, U, X, kc, xo, m, K, -1.0);
+  gram(sh, sh.gy, V, Y, kc, yo, n, K, 1.0);
+  // 2. balancing
+  for (int j = tid; j < K; j += NT) {
+    double a = sh.gx[j][j], b = sh.gy[j][j];
+    sh.dsc[j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += NT) {
+    int a = e % K, b = e / K;
+    double da = sh.dsc[a], db = sh.dsc[b];
+    sh.gx[a][b] *= da * db;
+    sh.gy[a][b] = (da > 0.0 && db > 0.0) ? sh.gy[a][b] / (da * db) : 0.0;
+  }
+  __syncthreads();
+  // 3. pivoted Cholesky of both
+  pchol(sh, sh.gx, sh.px, K, &sh.rx);
+  pchol(sh, sh.gy, sh.py, K, &sh.ry);
+  const int rx = sh.rx, ry = sh.ry;
+  // 4. M = R Pi_x^T Pi_y S^T: M[i][j] = sum_c R_i(c) S_j(c) over original
+  //    columns c, where R_i(c) = gx[px[i]][c] if c is at pivot position >= i
+  //    (zero otherwise).  Build position maps.
+  __shared__ int posx[KM], posy[KM];
+  for (int q = tid; q < K; q += NT) { posx[sh.px[q]] = q; posy[sh.py[q]] = q; }
+  __syncthreads();
+  for (int e = tid; e < rx * ry; e += NT) {
+    int i = e % rx, j = e / rx;
+    int pi = sh.px[i], pj = sh.py[j];
+    double s = 0.0;
+    for (int cidx = 0; cidx < K; ++cidx) {
+      if (posx[cidx] >= i && posy[cidx] >= j) s += sh.gx[pi][cidx] * sh.gy[pj][cidx];
+    }
+    sh.m[i][j] = s;
+  }
+  for (int e = tid; e < KM * KM; e += NT) {
+    int i = e % KM, j = e / KM;
+    sh.z[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // one-sided Jacobi on the columns of M (rx rows, ry columns): M Z = W Sig
+  const int ncol = ry + (ry & 1);
+  if (ncol >= 2 && rx > 0) {
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      if (tid == 0) sh.rot = 0;
+      __syncthreads();
+      for (int round = 0; round < ncol - 1; ++round) {
+        // round-robin pairing of ncol players: pair q = (a, b)
+        const int npair = ncol / 2;
+        const int grp = 8;                 // threads per pair
+        const int q = tid / grp, l = tid % grp;
+        for (int qq = q; qq < npair; qq += NT / grp) {
+          int a, b;
+          {
+            // players 0..ncol-1, player ncol-1 fixed
+            int x0 = (qq == 0) ? ncol - 1 : (round + qq) % (ncol - 1);
+            int x1 = (round + ncol - 1 - qq) % (ncol - 1);
+            if (qq == 0) x1 = round % (ncol - 1);
+            a = min(x0, x1);
+            b = max(x0, x1);
+          }
+          double al = 0, be = 0, ga = 0;
+          const bool valid = b < ry;
+          if (valid) {
+            for (int i = l; i < rx; i += grp) {
+              double u = sh.m[i][a], v = sh.m[i][b];
+              al += u * u;
+              be += v * v;
+              ga += u * v;
+            }
+          }
+          for (int o = grp / 2; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o);
+            be += __shfl_xor(be, o);
+            ga += __shfl_xor(ga, o);
+          }
+          if (valid && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+            double zeta = (be - al) / (2.0 * ga);
+            double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+            for (int i = l; i < rx; i += grp) {
+              double u = sh.m[i][a], v = sh.m[i][b];
+              sh.m[i][a] = cs * u - sn * v;
+              sh.m[i][b] = sn * u + cs * v;
+            }
+            for (int i = l; i < ry; i += grp) {
+              double u = sh.z[i][a], v = sh.z[i][b];
+              sh.z[i][a] = cs * u - sn * v;
+              sh.z[i][b] = sn * u + cs * v;
+            }
+            if (l == 0) sh.rot = 1;
+          }
+        }
+        __syncthreads();
+      }
+      if (!sh.rot) break;
+      __syncthreads();
+    }
+  }
+  // singular values and order
+  for (int j = tid; j < ry; j += NT) {
+    double s = 0.0;
+    for (int i = 0; i < rx; ++i) s += sh.m[i][j] * sh.m[i][j];
+    sh.sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int nr = (rx > 0) ? ry : 0;
+    for (int j = 0; j < nr; ++j) sh.ord[j] = j;
+    for (int a = 1; a < nr; ++a) {     // insertion sort, descending, stable
+      int v = sh.ord[a];
+      int b = a - 1;
+      while (b >= 0 && sh.sig[sh.ord[b]] < sh.sig[v]) { sh.ord[b + 1] = sh.ord[b]; --b; }
+      sh.ord[b + 1] = v;
+    }
+    int lim = min(nr, rx);
+    int k;
+    if (fixed > 0) {
+      k = min(fixed, lim);
+    } else {
+      double tot = 0.0;
+      for (int j = 0; j < nr; ++j) tot += sh.sig[j] * sh.sig[j];
+      double thr = eps * eps * tot, tail = 0.0;
+      k = nr;
+      for (int j = nr; j >= 0; --j) {
+        if (tail <= thr) k = j;
+        else break;
+        if (j > 0) tail += sh.sig[sh.ord[j - 1]] * sh.sig[sh.ord[j - 1]];
+      }
+      k = min(k, lim);
+      sh.capped = 0;
+      if (k > cap) {
+        k = cap;
+        sh.capped = 1;
+      }
+    }
+    sh.k = k;
+  }
+  __syncthreads();
+  const int k = sh.k;
+  // 6. per side: T = D^{+-1} Pi R11^{-1} (columns ord[0..k) of W Sig or Z),
+  //    by column-oriented back substitution in LDS; then stream the new
+  //    factor rows (in place: every row chunk is read before it is written).
+  // tt is indexed by stacked column: the unknown of pivot position i lives
+  // in row pv[i]; columns beyond the numerical rank stay zero.
+  __shared__ double tt[KM][33];
+  for (int side = 0; side < 2; ++side) {
+    const int r = side == 0 ? rx : ry;
+    double (*G)[KM + 1] = side == 0 ? sh.gx : sh.gy;
+    const int* pv = side == 0 ? sh.px : sh.py;
+    double (*src)[KM + 1] = side == 0 ? sh.m : sh.z;
+    for (int e = tid; e < K * k; e += NT) {
+      int c2 = e % K, c = e / K;
+      tt[c2][c] = 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * k; e += NT) {
+      int i = e % r, c = e / r;
+      tt[pv[i]][c] = src[i][sh.ord[c]];
+    }
+    __syncthreads();
+    for (int i = r - 1; i >= 0; --i) {
+      const int pi = pv[i];
+      const double d = G[pi][pi];
+      if (tid < k) tt[pi][tid] /= d;
+      __syncthreads();
+      for (int e = tid; e < i * k; e += NT) {
+        int j = e % i, c = e / i;
+        tt[pv[j]][c] -= G[pv[j]][pi] * tt[pi][c];
+      }
+      __syncthreads();
+    }
+    // balancing scale of the stacked columns
+    for (int e = tid; e < K * k; e += NT) {
+      int c2 = e % K, c = e / K;
+      double dd = sh.dsc[c2];
+      tt[c2][c] = side == 0 ? tt[c2][c] * dd : (dd > 0.0 ? tt[c2][c] / dd : 0.0);
+    }
+    __syncthreads();
+    const PRef& F = side == 0 ? U : V;
+    const PRef& T = side == 0 ? X : Y;
+    const int rows = side == 0 ? m : n;
+    const int off = side == 0 ? xo : yo;
+    const double sgn = side == 0 ? -1.0 : 1.0;
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+      const int h = min(64, rows - r0);
+      for (int e = tid; e < 64 * K; e += NT) {
+        int i = e % 64, j = e / 64;
+        double v = 0.0;
+        if (i < h) {
+          v = xs_get(F, T, kc, off, r0 + i, j);
+          if (j >= kc) v *= sgn;
+        }
+        sh.m[i][j] = v;
+      }
+      __syncthreads();
+      for (int e = tid; e < h * k; e += NT) {
+        int i = e % h, j = e / h;
+        double s = 0.0;
+        for (int c2 = 0; c2 < K; ++c2) s += sh.m[i][c2] * tt[c2][j];
+        pset(F, r0 + i, j, s);
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) *reinterpret_cast<int32_t*>(U.rankp) = k;
+  const double es = U.dt == DT_F64 ? 8.0 : 4.0;
+  const double flops = 2.0 * (m + n) * K * K - 4.0 * K * K * K / 3.0 + 2.0 * K * K * K +
+                       21.0 * K * K * K + 2.0 * (m + n) * K * k;
+  put_cost(op, flops, es * (double)(m + n) * (K + k), (double)sh.capped, (double)k);
+}
+
+// ---------------------------------------------------------------- matvec
+// T_b = V_b^T X[c0:c0+n, :] for every low-rank block b of the matvec copy.
+__global__ void __launch_bounds__(NT) k_mv_t(const MvLR* __restrict__ lr, const double* X,
+                                             int ldx, int nrhs) {
+  const MvLR e = lr[blockIdx.x];
+  if (e.k == 0) return;
+  const double* V = reinterpret_cast<const double*>(e.V);
+  double* T = reinterpret_cast<double*>(e.T);
+  __shared__ double sv[32][65];
+  __shared__ double sx[32][65];
+  const int tid = threadIdx.x;
+  const int ti = tid % 16, tj = tid / 16;
+  for (int k0 = 0; k0 < e.k; k0 += 64) {
+    const int kk = min(64, e.k - k0);
+    for (int c0 = 0; c0 < nrhs; c0 += 64) {
+      const int w = min(64, nrhs - c0);
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      for (int r0 = 0; r0 < e.n; r0 += 32) {
+        const int d = min(32, e.n - r0);
+        for (int q = tid; q < 32 * 64; q += NT) {
+          int i = q % 32, j = q / 32;
+          sv[i][j] = (i < d && j < kk) ? V[(r0 + i) + (size_t)(k0 + j) * e.n] : 0.0;
+          sx[i][j] = (i < d && j < w) ? X[(e.c0 + r0 + i) + (size_t)(c0 + j) * ldx] : 0.0;
+        }
+        __syncthreads();
+        for (int i = 0; i < d; ++i) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[u] = sv[i][ti + 16 * u];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bv[v] = sx[i][tj + 16 * v];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int a = ti + 16 * u, b = tj + 16 * v;
+          if (a < kk && b < w) T[(k0 + a) + (size_t)(c0 + b) * e.kcap] = acc[u][v];
+        }
+    }
+  }
+}
+
+// y[rows of leaf] = beta * b + alpha * sum over the leaf row's blocks (F X or
+// U T): (0, 1) gives y = A X, (1, -1) the residual b - A X.
+__global__ void __launch_bounds__(NT) k_mv_rows(const MvRow* __restrict__ rows,
+                                                const MvTerm* __restrict__ terms,
+                                                const double* X, int ldx, const double* B,
+                                                double beta, double alpha, double* Yo,
+                                                int nrhs) {
+  const MvRow r = rows[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < nrhs; c0 += 4) {
+    // each thread: row i = tid % 64, column c0 + tid / 64
+    const int i = tid % 64, j = c0 + tid / 64;
+    double acc = 0.0;
+    const bool act = i < r.rows && j < nrhs;
+    for (int q = 0; q < r.nt; ++q) {
+      const MvTerm t = terms[r.t0 + q];
+      const double* A = reinterpret_cast<const double*>(t.A);
+      if (!act) continue;
+      if (t.T == 0) {
+        const double* x = X + (size_t)j * ldx + t.c0;
+        for (int c = 0; c < t.ncol; ++c) acc += A[(t.roff + i) + (size_t)c * t.lda] * x[c];
+      } else {
+        const double* T = reinterpret_cast<const double*>(t.T) + (size_t)j * t.c0;
+        for (int c = 0; c < t.ncol; ++c) acc += A[(t.roff + i) + (size_t)c * t.lda] * T[c];
+      }
+    }
+    if (act) {
+      size_t o = (size_t)(r.r0 + i) + (size_t)j * ldx;
+      Yo[o] = beta * (B ? B[o] : 0.0) + alpha * acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- vectors
+__global__ void k_gather(const double* b, int64_t ldb, double* Y, int ldy, const int64_t* perm,
+                         int n, int nrhs) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nrhs) return;
+  int p = (int)(e % n), j = (int)(e / n);
+  Y[p + (size_t)j * ldy] = b[perm[p] + (size_t)j * ldb];
+}
+
+__global__ void k_scatter(const double* Y, int ldy, double* x, int64_t ldx, const int64_t* perm,
+                          int n, int nrhs) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nrhs) return;
+  int p = (int)(e % n), j = (int)(e / n);
+  x[perm[p] + (size_t)j * ldx] = Y[p + (size_t)j * ldy];
+}
+
+__global__ void k_axpy(double* X, const double* D, int ld, int n, int nrhs, double a) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nrhs) return;
+  int p = (int)(e % n), j = (int)(e / n);
+  X[p + (size_t)j * ld] = (a == 0.0 ? 0.0 : X[p + (size_t)j * ld]) + D[p + (size_t)j * ld];
+}
+
+// per column j: out[3j] = max|R_j|, out[3j+1] = max|X_j|, out[3j+2] = max|B_j|
+__global__ void __launch_bounds__(NT) k_colmax(const double* R, const double* X, const double* B,
+                                               int ld, int n, double* out) {
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double red[3][NT];
+  double a = 0, b = 0, c = 0;
+  for (int i = tid; i < n; i += NT) {
+    size_t o = (size_t)i + (size_t)j * ld;
+    a = fmax(a, fabs(R[o]));
+    b = fmax(b, fabs(X[o]));
+    c = fmax(c, fabs(B[o]));
+  }
+  red[0][tid] = a;
+  red[1][tid] = b;
+  red[2][tid] = c;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s)
+      for (int q = 0; q < 3; ++q) red[q][tid] = fmax(red[q][tid], red[q][tid + s]);
+    __syncthreads();
+  }
+  if (tid < 3) out[3 * j + tid] = red[tid][0];
+}
+
+__global__ void k_set_int(int32_t* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// ---------------------------------------------------------------- launchers
+static hipError_t launch_ops(int type, const Op* ops, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  dim3 g(count), b(NT);
+  switch (type) {
+    case OP_GETRF: hipLaunchKernelGGL(k_getrf, g, b, 0, s, ops); break;
+    case OP_TRSM_L:
+    case OP_TRSM_UT:
+    case OP_TRSM_U: hipLaunchKernelGGL(k_trsm, g, b, 0, s, ops); break;
+    case OP_PGEMM: hipLaunchKernelGGL(k_pgemm, g, b, 0, s, ops); break;
+    case OP_TRUNC: hipLaunchKernelGGL(k_trunc, g, b, 0, s, ops); break;
+    case OP_ADDD: hipLaunchKernelGGL(k_addd, g, b, 0, s, ops); break;
+    case OP_ZERO: hipLaunchKernelGGL(k_zero, g, b, 0, s, ops); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hlu
+
+extern "C" hipError_t hlu_launch_ops(int type, const void* ops, int count, hipStream_t s) {
+  return hlu::launch_ops(type, reinterpret_cast<const hlu::Op*>(ops), count, s);
+}
+
+extern "C" hipError_t hlu_launch_mv(const void* lr, int nlr, const void* rows, int nrows,
+                                    const void* terms, const double* X, int ldx, const double* B,
+                                    double beta, double alpha, double* Y, int nrhs,
+                                    hipStream_t s) {
+  if (nlr > 0)
+    hipLaunchKernelGGL(hlu::k_mv_t, dim3(nlr), dim3(NT), 0, s,
+                       reinterpret_cast<const hlu::MvLR*>(lr), X, ldx, nrhs);
+  if (nrows > 0)
+    hipLaunchKernelGGL(hlu::k_mv_rows, dim3(nrows), dim3(NT), 0, s,
+                       reinterpret_cast<const hlu::MvRow*>(rows),
+                       reinterpret_cast<const hlu::MvTerm*>(terms), X, ldx, B, beta, alpha, Y,
+                       nrhs);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, double* y, int ldy,
+                                     const int64_t* perm, int n, int nrhs, hipStream_t s) {
+  int64_t tot = (int64_t)n * nrhs;
+  dim3 g((unsigned)((tot + 255) / 256)), b(256);
+  if (tot == 0) return hipSuccess;
+  if (what == 0) hipLaunchKernelGGL(hlu::k_gather, g, b, 0, s, a, lda, y, ldy, perm, n, nrhs);
+  else if (what == 1)
+    hipLaunchKernelGGL(hlu::k_scatter, g, b, 0, s, a, ldy, y, lda, perm, n, nrhs);
+  else if (what == 2) hipLaunchKernelGGL(hlu::k_axpy, g, b, 0, s, y, a, ldy, n, nrhs, 1.0);
+  else if (what == 3) hipLaunchKernelGGL(hlu::k_axpy, g, b, 0, s, y, a, ldy, n, nrhs, 0.0);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
+                                        int n, int nrhs, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(hlu::k_colmax, dim3(nrhs), dim3(NT), 0, s, R, X, B, ld, n, out);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(hlu::k_set_int, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}

@@ -1,0 +1,74 @@
+// Device-visible descriptors of the static H-LU schedule.
+//
+// The host planner walks the recursive H-LU (the O1.1-O5.5 sequence of the
+// paper's Sec. 3.1, with the partitioned solves of Sec. 4.3) once, emits one
+// descriptor per primitive operation on dense leaf blocks and on the factor
+// panels of low-rank blocks, and groups independent operations of the same
+// type into waves.  Every kernel processes one descriptor per workgroup.
+#pragma once
+#include <stdint.h>
+
+namespace hlu {
+
+enum DType : uint8_t { DT_F64 = 0, DT_F32 = 1 };
+enum PKind : uint8_t { PK_MAT = 0, PK_IDENT = 1 };
+
+// A column-major panel (or the transpose of one) in device memory.
+// Element (i, j) of the panel is at ptr[i + j*ld] (trans = 0) or
+// ptr[j + i*ld] (trans = 1).  cols is static when rankp == 0, otherwise the
+// column count is the int32 at rankp (the live rank of a low-rank block or
+// the right-hand-side count of a solve).  kind == PK_IDENT stands for the
+// rows x rows identity (ptr unused).
+struct PRef {
+  uint64_t ptr;
+  uint64_t rankp;
+  int32_t ld;
+  int32_t rows;
+  int32_t cols;
+  uint8_t dt, trans, kind, pad;
+};
+
+enum OpType : int32_t {
+  OP_GETRF = 0,    // p0: b x b leaf (FP64) in place; p1.ptr: int32 piv[b];
+                   // p1.rankp: int32 info word; i0: first row of the leaf
+  OP_TRSM_L = 1,   // p0: factored leaf; p2.ptr: piv; p1 := L^{-1} P p1
+  OP_TRSM_UT = 2,  // p0: factored leaf; p1 := U^{-T} p1
+  OP_TRSM_U = 3,   // p0: factored leaf; p1 := U^{-1} p1
+  OP_PGEMM = 4,    // p3 += d0 * op(M) p2; i0 = 0: M dense p0;
+                   // i0 = 1: M = p0 p1^T (low-rank); i1: transpose M
+  OP_TRUNC = 5,    // C = p0 p1^T (rank at p0.rankp, capacity i2 & 0xffff,
+                   // fixed rank i2 >> 16); C := best approx of C - X Y^T with
+                   // X = p2 placed at row i0 of C, Y = p3 at row i1; d0 = eps
+  OP_ADDD = 6,     // p0 (dense FP64) -= p1 p2^T
+  OP_ZERO = 7,     // p0 := 0 (static columns)
+  OP_NTYPES = 8
+};
+
+struct Op {
+  int32_t type;
+  int32_t i0, i1, i2;
+  double d0;
+  uint64_t cost;   // device address of this op's {flops, bytes} record (0: none)
+  PRef p[4];
+};
+
+// Matvec with the refinement copy: per low-rank block, T = V^T X[s];
+// per leaf row cluster, y = b - sum(F X[s]) - sum(U T).
+struct MvLR {        // one low-rank block of the matvec copy (FP64)
+  uint64_t U, V, T;  // U: m x k (ld m), V: n x k (ld n), T: k x nrhs (ld kcap)
+  int32_t m, n, k, kcap;
+  int32_t r0, c0;    // first row / column (cluster order)
+};
+struct MvTerm {      // one contribution to a leaf row cluster
+  uint64_t A;        // dense: block pointer (ld = lda); low-rank: U pointer
+  uint64_t T;        // low-rank: T of the block (0 for dense)
+  int32_t lda;       // leading dimension of A
+  int32_t roff;      // row of the leaf inside the block
+  int32_t ncol;      // dense: block columns; low-rank: rank
+  int32_t c0;        // dense: first column (cluster order); low-rank: kcap (ld of T)
+};
+struct MvRow {       // one leaf row cluster
+  int32_t r0, rows, t0, nt;   // rows [r0, r0+rows); terms [t0, t0+nt)
+};
+
+}  // namespace hlu

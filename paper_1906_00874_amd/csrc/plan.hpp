@@ -1,0 +1,110 @@
+// Host planner: cluster tree, block tree, host assembly, device layout and
+// the static schedules of factorisation, solve and matvec.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ops.h"
+
+namespace hlu {
+
+struct Params {
+  int kernel = 0;          // 0 weighted, 1 point
+  double eta = 2.0;
+  int leaf = 32;
+  int fixed_rank = 0;
+  double eps_f = 1e-6;
+  int cap_f = 32;
+  double eps_mv = 1e-12;
+  int cap_mv = 64;
+  int mixed = 0;
+  double refine_tol = 0.0;
+  int refine_max_iter = 10;
+  int max_nrhs = 32;
+};
+
+struct Cluster {
+  int off = 0, size = 0;
+  double lo[3], hi[3];
+  int son[2] = {-1, -1};
+  int leaf = -1;           // leaf index if a leaf
+  int first_leaf = 0, nleaves = 0;
+};
+
+struct BNode {
+  int t, s;
+  char kind;               // 'F', 'R', 'H'
+  int son[4] = {-1, -1, -1, -1};
+  int blk = -1;            // leaf block index (F or R)
+};
+
+struct LBlock {
+  int t, s;
+  char kind;
+  int m, n;
+  uint64_t offF = 0;       // dense (FP64, ld m)
+  uint64_t offU = 0, offV = 0, offRank = 0;   // factor copy (capacity cap_f)
+  int objF = -1, objU = -1, objV = -1, objRank = -1;
+  // matvec copy
+  uint64_t mvU = 0, mvV = 0;
+  int mvk = 0;
+  int kf = 0;              // assembled rank of the factor copy
+};
+
+struct Batch {
+  int wave, type, start, count;
+};
+
+struct Schedule {
+  std::vector<Op> ops;     // sorted by (wave, type); pointers are byte offsets
+  std::vector<Batch> batches;
+  int waves = 0;
+};
+
+struct Plan {
+  Params prm;
+  int n = 0;
+  std::vector<double> xyz, area;   // cluster order
+  std::vector<int64_t> perm;       // perm[p] = original index
+  std::vector<Cluster> cl;
+  std::vector<int> leaves;         // cluster ids of leaves in order
+  std::vector<BNode> bn;
+  std::vector<LBlock> blk;
+  int broot = 0;
+
+  // device layout (byte offsets from the bound base)
+  uint64_t off_status = 0;         // int32 info, int32 flags, ...
+  uint64_t off_work = 0, size_work = 0;      // ranks | dense | low-rank
+  uint64_t off_pristine = 0;
+  uint64_t off_piv = 0;
+  uint64_t off_mv = 0, size_mv = 0;
+  uint64_t off_scratch = 0, size_scratch = 0;
+  uint64_t off_cost = 0;           // per-op {flops, bytes} (doubles)
+  uint64_t off_ws = 0;             // solve / refinement workspace
+  uint64_t off_nrhs = 0;           // int32 nrhs slot used by solve panels
+  uint64_t off_Y = 0, off_X = 0, off_B = 0, off_eta = 0;
+  uint64_t off_mvT = 0;
+  uint64_t off_ops_f = 0, off_ops_s = 0;
+  uint64_t off_mv_lr = 0, off_mv_terms = 0, off_mv_rows = 0, off_perm = 0;
+  uint64_t total = 0;
+
+  std::vector<char> img_work;      // host image of the work region
+  std::vector<char> img_mv;        // host image of the matvec region
+
+  Schedule fsched, ssched;
+  std::vector<MvLR> mv_lr;
+  std::vector<MvTerm> mv_terms;
+  std::vector<MvRow> mv_rows;
+
+  double anorm_inf = 0.0;          // max row sum of |A| (exact)
+  double flops_model = 0.0;
+  int64_t max_rank_f = 0;
+  std::string err;
+};
+
+// Build everything on the host; returns false and sets p.err on failure.
+bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n,
+                const Params& prm);
+
+}  // namespace hlu

@@ -1,0 +1,115 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the library loads
+and exports every declared entry point, argument errors are reported, and
+the host planner builds the same trees as the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from hlu_inputs import icosphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1906_00874_amd as P
+    return P
+
+
+def test_library_exports_every_declared_symbol():
+    P = _lib()
+    hdr = open(os.path.join(ROOT, "include", "hlu.h")).read()
+    names = set(re.findall(r"\b(hlu_[a-z_]+)\s*\(", hdr))
+    names -= {"hlu_handle_s"}
+    assert len(names) >= 15
+    for n in sorted(names):
+        assert hasattr(P.lib, n), n
+
+
+def test_plan_matches_oracle_trees():
+    P = _lib()
+    for level, leaf in [(2, 16), (3, 32), (4, 32)]:
+        xyz, area = icosphere(level)
+        h = P.HLU(xyz, area, assemble=False, leaf=leaf, eta=2.0, eps=1e-6, cap=32)
+        root, perm, leaves = O.cluster_tree(xyz, leaf)
+        assert np.array_equal(perm, h.perm())
+        H = O.HMatrix(xyz, area, leaf, 2.0, O.Rule(eps=1e-2, cap=4))
+        st = h.stats()
+        ost = H.stats()
+        assert st["leaves"] == ost["leaves"]
+        assert st["dense_blocks"] == ost["dense"]
+        assert st["lowrank_blocks"] == ost["lowrank"]
+        assert st["ops_factor"] > 0 and st["waves_factor"] > 0
+
+
+def test_plan_eta_zero_has_no_lowrank_blocks():
+    P = _lib()
+    xyz, area = icosphere(2)
+    h = P.HLU(xyz, area, assemble=False, leaf=16, eta=0.0, eps=1e-6)
+    assert h.stats()["lowrank_blocks"] == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(leaf=0), dict(leaf=65), dict(eta=-1.0), dict(cap=0), dict(cap=33),
+    dict(cap_mv=65), dict(eps=0.0), dict(eps=1.5), dict(max_nrhs=0), dict(max_nrhs=65),
+    dict(fixed_rank=40), dict(eps_mv=0.0),
+])
+def test_plan_argument_errors(bad):
+    P = _lib()
+    xyz, area = icosphere(1)
+    with pytest.raises(P.HLUError) as e:
+        P.HLU(xyz, area, assemble=False, **bad)
+    assert e.value.status == 1
+
+
+def test_plan_rejects_nan_and_null():
+    P = _lib()
+    xyz, area = icosphere(1)
+    xyz = xyz.copy()
+    xyz[3, 1] = np.nan
+    with pytest.raises(P.HLUError) as e:
+        P.HLU(xyz, area, assemble=False)
+    assert e.value.status == 1
+    h = C.c_void_p()
+    prm = P.binding.make_params()
+    assert P.lib.hlu_plan(None, None, 10, C.byref(prm), C.byref(h)) == 1
+    assert "NULL" in P.lib.hlu_last_error().decode()
+
+
+def test_state_errors_without_device():
+    P = _lib()
+    xyz, area = icosphere(1)
+    h = P.HLU(xyz, area, assemble=False)
+    dummy = C.c_void_p(256)
+    # solve before factor, factor before assemble, bind with too few bytes
+    assert P.lib.hlu_solve(h.h, dummy, dummy, 1, h.n, None) == 6
+    assert P.lib.hlu_factor(h.h, None) == 6
+    assert P.lib.hlu_assemble(h.h, None) == 6
+    assert P.lib.hlu_bind(h.h, dummy, 16) == 2
+    assert P.lib.hlu_required_bytes(None) == 0
+
+
+def test_schedule_statistics_scale():
+    P = _lib()
+    xyz, area = icosphere(3)
+    h = P.HLU(xyz, area, assemble=False, leaf=32)
+    st = h.stats()
+    # every op in a wave is independent; the wave count is at least the
+    # number of diagonal leaves (one getrf each, strictly ordered)
+    assert st["waves_factor"] >= st["leaves"]
+    launches = h.batches()
+    assert launches[0] == st["leaves"]          # one getrf launch per leaf
+
+
+@pytest.mark.parametrize("level,leaf,prec,fixed", [(2, 16, 0, 0), (3, 32, 0, 8), (3, 32, 1, 0),
+                                                   (4, 32, 1, 0), (3, 64, 0, 0)])
+def test_schedule_validates(level, leaf, prec, fixed):
+    """Every descriptor stays inside the buffer at full capacity and has
+    consistent operand shapes (checked on the host before any launch)."""
+    P = _lib()
+    xyz, area = icosphere(level)
+    h = P.HLU(xyz, area, assemble=False, leaf=leaf, precision=prec, fixed_rank=fixed)
+    h.validate()
