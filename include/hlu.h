@@ -122,6 +122,12 @@ hlu_status hlu_reset(hlu_handle h, void* stream);
  * recorded on the device and reported by hlu_sync. */
 hlu_status hlu_factor(hlu_handle h, void* stream);
 
+/* enable != 0 (the default): hlu_factor and the solves replay a HIP graph
+ * of the schedule (built on first use, one kernel node per wave); 0: one
+ * launch per wave from the host.  Both execute the same kernels in the same
+ * order. */
+hlu_status hlu_set_graph(hlu_handle h, int enable);
+
 /* hlu_factor with a HIP event pair around every launch on `stream`;
  * returns the summed launch durations (ms) and launch counts per op type
  * (arrays of 8).  Synchronises the stream; used for roofline figures. */
@@ -165,6 +171,13 @@ hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* 
 
 /* Number of kernel launches per op type in the factor schedule (8 int64). */
 hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches);
+
+/* Diagnostics: the per-op records of the last factorisation in schedule
+ * order (8 doubles per op: model flops, algorithmic bytes, rank-capacity hit,
+ * rank, start and end tick of the device wall clock, stack width, unused)
+ * and static op information (4 int32 per op: type, wave, rows of the first
+ * and second operand).  recs: ops_factor*8, info: ops_factor*4.  Synchronous. */
+hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info);
 
 /* Cluster-order permutation: perm[p] = original index of position p (host
  * array of n int64). */

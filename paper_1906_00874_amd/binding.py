@@ -60,6 +60,8 @@ _sig = {
     "hlu_factor": (C.c_int, [_P, _P]),
     "hlu_factor_batched": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
     "hlu_factor_profile": (C.c_int, [_P, _P, _P, _P]),
+    "hlu_set_graph": (C.c_int, [_P, C.c_int]),
+    "hlu_factor_records": (C.c_int, [_P, _P, _P]),
     "hlu_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_sync": (C.c_int, [_P, _P, C.POINTER(Info)]),
@@ -169,6 +171,9 @@ class HLU:
         self.bind()
         _check(lib.hlu_assemble(self.h, _stream(stream)))
 
+    def set_graph(self, enable):
+        _check(lib.hlu_set_graph(self.h, int(bool(enable))))
+
     def reset(self, stream=None):
         _check(lib.hlu_reset(self.h, _stream(stream)))
 
@@ -226,6 +231,14 @@ class HLU:
         _check(lib.hlu_factor_cost(self.h, f.ctypes.data_as(_P), b.ctypes.data_as(_P),
                                    c.ctypes.data_as(_P)))
         return f, b, c
+
+    def factor_records(self):
+        """(records (ops, 8) float64, info (ops, 4) int32) of the last factor."""
+        no = self.stats()["ops_factor"]
+        r = np.zeros((no, 8))
+        i = np.zeros((no, 4), dtype=np.int32)
+        _check(lib.hlu_factor_records(self.h, r.ctypes.data_as(_P), i.ctypes.data_as(_P)))
+        return r, i
 
     def export_factors(self, stream=None):
         """(Lhat, U) dense in cluster order (numpy, n <= 8192)."""

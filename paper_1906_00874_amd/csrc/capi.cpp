@@ -23,6 +23,11 @@ extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, dou
 extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
                                         int n, int nrhs, double* out, hipStream_t s);
 extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s);
+extern "C" hipError_t hlu_launch_wave(const void* ops, int count, size_t lds, hipStream_t s);
+extern "C" size_t hlu_lds_bytes(int type);
+extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* starts,
+                                           const int* counts, const size_t* lds, int nwaves,
+                                           int32_t* status, hipGraphExec_t* out);
 
 namespace {
 
@@ -76,7 +81,7 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
       why = "op " + std::to_string(i) + " (type " + std::to_string(o.type) + "): " + w;
       return false;
     };
-    if (o.cost && o.cost + 32 > T) return bad("cost record outside buffer");
+    if (o.cost && o.cost + hlu::kCostRecBytes > T) return bad("cost record outside buffer");
     switch (o.type) {
       case hlu::OP_GETRF:
         if (!panel_ok(o.p[0], T, why)) return bad(why.c_str());
@@ -160,6 +165,15 @@ struct hlu_handle_s {
   double eta_final = 0.0;
   bool not_converged = false;
   hlu_params params;
+  bool use_graph = true;
+  hipGraphExec_t graph_f = nullptr;   // factor schedule (with status reset)
+  hipGraphExec_t graph_s = nullptr;   // solve schedule
+  void drop_graphs() {
+    if (graph_f) hipGraphExecDestroy(graph_f);
+    if (graph_s) hipGraphExecDestroy(graph_s);
+    graph_f = graph_s = nullptr;
+  }
+  ~hlu_handle_s() { drop_graphs(); }
 };
 
 extern "C" {
@@ -311,6 +325,7 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
     HIPCHK(hipMemcpy(b + p.off_mv_rows, p.mv_rows.data(), p.mv_rows.size() * sizeof(hlu::MvRow), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b + p.off_perm, p.perm.data(), sizeof(int64_t) * p.n, hipMemcpyHostToDevice));
   HIPCHK(hipMemset(b + p.off_status, 0, 256));
+  h->drop_graphs();
   h->base = b;
   h->bytes = bytes;
   h->assembled = false;
@@ -369,11 +384,45 @@ hlu_status hlu_reset(hlu_handle h, void* stream) {
   return HLU_OK;
 }
 
+static size_t wave_lds(uint32_t mask) {
+  size_t l = 0;
+  for (int t = 0; t < hlu::OP_NTYPES; ++t)
+    if (mask & (1u << t)) l = std::max(l, hlu_lds_bytes(t));
+  return l;
+}
+
+static hlu_status build_graph(hlu_handle h, const hlu::Schedule& sc, uint64_t off_ops,
+                              int32_t* status, hipGraphExec_t* out) {
+  std::vector<int> st, ct;
+  std::vector<size_t> lds;
+  for (const hlu::Batch& w : sc.waves_list) {
+    st.push_back(w.start);
+    ct.push_back(w.count);
+    lds.push_back(wave_lds(w.mask));
+  }
+  hipError_t e = hlu_build_wave_graph(h->base + off_ops, st.data(), ct.data(), lds.data(),
+                                      (int)st.size(), status, out);
+  if (e != hipSuccess) return fail(HLU_ERR_DEVICE, std::string("graph: ") + hipGetErrorString(e));
+  return HLU_OK;
+}
+
+// One launch per wave (all op types of the wave together), or one replay of
+// the schedule's graph.  `status` (factor only) is reset first.
 static hlu_status run_schedule(hlu_handle h, const hlu::Schedule& sc, uint64_t off_ops,
-                               hipStream_t s) {
+                               hipStream_t s, int32_t* status, hipGraphExec_t* graph) {
+  if (h->use_graph && graph) {
+    if (!*graph) {
+      hlu_status st = build_graph(h, sc, off_ops, status, graph);
+      if (st != HLU_OK) return st;
+    }
+    HIPCHK(hipGraphLaunch(*graph, s));
+    return HLU_OK;
+  }
+  if (status) HIPCHK(hlu_launch_set_int(status, 0, s));
   const char* ops = h->base + off_ops;
-  for (const hlu::Batch& bt : sc.batches) {
-    hipError_t e = hlu_launch_ops(bt.type, ops + (size_t)bt.start * sizeof(hlu::Op), bt.count, s);
+  for (const hlu::Batch& w : sc.waves_list) {
+    hipError_t e = hlu_launch_wave(ops + (size_t)w.start * sizeof(hlu::Op), w.count,
+                                   wave_lds(w.mask), s);
     if (e != hipSuccess) return fail(HLU_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   }
   return HLU_OK;
@@ -384,10 +433,16 @@ hlu_status hlu_factor(hlu_handle h, void* stream) {
   if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
   if (h->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
-  hlu_status st = run_schedule(h, h->plan.fsched, h->plan.off_ops_f, s);
+  hlu_status st = run_schedule(h, h->plan.fsched, h->plan.off_ops_f, s,
+                               (int32_t*)(h->base + h->plan.off_status), &h->graph_f);
   if (st != HLU_OK) return st;
   h->factored = true;
+  return HLU_OK;
+}
+
+hlu_status hlu_set_graph(hlu_handle h, int enable) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  h->use_graph = enable != 0;
   return HLU_OK;
 }
 
@@ -443,9 +498,10 @@ hlu_status hlu_factor_batched(hlu_handle* hs, int count, void* stream) {
     for (int i = 0; i < count; ++i) {
       const hlu::Schedule& sc = hs[i]->plan.fsched;
       const char* ops = hs[i]->base + hs[i]->plan.off_ops_f;
-      while (cur[i] < sc.batches.size() && sc.batches[cur[i]].wave == w) {
-        const hlu::Batch& bt = sc.batches[cur[i]++];
-        HIPCHK(hlu_launch_ops(bt.type, ops + (size_t)bt.start * sizeof(hlu::Op), bt.count, s));
+      while (cur[i] < sc.waves_list.size() && sc.waves_list[cur[i]].wave == w) {
+        const hlu::Batch& bt = sc.waves_list[cur[i]++];
+        HIPCHK(hlu_launch_wave(ops + (size_t)bt.start * sizeof(hlu::Op), bt.count,
+                               wave_lds(bt.mask), s));
       }
     }
   for (int i = 0; i < count; ++i) hs[i]->factored = true;
@@ -469,7 +525,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
   HIPCHK(hlu_launch_set_int((int32_t*)(b + p.off_nrhs), nrhs, s));
   HIPCHK(hlu_launch_vec(0, b_dev, ld, B, n, perm, n, nrhs, s));        // B = P b
   HIPCHK(hlu_launch_vec(3, B, n, Y, n, nullptr, n, nrhs, s));          // Y = B
-  hlu_status st = run_schedule(h, p.ssched, p.off_ops_s, s);
+  hlu_status st = run_schedule(h, p.ssched, p.off_ops_s, s, nullptr, &h->graph_s);
   if (st != HLU_OK) return st;
   HIPCHK(hlu_launch_vec(3, Y, n, X, n, nullptr, n, nrhs, s));          // X = Y
   h->iters = 0;
@@ -498,7 +554,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
       best = std::min(best, eta);
       if (eta <= tol) break;
       if (it >= p.prm.refine_max_iter) { h->not_converged = true; break; }
-      st = run_schedule(h, p.ssched, p.off_ops_s, s);                    // Y = A_H^{-1} Y
+      st = run_schedule(h, p.ssched, p.off_ops_s, s, nullptr, &h->graph_s);                    // Y = A_H^{-1} Y
       if (st != HLU_OK) return st;
       HIPCHK(hlu_launch_vec(2, Y, n, X, n, nullptr, n, nrhs, s));        // X += Y
       h->iters = it + 1;
@@ -544,9 +600,11 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
   inf.eta_final = h->eta_final;
   if (h->factored && h->base && !h->plan.fsched.ops.empty()) {
     size_t no = h->plan.fsched.ops.size();
-    std::vector<double> c(no * 4);
-    HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * 32, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < no; ++i) inf.cap_hits += (int64_t)c[4 * i + 2];
+    const int R = hlu::kCostRecDoubles;
+    std::vector<double> c(no * R);
+    HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * hlu::kCostRecBytes,
+                     hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < no; ++i) inf.cap_hits += (int64_t)c[R * i + 2];
     // ranks of the low-rank blocks live at the start of the work region
     size_t nr = 0;
     for (const auto& b : h->plan.blk) nr += b.kind == 'R';
@@ -568,15 +626,40 @@ hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* 
   if (!h || !flops || !bytes || !counts) return fail(HLU_ERR_ARG, "NULL argument");
   if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
   size_t no = h->plan.fsched.ops.size();
-  std::vector<double> c(no * 4);
-  if (no) HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * 32, hipMemcpyDeviceToHost));
+  const int R = hlu::kCostRecDoubles;
+  std::vector<double> c(no * R);
+  if (no)
+    HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * hlu::kCostRecBytes,
+                     hipMemcpyDeviceToHost));
   for (int t = 0; t < 8; ++t) { flops[t] = 0; bytes[t] = 0; counts[t] = 0; }
   for (size_t i = 0; i < no; ++i) {
     int t = h->plan.fsched.ops[i].type;
-    flops[t] += c[4 * i];
-    bytes[t] += c[4 * i + 1];
+    flops[t] += c[R * i];
+    bytes[t] += c[R * i + 1];
     counts[t]++;
   }
+  return HLU_OK;
+}
+
+// Per-op records of the last factorisation in schedule order (8 doubles per
+// op) and static op information (type, wave, rows of p0, rows of p1).
+hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info) {
+  if (!h || !recs || !info) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  const hlu::Schedule& sc = h->plan.fsched;
+  size_t no = sc.ops.size();
+  if (no)
+    HIPCHK(hipMemcpy(recs, h->base + h->plan.off_cost, no * hlu::kCostRecBytes,
+                     hipMemcpyDeviceToHost));
+  for (const auto& w : sc.waves_list)
+    for (int q = 0; q < w.count; ++q) {
+      const hlu::Op& o = sc.ops[w.start + q];
+      int32_t* r = info + 4 * (size_t)(w.start + q);
+      r[0] = o.type;
+      r[1] = w.wave;
+      r[2] = o.p[0].rows;
+      r[3] = o.p[1].rows;
+    }
   return HLU_OK;
 }
 

@@ -30,16 +30,25 @@ __device__ __forceinline__ void pset(const PRef& r, int i, int j, double v) {
   else reinterpret_cast<float*>(r.ptr)[k] = (float)v;
 }
 
-// per-op record {model flops, algorithmic bytes, rank-capacity hit, rank}
+// per-op record {model flops, algorithmic bytes, rank-capacity hit, rank,
+// start tick, end tick, stack width, 0} (ticks of the constant-rate wall
+// clock, written by thread 0)
 __device__ __forceinline__ void put_cost(const Op& op, double flops, double bytes,
-                                         double cap_hit = 0.0, double rank = 0.0) {
+                                         double cap_hit = 0.0, double rank = 0.0,
+                                         double width = 0.0) {
   if (op.cost && threadIdx.x == 0) {
     double* c = reinterpret_cast<double*>(op.cost);
     c[0] = flops;
     c[1] = bytes;
     c[2] = cap_hit;
     c[3] = rank;
+    c[5] = (double)wall_clock64();
+    c[6] = width;
   }
+}
+
+__device__ __forceinline__ void start_tick(const Op& op) {
+  if (op.cost && threadIdx.x == 0) reinterpret_cast<double*>(op.cost)[4] = (double)wall_clock64();
 }
 
 // ---------------------------------------------------------------- getrf
@@ -47,14 +56,14 @@ __device__ __forceinline__ void put_cost(const Op& op, double flops, double byte
 // (b <= 64) held in LDS; pivot = first row of the largest |a_ik|.
 // Contraction is disabled so that the elimination rounds exactly like the
 // textbook update a - l*u.
-__global__ void __launch_bounds__(NT) k_getrf(const Op* __restrict__ ops) {
+#define LDS_GETRF (64 * 65 * 8 + 16)
+__device__ void d_getrf(const Op& op, char* smem) {
 #pragma clang fp contract(off)
-  const Op& op = ops[blockIdx.x];
   const PRef A = op.p[0];
   const int b = A.rows;
-  __shared__ double a[64][65];
-  __shared__ int s_piv;
-  __shared__ int s_info;
+  double (*a)[65] = reinterpret_cast<double (*)[65]>(smem);
+  int& s_piv = reinterpret_cast<int*>(smem + 64 * 65 * 8)[0];
+  int& s_info = reinterpret_cast<int*>(smem + 64 * 65 * 8)[1];
   const int tid = threadIdx.x;
   double* g = reinterpret_cast<double*>(A.ptr);
   for (int e = tid; e < b * b; e += NT) {
@@ -118,16 +127,16 @@ __global__ void __launch_bounds__(NT) k_getrf(const Op* __restrict__ ops) {
 // p1 := L^{-1} P p1 (OP_TRSM_L), U^{-T} p1 (OP_TRSM_UT) or U^{-1} p1
 // (OP_TRSM_U) with the factored b x b leaf p0 (b <= 64); the panel is
 // processed in chunks of 64 columns.
-__global__ void __launch_bounds__(NT) k_trsm(const Op* __restrict__ ops) {
-  const Op& op = ops[blockIdx.x];
+#define LDS_TRSM (2 * 64 * 65 * 8 + 64 * 4)
+__device__ void d_trsm(const Op& op, char* smem) {
   const PRef L = op.p[0];
   const PRef Y = op.p[1];
   const int b = L.rows;
   const int c = pcols(Y);
   const int type = op.type;
-  __shared__ double l[64][65];
-  __shared__ double y[64][65];
-  __shared__ int pv[64];
+  double (*l)[65] = reinterpret_cast<double (*)[65]>(smem);
+  double (*y)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
+  int* pv = reinterpret_cast<int*>(smem + 2 * 64 * 65 * 8);
   const int tid = threadIdx.x;
   const double* g = reinterpret_cast<const double*>(L.ptr);
   for (int e = tid; e < b * b; e += NT) {
@@ -201,17 +210,17 @@ __global__ void __launch_bounds__(NT) k_trsm(const Op* __restrict__ ops) {
 // ---------------------------------------------------------------- panel products
 // p3 += d0 * op(M) p2.  Dense M: tiles of 64 x 64 outputs with 32-deep LDS
 // slabs.  Low-rank M = A B^T: T = B^T X (k x c) in LDS, then Y += d0 A T.
-__global__ void __launch_bounds__(NT) k_pgemm(const Op* __restrict__ ops) {
-  const Op& op = ops[blockIdx.x];
+#define LDS_PGEMM (64 * 33 * 8 + 32 * 65 * 8 + 64 * 65 * 8)
+__device__ void d_pgemm(const Op& op, char* smem) {
   const PRef X = op.p[2];
   const PRef Y = op.p[3];
   const double sg = op.d0;
   const int tid = threadIdx.x;
   const int c = pcols(Y) < pcols(X) ? pcols(Y) : pcols(X);
   const int m = Y.rows;
-  __shared__ double sa[64][33];
-  __shared__ double sb[32][65];
-  __shared__ double st[64][65];
+  double (*sa)[33] = reinterpret_cast<double (*)[33]>(smem);
+  double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8);
+  double (*st)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8 + 32 * 65 * 8);
   const int ti = tid % 16, tj = tid / 16;   // 16 x 16 threads, 4 x 4 outputs each
   const double esx = X.dt == DT_F64 ? 8.0 : 4.0;
   const double esy = Y.dt == DT_F64 ? 8.0 : 4.0;
@@ -368,13 +377,13 @@ __global__ void __launch_bounds__(NT) k_pgemm(const Op* __restrict__ ops) {
 
 // ---------------------------------------------------------------- dense update
 // p0 (FP64 dense, m x n) -= p1 p2^T
-__global__ void __launch_bounds__(NT) k_addd(const Op* __restrict__ ops) {
-  const Op& op = ops[blockIdx.x];
+#define LDS_ADDD (64 * 33 * 8 + 32 * 65 * 8)
+__device__ void d_addd(const Op& op, char* smem) {
   const PRef C = op.p[0], X = op.p[1], Y = op.p[2];
   const int m = C.rows, n = C.cols;
   const int k = pcols(X);
-  __shared__ double sa[64][33];
-  __shared__ double sb[32][65];
+  double (*sa)[33] = reinterpret_cast<double (*)[33]>(smem);
+  double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8);
   const int tid = threadIdx.x;
   const int ti = tid % 16, tj = tid / 16;
   double* g = reinterpret_cast<double*>(C.ptr);
@@ -425,8 +434,7 @@ __global__ void __launch_bounds__(NT) k_addd(const Op* __restrict__ ops) {
 }
 
 // ---------------------------------------------------------------- zero
-__global__ void __launch_bounds__(NT) k_zero(const Op* __restrict__ ops) {
-  const Op& op = ops[blockIdx.x];
+__device__ void d_zero(const Op& op) {
   const PRef Z = op.p[0];
   const int tot = Z.rows * Z.cols;
   for (int e = threadIdx.x; e < tot; e += NT) {
@@ -438,26 +446,31 @@ __global__ void __launch_bounds__(NT) k_zero(const Op* __restrict__ ops) {
 // ---------------------------------------------------------------- truncation
 // C = U V^T (rank kc) and the term X Y^T (kx columns, X at row xo of C,
 // Y at row yo) are stacked as Xs = [U, -X], Ys = [V, Y] (K = kc + kx <= 64).
-//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys (FP64, streamed rows);
+//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys (FP64, rows streamed in
+//      chunks of 64, 4x4 register blocks per thread);
 //   2. column balancing so that |x_j| = |y_j|;
-//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T, Gy = Pi_y S^T S Pi_y^T,
-//      stopping at pivots below 1e-28 of the largest (rank revealing);
-//   4. M = R Pi_x^T Pi_y S^T and its one-sided Jacobi SVD M = W Sig Z^T;
+//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T, Gy = Pi_y S^T S Pi_y^T
+//      (pivot chosen by a wavefront argmax), stopping at pivots below 1e-14
+//      of the largest diagonal (rank revealing);
+//   4. M = R S^T over the stacked columns and its one-sided Jacobi SVD
+//      M = W Sig Z^T (round-robin pairs, 8 lanes per pair);
 //   5. rank choice (fixed, or the smallest k with discarded Frobenius norm
 //      <= eps |Sig|, capped);
 //   6. U := Xs Tx, V := Ys Ty with Tx = D Pi_x R11^{-1} W_k Sig_k and
-//      Ty = D^{-1} Pi_y S11^{-1} Z_k, streamed row by row (in place).
+//      Ty = D^{-1} Pi_y S11^{-1} Z_k, streamed row chunk by row chunk in
+//      place (each chunk is read before it is written).
 #define KM 64
 struct TruncShared {
   double gx[KM][KM + 1];
   double gy[KM][KM + 1];
-  double m[KM][KM + 1];     // chunk buffer / M / W
-  double z[KM][KM + 1];     // Z (right singular vectors) / Tx, Ty
+  double m[KM][KM + 1];     // chunk buffer / M / W Sig
+  double z[KM][KM + 1];     // Z
+  double tt[KM][33];        // Tx / Ty in stacked-column order
   double dsc[KM];
   double sig[KM];
-  int px[KM], py[KM], ord[KM];
-  int rx, ry, k, K, kc, rot, capped;
-  double red[NT / 64];
+  int px[KM], py[KM], posx[KM], posy[KM], ord[KM];
+  int rx, ry, k, rot, capped, sp;
+  double sdmax, mnorm2;
 };
 
 __device__ __forceinline__ double xs_get(const PRef& U, const PRef& X, int kc, int xo, int i,
@@ -468,86 +481,88 @@ __device__ __forceinline__ double xs_get(const PRef& U, const PRef& X, int kc, i
   return pget(X, ii, j - kc);
 }
 
-// G (K x K) = S^T S where S rows are produced by xs_get; rows streamed in
-// chunks of 64 through sh.m
-__device__ void gram(TruncShared& sh, double (*G)[KM + 1], const PRef& U, const PRef& X, int kc,
-                     int xo, int rows, int K, double xsign) {
+// G (K x K) = S^T S where the rows of S are [F, tsign * T(placed at off)];
+// rows streamed through sh.m (zero-padded to 64 columns).
+__device__ void trunc_gram(TruncShared& sh, double (*G)[KM + 1], const PRef& F, const PRef& T,
+                           int kc, int off, int rows, int K, double tsign) {
   const int tid = threadIdx.x;
-  // each thread owns up to 16 entries (i, j) of the K x K result
-  double acc[16];
+  const int ti = tid % 16, tj = tid / 16;
+  double acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   for (int r0 = 0; r0 < rows; r0 += 64) {
     const int h = min(64, rows - r0);
-    for (int e = tid; e < 64 * K; e += NT) {
+    for (int e = tid; e < 64 * KM; e += NT) {
       int i = e % 64, j = e / 64;
       double v = 0.0;
-      if (i < h) {
-        v = xs_get(U, X, kc, xo, r0 + i, j);
-        if (j >= kc) v *= xsign;
+      if (i < h && j < K) {
+        v = xs_get(F, T, kc, off, r0 + i, j);
+        if (j >= kc) v *= tsign;
       }
       sh.m[i][j] = v;
     }
     __syncthreads();
+    for (int i = 0; i < h; ++i) {
+      double av[4], bv[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      int e = tid + q * NT;
-      if (e < K * K) {
-        int a = e % K, b = e / K;
-        double s = 0.0;
-        for (int i = 0; i < h; ++i) s += sh.m[i][a] * sh.m[i][b];
-        acc[q] += s;
-      }
+      for (int u = 0; u < 4; ++u) av[u] = sh.m[i][ti + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = sh.m[i][tj + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    int e = tid + q * NT;
-    if (e < K * K) G[e % K][e / K] = acc[q];
-  }
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[ti + 16 * u][tj + 16 * v] = acc[u][v];
   __syncthreads();
 }
 
-// In-place pivoted Cholesky of G (K x K): on exit rows 0..r-1 of G hold R
-// (in pivot order: R[i][j] for pivot-ordered column j), piv holds the
-// column order and r the numerical rank.
-__device__ void pchol(TruncShared& sh, double (*G)[KM + 1], int* piv, int K, int* r_out) {
+// In-place pivoted Cholesky of G (K x K).  On exit rows piv[0..r) of G hold
+// the rows of R in stacked-column order (entries of columns eliminated
+// before a row's own pivot are zero), pos[c] is the pivot position of
+// column c, and r the numerical rank.
+__device__ void trunc_pchol(TruncShared& sh, double (*G)[KM + 1], int* piv, int* pos, int K,
+                            int* r_out) {
   const int tid = threadIdx.x;
-  __shared__ double s_dmax;
-  __shared__ int s_p;
-  for (int j = tid; j < K; j += NT) piv[j] = j;
+  for (int j = tid; j < KM; j += NT) piv[j] = j;
   __syncthreads();
-  // permute physically: we keep G in original indexing and track piv
   double dmax0 = 0.0;
   for (int j = 0; j < K; ++j) dmax0 = fmax(dmax0, G[j][j]);
   int r = 0;
   for (int step = 0; step < K; ++step) {
-    if (tid == 0) {
-      double best = -1.0;
-      int bp = step;
-      for (int q = step; q < K; ++q) {
-        double d = G[piv[q]][piv[q]];
-        if (d > best) { best = d; bp = q; }
+    if (tid < 64) {
+      const int q = tid;
+      double v = (q >= step && q < K) ? G[piv[q]][piv[q]] : -1.0;
+      int ix = q;
+      for (int o = 32; o > 0; o >>= 1) {
+        double v2 = __shfl_xor(v, o);
+        int i2 = __shfl_xor(ix, o);
+        if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
       }
-      int t = piv[step];
-      piv[step] = piv[bp];
-      piv[bp] = t;
-      s_dmax = best;
-      s_p = piv[step];
+      if (tid == 0) {
+        int t = piv[step];
+        piv[step] = piv[ix];
+        piv[ix] = t;
+        sh.sdmax = v;
+        sh.sp = piv[step];
+      }
     }
     __syncthreads();
-    if (!(s_dmax > 1e-14 * dmax0) || dmax0 <= 0.0) break;
-    const int p = s_p;
-    const double rp = sqrt(s_dmax);
-    // row p of R over the remaining columns (pivot order q >= step)
-    __syncthreads();
+    if (!(sh.sdmax > 1e-14 * dmax0) || !(dmax0 > 0.0)) break;
+    const int p = sh.sp;
+    const double rp = sqrt(sh.sdmax);
     for (int q = step + tid; q < K; q += NT) {
       int c = piv[q];
       G[p][c] = (q == step) ? rp : G[p][c] / rp;
     }
     __syncthreads();
-    // Schur update of the remaining block
     const int rem = K - step - 1;
     for (int e = tid; e < rem * rem; e += NT) {
       int a = piv[step + 1 + e % rem], b = piv[step + 1 + e / rem];
@@ -556,26 +571,33 @@ __device__ void pchol(TruncShared& sh, double (*G)[KM + 1], int* piv, int K, int
     __syncthreads();
     ++r;
   }
+  for (int q = tid; q < K; q += NT) pos[piv[q]] = q;
+  __syncthreads();
+  for (int e = tid; e < r * K; e += NT) {
+    int i = e % r, c = e / r;
+    if (pos[c] < i) G[piv[i]][c] = 0.0;
+  }
   if (tid == 0) *r_out = r;
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
-  const Op& op = ops[blockIdx.x];
+#define LDS_TRUNC (sizeof(TruncShared))
+__device__ void d_trunc(const Op& op, char* smem) {
   const PRef U = op.p[0], V = op.p[1], X = op.p[2], Y = op.p[3];
   const int xo = op.i0, yo = op.i1;
   const int cap = op.i2 & 0xffff, fixed = op.i2 >> 16;
   const double eps = op.d0;
   const int m = U.rows, n = V.rows;
-  __shared__ TruncShared sh;
+  TruncShared& sh = *reinterpret_cast<TruncShared*>(smem);
   const int tid = threadIdx.x;
+  const int ti = tid % 16, tj = tid / 16;
   const int kc = pcols(U);
   const int kx = pcols(X);
   const int K = kc + kx;
-  if (tid == 0) { sh.kc = kc; sh.K = K; sh.capped = 0; }
+  if (tid == 0) sh.capped = 0;
   // 1. Gram matrices
-  gram(sh, sh.gx, U, X, kc, xo, m, K, -1.0);
-  gram(sh, sh.gy, V, Y, kc, yo, n, K, 1.0);
+  trunc_gram(sh, sh.gx, U, X, kc, xo, m, K, -1.0);
+  trunc_gram(sh, sh.gy, V, Y, kc, yo, n, K, 1.0);
   // 2. balancing
   for (int j = tid; j < K; j += NT) {
     double a = sh.gx[j][j], b = sh.gy[j][j];
@@ -589,51 +611,68 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
     sh.gy[a][b] = (da > 0.0 && db > 0.0) ? sh.gy[a][b] / (da * db) : 0.0;
   }
   __syncthreads();
-  // 3. pivoted Cholesky of both
-  pchol(sh, sh.gx, sh.px, K, &sh.rx);
-  pchol(sh, sh.gy, sh.py, K, &sh.ry);
+  // 3. pivoted Cholesky of both sides
+  trunc_pchol(sh, sh.gx, sh.px, sh.posx, K, &sh.rx);
+  trunc_pchol(sh, sh.gy, sh.py, sh.posy, K, &sh.ry);
   const int rx = sh.rx, ry = sh.ry;
-  // 4. M = R Pi_x^T Pi_y S^T: M[i][j] = sum_c R_i(c) S_j(c) over original
-  //    columns c, where R_i(c) = gx[px[i]][c] if c is at pivot position >= i
-  //    (zero otherwise).  Build position maps.
-  __shared__ int posx[KM], posy[KM];
-  for (int q = tid; q < K; q += NT) { posx[sh.px[q]] = q; posy[sh.py[q]] = q; }
-  __syncthreads();
-  for (int e = tid; e < rx * ry; e += NT) {
-    int i = e % rx, j = e / rx;
-    int pi = sh.px[i], pj = sh.py[j];
-    double s = 0.0;
-    for (int cidx = 0; cidx < K; ++cidx) {
-      if (posx[cidx] >= i && posy[cidx] >= j) s += sh.gx[pi][cidx] * sh.gy[pj][cidx];
+  // 4. M = R S^T (rows of R / S in pivot order), Z = I
+  {
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    int ra[4], sb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ra[u] = (ti + 16 * u < rx) ? sh.px[ti + 16 * u] : -1;
+      sb[u] = (tj + 16 * u < ry) ? sh.py[tj + 16 * u] : -1;
     }
-    sh.m[i][j] = s;
+    for (int c = 0; c < K; ++c) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = ra[u] >= 0 ? sh.gx[ra[u]][c] : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = sb[v] >= 0 ? sh.gy[sb[v]][c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sh.m[ti + 16 * u][tj + 16 * v] = acc[u][v];
   }
   for (int e = tid; e < KM * KM; e += NT) {
     int i = e % KM, j = e / KM;
     sh.z[i][j] = (i == j) ? 1.0 : 0.0;
   }
+  if (tid == 0) sh.mnorm2 = 0.0;
+  __syncthreads();
+  if (tid < 64) {
+    double s = 0.0;
+    for (int i = 0; i < rx; ++i)
+      if (tid < ry) s += sh.m[i][tid] * sh.m[i][tid];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (tid == 0) sh.mnorm2 = s;
+  }
   __syncthreads();
   // one-sided Jacobi on the columns of M (rx rows, ry columns): M Z = W Sig
   const int ncol = ry + (ry & 1);
-  if (ncol >= 2 && rx > 0) {
-    for (int sweep = 0; sweep < 30; ++sweep) {
+  const double tiny = 1e-30 * sh.mnorm2;
+  if (ncol >= 2 && rx > 0 && sh.mnorm2 > 0.0) {
+    for (int sweep = 0; sweep < 20; ++sweep) {
       if (tid == 0) sh.rot = 0;
       __syncthreads();
       for (int round = 0; round < ncol - 1; ++round) {
-        // round-robin pairing of ncol players: pair q = (a, b)
         const int npair = ncol / 2;
-        const int grp = 8;                 // threads per pair
+        const int grp = 8;
         const int q = tid / grp, l = tid % grp;
-        for (int qq = q; qq < npair; qq += NT / grp) {
-          int a, b;
-          {
-            // players 0..ncol-1, player ncol-1 fixed
-            int x0 = (qq == 0) ? ncol - 1 : (round + qq) % (ncol - 1);
-            int x1 = (round + ncol - 1 - qq) % (ncol - 1);
-            if (qq == 0) x1 = round % (ncol - 1);
-            a = min(x0, x1);
-            b = max(x0, x1);
-          }
+        if (q < npair) {
+          int x0 = (q == 0) ? ncol - 1 : (round + q) % (ncol - 1);
+          int x1 = (q == 0) ? round % (ncol - 1) : (round + ncol - 1 - q) % (ncol - 1);
+          const int a = min(x0, x1), b = max(x0, x1);
           double al = 0, be = 0, ga = 0;
           const bool valid = b < ry;
           if (valid) {
@@ -649,7 +688,7 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
             be += __shfl_xor(be, o);
             ga += __shfl_xor(ga, o);
           }
-          if (valid && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          if (valid && al > tiny && be > tiny && fabs(ga) > 1e-15 * sqrt(al * be)) {
             double zeta = (be - al) / (2.0 * ga);
             double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
@@ -672,30 +711,34 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
       __syncthreads();
     }
   }
-  // singular values and order
+  // singular values, descending order (stable), rank choice
   for (int j = tid; j < ry; j += NT) {
     double s = 0.0;
     for (int i = 0; i < rx; ++i) s += sh.m[i][j] * sh.m[i][j];
     sh.sig[j] = sqrt(s);
   }
   __syncthreads();
-  if (tid == 0) {
-    int nr = (rx > 0) ? ry : 0;
-    for (int j = 0; j < nr; ++j) sh.ord[j] = j;
-    for (int a = 1; a < nr; ++a) {     // insertion sort, descending, stable
-      int v = sh.ord[a];
-      int b = a - 1;
-      while (b >= 0 && sh.sig[sh.ord[b]] < sh.sig[v]) { sh.ord[b + 1] = sh.ord[b]; --b; }
-      sh.ord[b + 1] = v;
+  const int nr = rx > 0 ? ry : 0;
+  for (int j = tid; j < nr; j += NT) {
+    const double sj = sh.sig[j];
+    int c = 0;
+    for (int i = 0; i < nr; ++i) {
+      const double si = sh.sig[i];
+      c += (si > sj || (si == sj && i < j)) ? 1 : 0;
     }
-    int lim = min(nr, rx);
+    sh.ord[c] = j;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int lim = min(nr, rx);
     int k;
     if (fixed > 0) {
       k = min(fixed, lim);
     } else {
       double tot = 0.0;
       for (int j = 0; j < nr; ++j) tot += sh.sig[j] * sh.sig[j];
-      double thr = eps * eps * tot, tail = 0.0;
+      const double thr = eps * eps * tot;
+      double tail = 0.0;
       k = nr;
       for (int j = nr; j >= 0; --j) {
         if (tail <= thr) k = j;
@@ -703,7 +746,6 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
         if (j > 0) tail += sh.sig[sh.ord[j - 1]] * sh.sig[sh.ord[j - 1]];
       }
       k = min(k, lim);
-      sh.capped = 0;
       if (k > cap) {
         k = cap;
         sh.capped = 1;
@@ -713,43 +755,37 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
   }
   __syncthreads();
   const int k = sh.k;
-  // 6. per side: T = D^{+-1} Pi R11^{-1} (columns ord[0..k) of W Sig or Z),
-  //    by column-oriented back substitution in LDS; then stream the new
-  //    factor rows (in place: every row chunk is read before it is written).
-  // tt is indexed by stacked column: the unknown of pivot position i lives
-  // in row pv[i]; columns beyond the numerical rank stay zero.
-  __shared__ double tt[KM][33];
+  // 6. per side: back substitution into tt (stacked-column order), then
+  //    stream the new factor rows with 4 x 2 register blocks per thread
   for (int side = 0; side < 2; ++side) {
     const int r = side == 0 ? rx : ry;
     double (*G)[KM + 1] = side == 0 ? sh.gx : sh.gy;
     const int* pv = side == 0 ? sh.px : sh.py;
     double (*src)[KM + 1] = side == 0 ? sh.m : sh.z;
-    for (int e = tid; e < K * k; e += NT) {
-      int c2 = e % K, c = e / K;
-      tt[c2][c] = 0.0;
+    for (int e = tid; e < KM * 32; e += NT) {
+      int c2 = e % KM, c = e / KM;
+      sh.tt[c2][c] = 0.0;
     }
     __syncthreads();
     for (int e = tid; e < r * k; e += NT) {
       int i = e % r, c = e / r;
-      tt[pv[i]][c] = src[i][sh.ord[c]];
+      sh.tt[pv[i]][c] = src[i][sh.ord[c]];
     }
     __syncthreads();
     for (int i = r - 1; i >= 0; --i) {
       const int pi = pv[i];
-      const double d = G[pi][pi];
-      if (tid < k) tt[pi][tid] /= d;
+      if (tid < k) sh.tt[pi][tid] /= G[pi][pi];
       __syncthreads();
       for (int e = tid; e < i * k; e += NT) {
         int j = e % i, c = e / i;
-        tt[pv[j]][c] -= G[pv[j]][pi] * tt[pi][c];
+        sh.tt[pv[j]][c] -= G[pv[j]][pi] * sh.tt[pi][c];
       }
       __syncthreads();
     }
-    // balancing scale of the stacked columns
     for (int e = tid; e < K * k; e += NT) {
       int c2 = e % K, c = e / K;
       double dd = sh.dsc[c2];
-      tt[c2][c] = side == 0 ? tt[c2][c] * dd : (dd > 0.0 ? tt[c2][c] / dd : 0.0);
+      sh.tt[c2][c] = side == 0 ? sh.tt[c2][c] * dd : (dd > 0.0 ? sh.tt[c2][c] / dd : 0.0);
     }
     __syncthreads();
     const PRef& F = side == 0 ? U : V;
@@ -769,12 +805,28 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
         sh.m[i][j] = v;
       }
       __syncthreads();
-      for (int e = tid; e < h * k; e += NT) {
-        int i = e % h, j = e / h;
-        double s = 0.0;
-        for (int c2 = 0; c2 < K; ++c2) s += sh.m[i][c2] * tt[c2][j];
-        pset(F, r0 + i, j, s);
+      double o[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) o[u][0] = o[u][1] = 0.0;
+      for (int c2 = 0; c2 < K; ++c2) {
+        double av[4], bv[2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = sh.m[ti + 16 * u][c2];
+        bv[0] = sh.tt[c2][tj];
+        bv[1] = sh.tt[c2][tj + 16];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          o[u][0] += av[u] * bv[0];
+          o[u][1] += av[u] * bv[1];
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          int i = ti + 16 * u, j = tj + 16 * v;
+          if (i < h && j < k) pset(F, r0 + i, j, o[u][v]);
+        }
       __syncthreads();
     }
   }
@@ -782,7 +834,7 @@ __global__ void __launch_bounds__(NT) k_trunc(const Op* __restrict__ ops) {
   const double es = U.dt == DT_F64 ? 8.0 : 4.0;
   const double flops = 2.0 * (m + n) * K * K - 4.0 * K * K * K / 3.0 + 2.0 * K * K * K +
                        21.0 * K * K * K + 2.0 * (m + n) * K * k;
-  put_cost(op, flops, es * (double)(m + n) * (K + k), (double)sh.capped, (double)k);
+  put_cost(op, flops, es * (double)(m + n) * (K + k), (double)sh.capped, (double)k, (double)K);
 }
 
 // ---------------------------------------------------------------- matvec
@@ -925,24 +977,114 @@ __global__ void k_set_int(int32_t* p, int v) {
 }
 
 // ---------------------------------------------------------------- launchers
-static hipError_t launch_ops(int type, const Op* ops, int count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  dim3 g(count), b(NT);
-  switch (type) {
-    case OP_GETRF: hipLaunchKernelGGL(k_getrf, g, b, 0, s, ops); break;
+// One workgroup per descriptor; the descriptors of a launch may mix op
+// types (one launch per wave of the schedule).  Each op type carves its
+// tiles out of the same dynamic LDS buffer, so a launch requests the
+// largest footprint among the types it contains.
+__global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
+  extern __shared__ __align__(16) char smem[];
+  const Op& op = ops[blockIdx.x];
+  start_tick(op);
+  switch (op.type) {
+    case OP_GETRF: d_getrf(op, smem); break;
     case OP_TRSM_L:
     case OP_TRSM_UT:
-    case OP_TRSM_U: hipLaunchKernelGGL(k_trsm, g, b, 0, s, ops); break;
-    case OP_PGEMM: hipLaunchKernelGGL(k_pgemm, g, b, 0, s, ops); break;
-    case OP_TRUNC: hipLaunchKernelGGL(k_trunc, g, b, 0, s, ops); break;
-    case OP_ADDD: hipLaunchKernelGGL(k_addd, g, b, 0, s, ops); break;
-    case OP_ZERO: hipLaunchKernelGGL(k_zero, g, b, 0, s, ops); break;
-    default: return hipErrorInvalidValue;
+    case OP_TRSM_U: d_trsm(op, smem); break;
+    case OP_PGEMM: d_pgemm(op, smem); break;
+    case OP_TRUNC: d_trunc(op, smem); break;
+    case OP_ADDD: d_addd(op, smem); break;
+    case OP_ZERO: d_zero(op); break;
+    default: break;
   }
+}
+
+static size_t lds_bytes(int type) {
+  switch (type) {
+    case OP_GETRF: return LDS_GETRF;
+    case OP_TRSM_L:
+    case OP_TRSM_UT:
+    case OP_TRSM_U: return LDS_TRSM;
+    case OP_PGEMM: return LDS_PGEMM;
+    case OP_TRUNC: return LDS_TRUNC;
+    case OP_ADDD: return LDS_ADDD;
+    default: return 0;
+  }
+}
+
+static hipError_t launch_wave(const Op* ops, int count, size_t lds, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_wave),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)LDS_TRUNC);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_wave, dim3(count), dim3(NT), lds, s, ops);
   return hipGetLastError();
 }
 
+static hipError_t launch_ops(int type, const Op* ops, int count, hipStream_t s) {
+  if (type < 0 || type >= OP_NTYPES) return hipErrorInvalidValue;
+  return launch_wave(ops, count, lds_bytes(type), s);
+}
+
 }  // namespace hlu
+
+extern "C" size_t hlu_lds_bytes(int type) { return hlu::lds_bytes(type); }
+
+// A graph that replays a schedule: a kernel node resetting the status word
+// (when given), then one k_wave node per wave, each depending on the
+// previous one.  Built explicitly (no stream capture).
+extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* starts,
+                                           const int* counts, const size_t* lds, int nwaves,
+                                           int32_t* status, hipGraphExec_t* out) {
+  *out = nullptr;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hlu::k_wave),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sizeof(hlu::TruncShared));
+  if (e != hipSuccess) return e;
+  hipGraph_t g;
+  e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr;
+  if (status) {
+    hipKernelNodeParams p = {};
+    int zero = 0;
+    void* args[] = {&status, &zero};
+    p.func = reinterpret_cast<void*>(&hlu::k_set_int);
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(64);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    e = hipGraphAddKernelNode(&prev, g, nullptr, 0, &p);
+    if (e != hipSuccess) { hipGraphDestroy(g); return e; }
+  }
+  for (int w = 0; w < nwaves && e == hipSuccess; ++w) {
+    if (counts[w] <= 0) continue;
+    const hlu::Op* ops = reinterpret_cast<const hlu::Op*>(ops_base) + starts[w];
+    hipKernelNodeParams p = {};
+    void* args[] = {&ops};
+    p.func = reinterpret_cast<void*>(&hlu::k_wave);
+    p.gridDim = dim3(counts[w]);
+    p.blockDim = dim3(NT);
+    p.sharedMemBytes = (unsigned)lds[w];
+    p.kernelParams = args;
+    p.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+    prev = node;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
+
+extern "C" hipError_t hlu_launch_wave(const void* ops, int count, size_t lds, hipStream_t s) {
+  return hlu::launch_wave(reinterpret_cast<const hlu::Op*>(ops), count, lds, s);
+}
 
 extern "C" hipError_t hlu_launch_ops(int type, const void* ops, int count, hipStream_t s) {
   return hlu::launch_ops(type, reinterpret_cast<const hlu::Op*>(ops), count, s);

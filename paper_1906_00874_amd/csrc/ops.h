@@ -44,6 +44,12 @@ enum OpType : int32_t {
   OP_NTYPES = 8
 };
 
+// Bytes of the per-op record a kernel writes at Op::cost: doubles {model
+// flops, algorithmic bytes, rank-capacity hit, rank, start tick, end tick,
+// stack width, unused}.
+constexpr int kCostRecBytes = 64;
+constexpr int kCostRecDoubles = kCostRecBytes / 8;
+
 struct Op {
   int32_t type;
   int32_t i0, i1, i2;

@@ -500,7 +500,7 @@ class Builder {
     int w = schedule(acc);
     if (want_cost) {
       op.cost = cost_cur;
-      cost_cur += 32;
+      cost_cur += kCostRecBytes;
     } else {
       op.cost = 0;
     }
@@ -872,13 +872,18 @@ class Builder {
     });
     S.ops.resize(n);
     S.batches.clear();
+    S.waves_list.clear();
     S.waves = 0;
     for (int k = 0; k < n; ++k) {
       S.ops[k] = ops[idx[k]];
       int w = wave[idx[k]], t = ops[idx[k]].type;
       if (S.batches.empty() || S.batches.back().wave != w || S.batches.back().type != t)
-        S.batches.push_back(Batch{w, t, k, 0});
+        S.batches.push_back(Batch{w, t, k, 0, 1u << t});
       S.batches.back().count++;
+      if (S.waves_list.empty() || S.waves_list.back().wave != w)
+        S.waves_list.push_back(Batch{w, -1, k, 0, 0u});
+      S.waves_list.back().count++;
+      S.waves_list.back().mask |= 1u << t;
       S.waves = std::max(S.waves, w + 1);
     }
   }
@@ -1131,7 +1136,7 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     p.off_cost = cur;
     // patch op cost records to absolute offsets
     for (auto& op : p.fsched.ops) op.cost += p.off_cost;
-    cur = align256(cur + (uint64_t)p.fsched.ops.size() * 32);
+    cur = align256(cur + (uint64_t)p.fsched.ops.size() * kCostRecBytes);
   }
   {
     Builder B(p, p.ssched);

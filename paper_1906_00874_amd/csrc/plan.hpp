@@ -54,11 +54,13 @@ struct LBlock {
 
 struct Batch {
   int wave, type, start, count;
+  uint32_t mask;           // op types present (bit per type)
 };
 
 struct Schedule {
   std::vector<Op> ops;     // sorted by (wave, type); pointers are byte offsets
-  std::vector<Batch> batches;
+  std::vector<Batch> batches;      // one per (wave, type)
+  std::vector<Batch> waves_list;   // one per wave (all types)
   int waves = 0;
 };
 

@@ -244,6 +244,32 @@ def test_solve_argument_and_state_errors(P):
     h.sync()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replays_match_eager(P, prec):
+    """The graph of the schedule replayed several times (with eager work and
+    synchronisations in between) gives bitwise the eager factors and solve."""
+    import torch
+    xyz, area, h = _hlu(P, 3, 32, eps=1e-6, precision=prec, max_nrhs=4)
+    b = torch.tensor(rhs_normal(5, h.n, 3), device="cuda")
+    h.set_graph(False)
+    h.factor()
+    h.sync()
+    L0, U0 = h.export_factors()
+    x0 = h.solve(b).cpu().numpy()
+    h.set_graph(True)
+    for rep in range(3):
+        h.reset()
+        junk = torch.randn(1000, device="cuda").sum()       # eager work between replays
+        torch.cuda.synchronize()
+        h.factor()
+        h.sync()
+        L, U = h.export_factors()
+        x = h.solve(b).cpu().numpy()
+        assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
+        assert np.array_equal(x, x0), rep
+        del junk
+
+
 def test_refinement_not_converged_is_reported(P):
     """A very loose factorisation with one refinement step cannot reach the
     target: the solve reports NOT_CONVERGED instead of a silent answer."""
