@@ -128,6 +128,15 @@ hlu_status hlu_factor(hlu_handle h, void* stream);
  * order. */
 hlu_status hlu_set_graph(hlu_handle h, int enable);
 
+/* Executor of hlu_factor.  0 (the default): one launch per wave of the
+ * static schedule.  1: one persistent launch that runs each op as soon as
+ * its own predecessors in the dependency graph have finished (a device-side
+ * dataflow executor: the analogue of nested tasks with weak dependencies and
+ * early release, Sec. 4.3).  Both give bitwise identical factors.  A wait in
+ * the dataflow executor that exceeds 20 s raises an error flag that makes
+ * every workgroup exit; hlu_sync then returns HLU_ERR_DEVICE. */
+hlu_status hlu_set_executor(hlu_handle h, int mode);
+
 /* hlu_factor with a HIP event pair around every launch on `stream`;
  * returns the summed launch durations (ms) and launch counts per op type
  * (arrays of 8).  Synchronises the stream; used for roofline figures. */

@@ -61,6 +61,7 @@ _sig = {
     "hlu_factor_batched": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
     "hlu_factor_profile": (C.c_int, [_P, _P, _P, _P]),
     "hlu_set_graph": (C.c_int, [_P, C.c_int]),
+    "hlu_set_executor": (C.c_int, [_P, C.c_int]),
     "hlu_factor_records": (C.c_int, [_P, _P, _P]),
     "hlu_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
@@ -173,6 +174,10 @@ class HLU:
 
     def set_graph(self, enable):
         _check(lib.hlu_set_graph(self.h, int(bool(enable))))
+
+    def set_executor(self, mode):
+        """0: one launch per wave; 1: persistent dataflow executor."""
+        _check(lib.hlu_set_executor(self.h, int(mode)))
 
     def reset(self, stream=None):
         _check(lib.hlu_reset(self.h, _stream(stream)))

@@ -28,6 +28,15 @@ extern "C" size_t hlu_lds_bytes(int type);
 extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* starts,
                                            const int* counts, const size_t* lds, int nwaves,
                                            int32_t* status, hipGraphExec_t* out);
+extern "C" hipError_t hlu_launch_dataflow(const void* ops, const int* succ_off, const int* succ,
+                                          const int* indeg0, int* indeg, int* queue,
+                                          const int* ready0, int nready, int* ctrl, int n,
+                                          int workers, long long timeout, hipStream_t s);
+extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off, const int* succ,
+                                         const int* indeg0, int* indeg, int* queue,
+                                         const int* ready0, int nready, int* ctrl, int n,
+                                         int workers, long long timeout, int32_t* status,
+                                         hipGraphExec_t* out);
 
 namespace {
 
@@ -121,16 +130,24 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
         break;
       }
       case hlu::OP_TRUNC: {
-        const hlu::PRef &U = o.p[0], &V = o.p[1], &X = o.p[2], &Y = o.p[3];
-        for (int q = 0; q < 4; ++q)
+        const hlu::PRef &U = o.p[0], &V = o.p[1];
+        for (int q = 0; q < 2; ++q)
           if (!panel_ok(o.p[q], T, why)) return bad(why.c_str());
         int cap = o.i2 & 0xffff;
         if (!U.rankp || U.rankp != V.rankp || U.cols != cap || V.cols != cap || cap > 32)
           return bad("truncation target");
-        if (o.i0 < 0 || o.i1 < 0 || o.i0 + X.rows > U.rows || o.i1 + Y.rows > V.rows)
-          return bad("truncation term placement");
-        if (X.cols != Y.cols) return bad("truncation term widths");
-        if (cap + X.cols > 64) return bad("stack wider than 64");
+        if (o.i1 < 1 || o.i1 > 16 || o.i0 < 0 || (size_t)(o.i0 + o.i1) > sc.terms.size())
+          return bad("truncation term list");
+        if (o.p[2].ptr != p.off_terms_f) return bad("truncation term table");
+        for (int t = o.i0; t < o.i0 + o.i1; ++t) {
+          const hlu::Term& tm = sc.terms[t];
+          if (!panel_ok(tm.X, T, why) || !panel_ok(tm.Y, T, why)) return bad(why.c_str());
+          if (tm.xo < 0 || tm.yo < 0 || tm.xo + tm.X.rows > U.rows || tm.yo + tm.Y.rows > V.rows)
+            return bad("truncation term placement");
+          if (tm.X.cols != tm.Y.cols) return bad("truncation term widths");
+          if (cap + tm.X.cols > 64) return bad("term wider than the stack allows");
+          if (tm.X.rankp != tm.Y.rankp) return bad("truncation term rank pointers differ");
+        }
         break;
       }
       case hlu::OP_ADDD: {
@@ -166,12 +183,15 @@ struct hlu_handle_s {
   bool not_converged = false;
   hlu_params params;
   bool use_graph = true;
+  int executor = 0;                   // 0: waves, 1: dataflow
   hipGraphExec_t graph_f = nullptr;   // factor schedule (with status reset)
   hipGraphExec_t graph_s = nullptr;   // solve schedule
+  hipGraphExec_t graph_df = nullptr;  // factor by the dataflow executor
   void drop_graphs() {
     if (graph_f) hipGraphExecDestroy(graph_f);
     if (graph_s) hipGraphExecDestroy(graph_s);
-    graph_f = graph_s = nullptr;
+    if (graph_df) hipGraphExecDestroy(graph_df);
+    graph_f = graph_s = graph_df = nullptr;
   }
   ~hlu_handle_s() { drop_graphs(); }
 };
@@ -245,8 +265,29 @@ hlu_status hlu_validate(hlu_handle h) {
   std::string why;
   if (!validate(h->plan, h->plan.fsched, why)) return fail(HLU_ERR_ARG, "factor schedule: " + why);
   if (!validate(h->plan, h->plan.ssched, why)) return fail(HLU_ERR_ARG, "solve schedule: " + why);
-  // matvec tables
   const hlu::Plan& p = h->plan;
+  // dependency graph: successors lie later in schedule order (acyclic), and
+  // every in-degree equals the number of edges pointing at the op
+  {
+    const hlu::Schedule& sc = p.fsched;
+    const size_t N = sc.ops.size();
+    if (sc.succ_off.size() != N + 1 || sc.indeg0.size() != N)
+      return fail(HLU_ERR_ARG, "dependency graph size");
+    std::vector<int32_t> cnt(N, 0);
+    for (size_t i = 0; i < N; ++i)
+      for (int32_t e = sc.succ_off[i]; e < sc.succ_off[i + 1]; ++e) {
+        int32_t s = sc.succ[e];
+        if (s <= (int64_t)i || s >= (int64_t)N) return fail(HLU_ERR_ARG, "dependency edge order");
+        cnt[s]++;
+      }
+    size_t nready = 0;
+    for (size_t i = 0; i < N; ++i) {
+      if (cnt[i] != sc.indeg0[i]) return fail(HLU_ERR_ARG, "dependency in-degree");
+      nready += sc.indeg0[i] == 0;
+    }
+    if (nready != sc.ready0.size()) return fail(HLU_ERR_ARG, "initial ready list");
+  }
+  // matvec tables
   for (const auto& e : p.mv_lr) {
     if (e.k > 0 && (e.U < 512 || e.U + (uint64_t)e.m * e.k * 8 > p.total ||
                     e.V + (uint64_t)e.n * e.k * 8 > p.total ||
@@ -305,6 +346,29 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
   std::vector<hlu::Op> f = p.fsched.ops, s = p.ssched.ops;
   for (auto& op : f) relocate(op, base);
   for (auto& op : s) relocate(op, base);
+  std::vector<hlu::Term> tf = p.fsched.terms;
+  for (auto& t : tf) {
+    relocate(t.X, base);
+    relocate(t.Y, base);
+  }
+  if (!tf.empty())
+    HIPCHK(hipMemcpy((char*)dev_ptr + p.off_terms_f, tf.data(), tf.size() * sizeof(hlu::Term),
+                     hipMemcpyHostToDevice));
+  {
+    const hlu::Schedule& sc = p.fsched;
+    char* d = (char*)dev_ptr;
+    HIPCHK(hipMemcpy(d + p.off_df_succ_off, sc.succ_off.data(), sc.succ_off.size() * 4,
+                     hipMemcpyHostToDevice));
+    if (!sc.succ.empty())
+      HIPCHK(hipMemcpy(d + p.off_df_succ, sc.succ.data(), sc.succ.size() * 4, hipMemcpyHostToDevice));
+    if (!sc.indeg0.empty())
+      HIPCHK(hipMemcpy(d + p.off_df_indeg0, sc.indeg0.data(), sc.indeg0.size() * 4,
+                       hipMemcpyHostToDevice));
+    if (!sc.ready0.empty())
+      HIPCHK(hipMemcpy(d + p.off_df_ready0, sc.ready0.data(), sc.ready0.size() * 4,
+                       hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(d + p.off_df_ctrl, 0, 256));
+  }
   std::vector<hlu::MvLR> lr = p.mv_lr;
   for (auto& e : lr) {
     if (e.U) e.U += base;
@@ -428,15 +492,68 @@ static hlu_status run_schedule(hlu_handle h, const hlu::Schedule& sc, uint64_t o
   return HLU_OK;
 }
 
+// device facts for the dataflow executor: workgroups (one per compute
+// unit: the largest op type's LDS allows one resident workgroup) and the
+// wall-clock ticks per second
+static hlu_status device_facts(int* cus, long long* ticks_per_s) {
+  int dev = 0, cu = 0, rate_khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+  *cus = cu > 0 ? cu : 1;
+  *ticks_per_s = rate_khz > 0 ? (long long)rate_khz * 1000 : 100000000LL;
+  return HLU_OK;
+}
+
+static hlu_status run_dataflow(hlu_handle h, hipStream_t s) {
+  hlu::Plan& p = h->plan;
+  const hlu::Schedule& sc = p.fsched;
+  char* b = h->base;
+  int cus = 0;
+  long long tps = 0;
+  hlu_status st = device_facts(&cus, &tps);
+  if (st != HLU_OK) return st;
+  const long long timeout = 20 * tps;   // no single wait may exceed 20 s
+  int32_t* status = (int32_t*)(b + p.off_status);
+  const int* succ_off = (const int*)(b + p.off_df_succ_off);
+  const int* succ = (const int*)(b + p.off_df_succ);
+  const int* indeg0 = (const int*)(b + p.off_df_indeg0);
+  int* indeg = (int*)(b + p.off_df_indeg);
+  int* queue = (int*)(b + p.off_df_queue);
+  const int* ready0 = (const int*)(b + p.off_df_ready0);
+  int* ctrl = (int*)(b + p.off_df_ctrl);
+  const int n = (int)sc.ops.size(), nready = (int)sc.ready0.size();
+  if (h->use_graph) {
+    if (!h->graph_df)
+      HIPCHK(hlu_build_df_graph(b + p.off_ops_f, succ_off, succ, indeg0, indeg, queue, ready0,
+                                nready, ctrl, n, cus, timeout, status, &h->graph_df));
+    HIPCHK(hipGraphLaunch(h->graph_df, s));
+    return HLU_OK;
+  }
+  HIPCHK(hlu_launch_set_int(status, 0, s));
+  HIPCHK(hlu_launch_dataflow(b + p.off_ops_f, succ_off, succ, indeg0, indeg, queue, ready0, nready,
+                             ctrl, n, cus, timeout, s));
+  return HLU_OK;
+}
+
 hlu_status hlu_factor(hlu_handle h, void* stream) {
   if (!h) return fail(HLU_ERR_ARG, "NULL handle");
   if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
   if (h->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
   hipStream_t s = (hipStream_t)stream;
-  hlu_status st = run_schedule(h, h->plan.fsched, h->plan.off_ops_f, s,
-                               (int32_t*)(h->base + h->plan.off_status), &h->graph_f);
+  hlu_status st = h->executor == 1
+                      ? run_dataflow(h, s)
+                      : run_schedule(h, h->plan.fsched, h->plan.off_ops_f, s,
+                                     (int32_t*)(h->base + h->plan.off_status), &h->graph_f);
   if (st != HLU_OK) return st;
   h->factored = true;
+  return HLU_OK;
+}
+
+hlu_status hlu_set_executor(hlu_handle h, int mode) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (mode != 0 && mode != 1) return fail(HLU_ERR_ARG, "executor must be 0 (waves) or 1 (dataflow)");
+  h->executor = mode;
   return HLU_OK;
 }
 
@@ -590,10 +707,12 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
   HIPCHK(hipStreamSynchronize(s));
   hlu_info inf;
   std::memset(&inf, 0, sizeof(inf));
+  int32_t df_error = 0;
   if (h->base) {
     int32_t st = 0;
     HIPCHK(hipMemcpy(&st, h->base + h->plan.off_status, 4, hipMemcpyDeviceToHost));
     if (st > 0) inf.info = h->plan.perm[st - 1] + 1;
+    HIPCHK(hipMemcpy(&df_error, h->base + h->plan.off_df_ctrl + 8, 4, hipMemcpyDeviceToHost));
   }
   inf.iters = h->iters;
   for (int i = 0; i < 16; ++i) inf.eta_hist[i] = h->eta_hist[i];
@@ -615,6 +734,9 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
     inf.max_rank = mr;
   }
   if (out) *out = inf;
+  if (df_error)
+    return fail(HLU_ERR_DEVICE, df_error == 2 ? "dataflow executor: queue overflow"
+                                              : "dataflow executor: a wait exceeded its time limit");
   if (inf.info) return fail(HLU_ERR_SINGULAR, "zero pivot");
   if (h->not_converged) return fail(HLU_ERR_NOT_CONVERGED, "refinement did not converge");
   return HLU_OK;
@@ -786,13 +908,30 @@ hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev, con
                             int fixed_rank, void* stream) {
   if (!U_dev || !V_dev || !rank_dev || (kx > 0 && (!X_dev || !Y_dev)))
     return fail(HLU_ERR_ARG, "NULL argument");
-  if (m < 1 || n < 1 || kc < 0 || kx < 0 || kc > cap || kc + kx > 64 || cap < 1 || cap > 32 ||
-      fixed_rank < 0 || fixed_rank > cap)
+  const int w = 64 - cap;   // widest term the stack admits
+  if (m < 1 || n < 1 || kc < 0 || kx < 0 || kc > cap || cap < 1 || cap > 32 ||
+      kx > 16 * w || fixed_rank < 0 || fixed_rank > cap)
     return fail(HLU_ERR_ARG, "sizes out of range");
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hlu_launch_set_int(rank_dev, kc, s));
-  std::vector<hlu::Op> ops(1);
-  hlu::Op& o = ops[0];
+  // the update is split into terms of at most w columns; the kernel adds
+  // them in passes whose stacked width stays <= 64
+  std::vector<hlu::Term> terms;
+  for (int c0 = 0; c0 < kx; c0 += w) {
+    hlu::Term t;
+    std::memset(&t, 0, sizeof(t));
+    int cw = std::min(w, kx - c0);
+    t.X.ptr = (uint64_t)(X_dev + (size_t)c0 * m);
+    t.X.ld = m;
+    t.X.rows = m;
+    t.X.cols = cw;
+    t.Y.ptr = (uint64_t)(Y_dev + (size_t)c0 * n);
+    t.Y.ld = n;
+    t.Y.rows = n;
+    t.Y.cols = cw;
+    terms.push_back(t);
+  }
+  hlu::Op o;
   std::memset(&o, 0, sizeof(o));
   o.type = hlu::OP_TRUNC;
   o.p[0].ptr = (uint64_t)U_dev;
@@ -805,17 +944,24 @@ hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev, con
   o.p[1].ld = n;
   o.p[1].rows = n;
   o.p[1].cols = cap;
-  o.p[2].ptr = (uint64_t)X_dev;
-  o.p[2].ld = m;
-  o.p[2].rows = m;
-  o.p[2].cols = kx;
-  o.p[3].ptr = (uint64_t)Y_dev;
-  o.p[3].ld = n;
-  o.p[3].rows = n;
-  o.p[3].cols = kx;
+  o.i0 = 0;
+  o.i1 = (int)terms.size();
   o.i2 = cap | (fixed_rank << 16);
   o.d0 = eps;
-  return run_single(ops, hlu::OP_TRUNC, s);
+  if (terms.empty()) return HLU_OK;
+  void* d = nullptr;
+  const size_t bytes = sizeof(hlu::Op) + terms.size() * sizeof(hlu::Term);
+  HIPCHK(hipMalloc(&d, bytes));
+  o.p[2].ptr = (uint64_t)((char*)d + sizeof(hlu::Op));
+  hipError_t e = hipMemcpyAsync(d, &o, sizeof(o), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((char*)d + sizeof(hlu::Op), terms.data(), terms.size() * sizeof(hlu::Term),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hlu_launch_ops(hlu::OP_TRUNC, d, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(d);
+  if (e != hipSuccess) return fail(HLU_ERR_DEVICE, hipGetErrorString(e));
+  return HLU_OK;
 }
 
 }  // extern "C"

@@ -13,8 +13,12 @@ namespace hlu {
 
 #define NT 256
 
+// live column count: ranks change while a schedule runs, so they are read
+// with a device-scope atomic load (never through a cached scalar load)
 __device__ __forceinline__ int pcols(const PRef& r) {
-  return r.rankp ? *reinterpret_cast<const int32_t*>(r.rankp) : r.cols;
+  return r.rankp ? __hip_atomic_load(reinterpret_cast<int32_t*>(r.rankp), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT)
+                 : r.cols;
 }
 
 __device__ __forceinline__ double pget(const PRef& r, int i, int j) {
@@ -441,52 +445,74 @@ __device__ void d_zero(const Op& op) {
     int i = e % Z.rows, j = e / Z.rows;
     pset(Z, i, j, 0.0);
   }
+  put_cost(op, 0.0, (Z.dt == DT_F64 ? 8.0 : 4.0) * tot);
 }
 
 // ---------------------------------------------------------------- truncation
-// C = U V^T (rank kc) and the term X Y^T (kx columns, X at row xo of C,
-// Y at row yo) are stacked as Xs = [U, -X], Ys = [V, Y] (K = kc + kx <= 64).
-//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys (FP64, rows streamed in
-//      chunks of 64, 4x4 register blocks per thread);
+// C = U V^T (rank kc) minus a list of low-rank terms X_t Y_t^T (X_t placed at
+// row xo_t of C, Y_t at row yo_t, zero elsewhere).  The terms are taken in
+// passes whose stacked width K = kc + sum k_t stays <= 64 (live ranks read at
+// run time); every pass replaces C by the best approximation of
+// [U, -X_a, ..., -X_b] [V, Y_a, ..., Y_b]^T:
+//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys in FP64 (rows streamed in
+//      chunks of 64, only the K live columns, 4x4 blocks per thread over
+//      row groups);
 //   2. column balancing so that |x_j| = |y_j|;
-//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T, Gy = Pi_y S^T S Pi_y^T
-//      (pivot chosen by a wavefront argmax), stopping at pivots below 1e-14
-//      of the largest diagonal (rank revealing);
-//   4. M = R S^T over the stacked columns and its one-sided Jacobi SVD
-//      M = W Sig Z^T (round-robin pairs, 8 lanes per pair);
+//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T, Gy = Pi_y S^T S Pi_y^T,
+//      stopping at pivots below 1e-14 of the largest diagonal;
+//   4. M = R S^T and its one-sided Jacobi SVD M = W Sig Z^T;
 //   5. rank choice (fixed, or the smallest k with discarded Frobenius norm
 //      <= eps |Sig|, capped);
-//   6. U := Xs Tx, V := Ys Ty with Tx = D Pi_x R11^{-1} W_k Sig_k and
-//      Ty = D^{-1} Pi_y S11^{-1} Z_k, streamed row chunk by row chunk in
-//      place (each chunk is read before it is written).
+//   6. Tx = D Pi_x R11^{-1} W_k Sig_k, Ty = D^{-1} Pi_y S11^{-1} Z_k;
+//   7. U := Xs Tx, V := Ys Ty streamed in place (each row chunk is read
+//      before it is written).
 #define KM 64
+#define TMAX 16
 struct TruncShared {
-  double gx[KM][KM + 1];
-  double gy[KM][KM + 1];
-  double m[KM][KM + 1];     // chunk buffer / M / W Sig
-  double z[KM][KM + 1];     // Z
-  double tt[KM][33];        // Tx / Ty in stacked-column order
+  double gx[KM][KM + 1];    // Gx -> R -> (after step 6) Ty
+  double gy[KM][KM + 1];    // Gy -> S
+  double m[KM][KM + 1];     // row chunks / M -> W Sig / row chunks
+  double z[KM][KM + 1];     // Gram partials / Z
+  double tt[KM][33];        // Tx
   double dsc[KM];
   double sig[KM];
+  Term tm[TMAX];            // terms of the current pass
   int px[KM], py[KM], posx[KM], posy[KM], ord[KM];
-  int rx, ry, k, rot, capped, sp;
-  double sdmax, mnorm2;
+  int8_t colt[KM], colj[KM];   // stacked column -> (term, column in term)
+  int rx, ry, k, rot, capped, sp, K, kc, tb, te;
+  double sdmax, mnorm;
 };
 
-__device__ __forceinline__ double xs_get(const PRef& U, const PRef& X, int kc, int xo, int i,
-                                         int j) {
-  if (j < kc) return pget(U, i, j);
-  int ii = i - xo;
-  if (ii < 0 || ii >= X.rows) return 0.0;
-  return pget(X, ii, j - kc);
+// element (i, j) of the stacked panel of one side (0: [U, -X..], 1: [V, Y..])
+__device__ __forceinline__ double stk(const TruncShared& sh, const PRef& F, int side, int i,
+                                      int j) {
+  if (j < sh.kc) return pget(F, i, j);
+  const Term& t = sh.tm[sh.colt[j]];
+  const int ii = i - (side ? t.yo : t.xo);
+  const PRef& T = side ? t.Y : t.X;
+  if (ii < 0 || ii >= T.rows) return 0.0;
+  const double v = pget(T, ii, sh.colj[j]);
+  return side ? v : -v;
 }
 
-// G (K x K) = S^T S where the rows of S are [F, tsign * T(placed at off)];
-// rows streamed through sh.m (zero-padded to 64 columns).
-__device__ void trunc_gram(TruncShared& sh, double (*G)[KM + 1], const PRef& F, const PRef& T,
-                           int kc, int off, int rows, int K, double tsign) {
+__device__ __forceinline__ void trunc_load_chunk(TruncShared& sh, const PRef& F, int side, int r0,
+                                                 int h, int K) {
+  for (int e = threadIdx.x; e < 64 * K; e += NT) {
+    int i = e % 64, j = e / 64;
+    sh.m[i][j] = i < h ? stk(sh, F, side, r0 + i, j) : 0.0;
+  }
+}
+
+// G (K x K) = S^T S of the stacked panel of one side
+__device__ void trunc_gram(TruncShared& sh, double (*G)[KM + 1], const PRef& F, int side,
+                           int rows, int K) {
   const int tid = threadIdx.x;
-  const int ti = tid % 16, tj = tid / 16;
+  const int B = (K + 3) / 4;
+  const int BB = B * B;
+  const int NG = BB > 0 ? min(NT / BB, 16) : 1;
+  const int grp = BB > 0 ? tid / BB : 0, blk = BB > 0 ? tid % BB : 0;
+  const bool act = BB > 0 && grp < NG;
+  const int bi = act ? blk / B : 0, bj = act ? blk % B : 0;
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -494,33 +520,40 @@ __device__ void trunc_gram(TruncShared& sh, double (*G)[KM + 1], const PRef& F, 
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   for (int r0 = 0; r0 < rows; r0 += 64) {
     const int h = min(64, rows - r0);
-    for (int e = tid; e < 64 * KM; e += NT) {
-      int i = e % 64, j = e / 64;
-      double v = 0.0;
-      if (i < h && j < K) {
-        v = xs_get(F, T, kc, off, r0 + i, j);
-        if (j >= kc) v *= tsign;
-      }
-      sh.m[i][j] = v;
-    }
+    trunc_load_chunk(sh, F, side, r0, h, K);
     __syncthreads();
-    for (int i = 0; i < h; ++i) {
-      double av[4], bv[4];
+    if (act) {
+      for (int i = grp; i < h; i += NG) {
+        double av[4], bv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = sh.m[i][ti + 16 * u];
+        for (int u = 0; u < 4; ++u) {
+          int a = 4 * bi + u, b = 4 * bj + u;
+          av[u] = a < K ? sh.m[i][a] : 0.0;
+          bv[u] = b < K ? sh.m[i][b] : 0.0;
+        }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = sh.m[i][tj + 16 * v];
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
     }
     __syncthreads();
   }
+  double* part = &sh.z[0][0];
+  if (act) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) G[ti + 16 * u][tj + 16 * v] = acc[u][v];
+      for (int v = 0; v < 4; ++v) part[(size_t)(grp * BB + blk) * 16 + u * 4 + v] = acc[u][v];
+  }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += NT) {
+    int a = e % K, b = e / K;
+    int q = ((a / 4) * B + (b / 4)) * 16 + (a % 4) * 4 + (b % 4);
+    double s = 0.0;
+    for (int g = 0; g < NG; ++g) s += part[(size_t)g * BB * 16 + q];
+    G[a][b] = s;
+  }
   __syncthreads();
 }
 
@@ -581,260 +614,287 @@ __device__ void trunc_pchol(TruncShared& sh, double (*G)[KM + 1], int* piv, int*
   __syncthreads();
 }
 
+// Column-oriented back substitution: out[c2][c] (stacked column c2, kept
+// singular vector c) = D^{+-1} Pi R11^{-1} src[:, ord[c]].
+__device__ void trunc_backsub(TruncShared& sh, double (*G)[KM + 1], const int* pv, int r,
+                              double (*src)[KM + 1], double (*out)[33], int K, int k,
+                              bool scale_mul) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < KM * 33; e += NT) out[e % KM][e / KM] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < r * k; e += NT) {
+    int i = e % r, c = e / r;
+    out[pv[i]][c] = src[i][sh.ord[c]];
+  }
+  __syncthreads();
+  for (int i = r - 1; i >= 0; --i) {
+    const int pi = pv[i];
+    if (tid < k) out[pi][tid] /= G[pi][pi];
+    __syncthreads();
+    for (int e = tid; e < i * k; e += NT) {
+      int j = e % i, c = e / i;
+      out[pv[j]][c] -= G[pv[j]][pi] * out[pi][c];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < K * k; e += NT) {
+    int c2 = e % K, c = e / K;
+    double dd = sh.dsc[c2];
+    out[c2][c] = scale_mul ? out[c2][c] * dd : (dd > 0.0 ? out[c2][c] / dd : 0.0);
+  }
+  __syncthreads();
+}
+
+// rows of F := stacked rows . T  (T: K x k, in place, chunks of 64 rows)
+__device__ void trunc_apply(TruncShared& sh, const PRef& F, int side, int rows, int K, int k,
+                            double (*T)[33]) {
+  const int tid = threadIdx.x;
+  const int i = tid % 64, cb = tid / 64;
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    const int h = min(64, rows - r0);
+    trunc_load_chunk(sh, F, side, r0, h, K);
+    __syncthreads();
+    if (i < h && cb * 8 < k) {
+      const int c0 = cb * 8;
+      double o[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) o[v] = 0.0;
+      for (int c2 = 0; c2 < K; ++c2) {
+        const double a = sh.m[i][c2];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) o[v] += a * T[c2][c0 + v];
+      }
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        if (c0 + v < k) pset(F, r0 + i, c0 + v, o[v]);
+    }
+    __syncthreads();
+  }
+}
+
 #define LDS_TRUNC (sizeof(TruncShared))
 __device__ void d_trunc(const Op& op, char* smem) {
-  const PRef U = op.p[0], V = op.p[1], X = op.p[2], Y = op.p[3];
-  const int xo = op.i0, yo = op.i1;
+  const PRef U = op.p[0], V = op.p[1];
+  const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
+  const int nterms = op.i1;
   const int cap = op.i2 & 0xffff, fixed = op.i2 >> 16;
   const double eps = op.d0;
   const int m = U.rows, n = V.rows;
   TruncShared& sh = *reinterpret_cast<TruncShared*>(smem);
   const int tid = threadIdx.x;
-  const int ti = tid % 16, tj = tid / 16;
-  const int kc = pcols(U);
-  const int kx = pcols(X);
-  const int K = kc + kx;
-  if (tid == 0) sh.capped = 0;
-  // 1. Gram matrices
-  trunc_gram(sh, sh.gx, U, X, kc, xo, m, K, -1.0);
-  trunc_gram(sh, sh.gy, V, Y, kc, yo, n, K, 1.0);
-  // 2. balancing
-  for (int j = tid; j < K; j += NT) {
-    double a = sh.gx[j][j], b = sh.gy[j][j];
-    sh.dsc[j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 0.0;
-  }
+  double flops = 0.0, bytes = 0.0;
+  const double es = U.dt == DT_F64 ? 8.0 : 4.0;
+  int capped_any = 0, Kmax = 0;
+  if (tid == 0) sh.te = 0;
   __syncthreads();
-  for (int e = tid; e < K * K; e += NT) {
-    int a = e % K, b = e / K;
-    double da = sh.dsc[a], db = sh.dsc[b];
-    sh.gx[a][b] *= da * db;
-    sh.gy[a][b] = (da > 0.0 && db > 0.0) ? sh.gy[a][b] / (da * db) : 0.0;
-  }
-  __syncthreads();
-  // 3. pivoted Cholesky of both sides
-  trunc_pchol(sh, sh.gx, sh.px, sh.posx, K, &sh.rx);
-  trunc_pchol(sh, sh.gy, sh.py, sh.posy, K, &sh.ry);
-  const int rx = sh.rx, ry = sh.ry;
-  // 4. M = R S^T (rows of R / S in pivot order), Z = I
-  {
-    double acc[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    int ra[4], sb[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ra[u] = (ti + 16 * u < rx) ? sh.px[ti + 16 * u] : -1;
-      sb[u] = (tj + 16 * u < ry) ? sh.py[tj + 16 * u] : -1;
+  while (sh.te < nterms) {
+    // choose this pass's terms and map the stacked columns
+    if (tid == 0) {
+      const int kc = pcols(U);
+      int K = kc, t = sh.te, c = 0;
+      const int tb = t;
+      while (t < nterms && t - tb < TMAX) {
+        const int w = pcols(terms[t].X);
+        if (t > tb && K + w > KM) break;
+        for (int j = 0; j < w; ++j) {
+          sh.colt[K + j] = (int8_t)(t - tb);
+          sh.colj[K + j] = (int8_t)j;
+        }
+        sh.tm[t - tb] = terms[t];
+        K += w;
+        ++t;
+        ++c;
+      }
+      sh.kc = kc;
+      sh.K = K;
+      sh.tb = tb;
+      sh.te = t;
+      sh.capped = 0;
     }
-    for (int c = 0; c < K; ++c) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = ra[u] >= 0 ? sh.gx[ra[u]][c] : 0.0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = sb[v] >= 0 ? sh.gy[sb[v]][c] : 0.0;
+    __syncthreads();
+    const int K = sh.K, kc = sh.kc;
+    Kmax = max(Kmax, K);
+    // 1. Gram matrices
+    trunc_gram(sh, sh.gx, U, 0, m, K);
+    trunc_gram(sh, sh.gy, V, 1, n, K);
+    // 2. balancing
+    for (int j = tid; j < K; j += NT) {
+      double a = sh.gx[j][j], b = sh.gy[j][j];
+      sh.dsc[j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < K * K; e += NT) {
+      int a = e % K, b = e / K;
+      double da = sh.dsc[a], db = sh.dsc[b];
+      sh.gx[a][b] *= da * db;
+      sh.gy[a][b] = (da > 0.0 && db > 0.0) ? sh.gy[a][b] / (da * db) : 0.0;
+    }
+    __syncthreads();
+    // 3. pivoted Cholesky of both sides
+    trunc_pchol(sh, sh.gx, sh.px, sh.posx, K, &sh.rx);
+    trunc_pchol(sh, sh.gy, sh.py, sh.posy, K, &sh.ry);
+    const int rx = sh.rx, ry = sh.ry;
+    // 4. M = R S^T (rows in pivot order), Z = I
+    {
+      const int ti = tid % 16, tj = tid / 16;
+      double acc[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-    }
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      int ra[4], sb[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u) {
+        ra[u] = (ti + 16 * u < rx) ? sh.px[ti + 16 * u] : -1;
+        sb[u] = (tj + 16 * u < ry) ? sh.py[tj + 16 * u] : -1;
+      }
+      for (int c = 0; c < K; ++c) {
+        double av[4], bv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sh.m[ti + 16 * u][tj + 16 * v] = acc[u][v];
-  }
-  for (int e = tid; e < KM * KM; e += NT) {
-    int i = e % KM, j = e / KM;
-    sh.z[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  if (tid == 0) sh.mnorm2 = 0.0;
-  __syncthreads();
-  if (tid < 64) {
-    double s = 0.0;
-    for (int i = 0; i < rx; ++i)
-      if (tid < ry) s += sh.m[i][tid] * sh.m[i][tid];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (tid == 0) sh.mnorm2 = s;
-  }
-  __syncthreads();
-  // one-sided Jacobi on the columns of M (rx rows, ry columns): M Z = W Sig
-  const int ncol = ry + (ry & 1);
-  const double tiny = 1e-30 * sh.mnorm2;
-  if (ncol >= 2 && rx > 0 && sh.mnorm2 > 0.0) {
-    for (int sweep = 0; sweep < 20; ++sweep) {
-      if (tid == 0) sh.rot = 0;
+        for (int u = 0; u < 4; ++u) av[u] = ra[u] >= 0 ? sh.gx[ra[u]][c] : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bv[v] = sb[v] >= 0 ? sh.gy[sb[v]][c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
       __syncthreads();
-      for (int round = 0; round < ncol - 1; ++round) {
-        const int npair = ncol / 2;
-        const int grp = 8;
-        const int q = tid / grp, l = tid % grp;
-        if (q < npair) {
-          int x0 = (q == 0) ? ncol - 1 : (round + q) % (ncol - 1);
-          int x1 = (q == 0) ? round % (ncol - 1) : (round + ncol - 1 - q) % (ncol - 1);
-          const int a = min(x0, x1), b = max(x0, x1);
-          double al = 0, be = 0, ga = 0;
-          const bool valid = b < ry;
-          if (valid) {
-            for (int i = l; i < rx; i += grp) {
-              double u = sh.m[i][a], v = sh.m[i][b];
-              al += u * u;
-              be += v * v;
-              ga += u * v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sh.m[ti + 16 * u][tj + 16 * v] = acc[u][v];
+    }
+    for (int e = tid; e < KM * KM; e += NT) {
+      int i = e % KM, j = e / KM;
+      sh.z[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double s = 0.0;
+      for (int e = tid; e < rx * ry; e += 64) {
+        const double v = sh.m[e % rx][e / rx];
+        s += v * v;
+      }
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      if (tid == 0) sh.mnorm = s;
+    }
+    __syncthreads();
+    const double ms = sh.mnorm;
+    // one-sided Jacobi on the columns of M (rx rows, ry columns)
+    const int ncol = ry + (ry & 1);
+    const double tiny = 1e-30 * ms;
+    if (ncol >= 2 && rx > 0 && ms > 0.0) {
+      const int npair = ncol / 2;
+      int grp = 64;
+      while (grp > 1 && grp * npair > NT) grp >>= 1;   // threads per pair
+      const int q = tid / grp, l = tid % grp;
+      for (int sweep = 0; sweep < 24; ++sweep) {
+        if (tid == 0) sh.rot = 0;
+        __syncthreads();
+        for (int round = 0; round < ncol - 1; ++round) {
+          if (q < npair) {
+            int x0 = (q == 0) ? ncol - 1 : (round + q) % (ncol - 1);
+            int x1 = (q == 0) ? round % (ncol - 1) : (round + ncol - 1 - q) % (ncol - 1);
+            const int a = min(x0, x1), b = max(x0, x1);
+            double al = 0, be = 0, ga = 0;
+            const bool valid = b < ry;
+            if (valid) {
+              for (int i = l; i < rx; i += grp) {
+                double u = sh.m[i][a], v = sh.m[i][b];
+                al += u * u;
+                be += v * v;
+                ga += u * v;
+              }
+            }
+            for (int o = grp / 2; o > 0; o >>= 1) {
+              al += __shfl_xor(al, o);
+              be += __shfl_xor(be, o);
+              ga += __shfl_xor(ga, o);
+            }
+            if (valid && al > tiny && be > tiny && fabs(ga) > 1e-15 * sqrt(al * be)) {
+              double zeta = (be - al) / (2.0 * ga);
+              double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+              for (int i = l; i < rx; i += grp) {
+                double u = sh.m[i][a], v = sh.m[i][b];
+                sh.m[i][a] = cs * u - sn * v;
+                sh.m[i][b] = sn * u + cs * v;
+              }
+              for (int i = l; i < ry; i += grp) {
+                double u = sh.z[i][a], v = sh.z[i][b];
+                sh.z[i][a] = cs * u - sn * v;
+                sh.z[i][b] = sn * u + cs * v;
+              }
+              if (l == 0) sh.rot = 1;
             }
           }
-          for (int o = grp / 2; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o);
-            be += __shfl_xor(be, o);
-            ga += __shfl_xor(ga, o);
-          }
-          if (valid && al > tiny && be > tiny && fabs(ga) > 1e-15 * sqrt(al * be)) {
-            double zeta = (be - al) / (2.0 * ga);
-            double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-            for (int i = l; i < rx; i += grp) {
-              double u = sh.m[i][a], v = sh.m[i][b];
-              sh.m[i][a] = cs * u - sn * v;
-              sh.m[i][b] = sn * u + cs * v;
-            }
-            for (int i = l; i < ry; i += grp) {
-              double u = sh.z[i][a], v = sh.z[i][b];
-              sh.z[i][a] = cs * u - sn * v;
-              sh.z[i][b] = sn * u + cs * v;
-            }
-            if (l == 0) sh.rot = 1;
-          }
+          __syncthreads();
         }
+        if (!sh.rot) break;
         __syncthreads();
       }
-      if (!sh.rot) break;
-      __syncthreads();
     }
-  }
-  // singular values, descending order (stable), rank choice
-  for (int j = tid; j < ry; j += NT) {
-    double s = 0.0;
-    for (int i = 0; i < rx; ++i) s += sh.m[i][j] * sh.m[i][j];
-    sh.sig[j] = sqrt(s);
-  }
-  __syncthreads();
-  const int nr = rx > 0 ? ry : 0;
-  for (int j = tid; j < nr; j += NT) {
-    const double sj = sh.sig[j];
-    int c = 0;
-    for (int i = 0; i < nr; ++i) {
-      const double si = sh.sig[i];
-      c += (si > sj || (si == sj && i < j)) ? 1 : 0;
-    }
-    sh.ord[c] = j;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const int lim = min(nr, rx);
-    int k;
-    if (fixed > 0) {
-      k = min(fixed, lim);
-    } else {
-      double tot = 0.0;
-      for (int j = 0; j < nr; ++j) tot += sh.sig[j] * sh.sig[j];
-      const double thr = eps * eps * tot;
-      double tail = 0.0;
-      k = nr;
-      for (int j = nr; j >= 0; --j) {
-        if (tail <= thr) k = j;
-        else break;
-        if (j > 0) tail += sh.sig[sh.ord[j - 1]] * sh.sig[sh.ord[j - 1]];
-      }
-      k = min(k, lim);
-      if (k > cap) {
-        k = cap;
-        sh.capped = 1;
-      }
-    }
-    sh.k = k;
-  }
-  __syncthreads();
-  const int k = sh.k;
-  // 6. per side: back substitution into tt (stacked-column order), then
-  //    stream the new factor rows with 4 x 2 register blocks per thread
-  for (int side = 0; side < 2; ++side) {
-    const int r = side == 0 ? rx : ry;
-    double (*G)[KM + 1] = side == 0 ? sh.gx : sh.gy;
-    const int* pv = side == 0 ? sh.px : sh.py;
-    double (*src)[KM + 1] = side == 0 ? sh.m : sh.z;
-    for (int e = tid; e < KM * 32; e += NT) {
-      int c2 = e % KM, c = e / KM;
-      sh.tt[c2][c] = 0.0;
+    // singular values, descending order (stable), rank choice
+    const int nr = rx > 0 ? ry : 0;
+    for (int j = tid; j < nr; j += NT) {
+      double s = 0.0;
+      for (int i = 0; i < rx; ++i) s += sh.m[i][j] * sh.m[i][j];
+      sh.sig[j] = sqrt(s);
     }
     __syncthreads();
-    for (int e = tid; e < r * k; e += NT) {
-      int i = e % r, c = e / r;
-      sh.tt[pv[i]][c] = src[i][sh.ord[c]];
+    for (int j = tid; j < nr; j += NT) {
+      const double sj = sh.sig[j];
+      int c = 0;
+      for (int i = 0; i < nr; ++i) {
+        const double si = sh.sig[i];
+        c += (si > sj || (si == sj && i < j)) ? 1 : 0;
+      }
+      sh.ord[c] = j;
     }
     __syncthreads();
-    for (int i = r - 1; i >= 0; --i) {
-      const int pi = pv[i];
-      if (tid < k) sh.tt[pi][tid] /= G[pi][pi];
-      __syncthreads();
-      for (int e = tid; e < i * k; e += NT) {
-        int j = e % i, c = e / i;
-        sh.tt[pv[j]][c] -= G[pv[j]][pi] * sh.tt[pi][c];
+    if (tid == 0) {
+      const int lim = min(nr, rx);
+      int k;
+      if (fixed > 0) {
+        k = min(fixed, lim);
+      } else {
+        double tot = 0.0;
+        for (int j = 0; j < nr; ++j) tot += sh.sig[j] * sh.sig[j];
+        const double thr = eps * eps * tot;
+        double tail = 0.0;
+        k = nr;
+        for (int j = nr; j >= 0; --j) {
+          if (tail <= thr) k = j;
+          else break;
+          if (j > 0) tail += sh.sig[sh.ord[j - 1]] * sh.sig[sh.ord[j - 1]];
+        }
+        k = min(k, lim);
+        if (k > cap) {
+          k = cap;
+          sh.capped = 1;
+        }
       }
-      __syncthreads();
-    }
-    for (int e = tid; e < K * k; e += NT) {
-      int c2 = e % K, c = e / K;
-      double dd = sh.dsc[c2];
-      sh.tt[c2][c] = side == 0 ? sh.tt[c2][c] * dd : (dd > 0.0 ? sh.tt[c2][c] / dd : 0.0);
+      sh.k = k;
     }
     __syncthreads();
-    const PRef& F = side == 0 ? U : V;
-    const PRef& T = side == 0 ? X : Y;
-    const int rows = side == 0 ? m : n;
-    const int off = side == 0 ? xo : yo;
-    const double sgn = side == 0 ? -1.0 : 1.0;
-    for (int r0 = 0; r0 < rows; r0 += 64) {
-      const int h = min(64, rows - r0);
-      for (int e = tid; e < 64 * K; e += NT) {
-        int i = e % 64, j = e / 64;
-        double v = 0.0;
-        if (i < h) {
-          v = xs_get(F, T, kc, off, r0 + i, j);
-          if (j >= kc) v *= sgn;
-        }
-        sh.m[i][j] = v;
-      }
-      __syncthreads();
-      double o[4][2];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) o[u][0] = o[u][1] = 0.0;
-      for (int c2 = 0; c2 < K; ++c2) {
-        double av[4], bv[2];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) av[u] = sh.m[ti + 16 * u][c2];
-        bv[0] = sh.tt[c2][tj];
-        bv[1] = sh.tt[c2][tj + 16];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          o[u][0] += av[u] * bv[0];
-          o[u][1] += av[u] * bv[1];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          int i = ti + 16 * u, j = tj + 16 * v;
-          if (i < h && j < k) pset(F, r0 + i, j, o[u][v]);
-        }
-      __syncthreads();
-    }
+    const int k = sh.k;
+    capped_any |= sh.capped;
+    // 6. Tx into tt; Ty into the space of gx (R is no longer needed)
+    trunc_backsub(sh, sh.gx, sh.px, rx, sh.m, sh.tt, K, k, true);
+    double (*ty)[33] = reinterpret_cast<double (*)[33]>(&sh.gx[0][0]);
+    trunc_backsub(sh, sh.gy, sh.py, ry, sh.z, ty, K, k, false);
+    // 7. new factors, streamed in place; then the new rank
+    trunc_apply(sh, U, 0, m, K, k, sh.tt);
+    trunc_apply(sh, V, 1, n, K, k, ty);
+    if (tid == 0) *reinterpret_cast<int32_t*>(U.rankp) = k;
+    __threadfence_block();
+    __syncthreads();
+    flops += 2.0 * (m + n) * K * K - 4.0 * K * K * K / 3.0 + 2.0 * K * K * K +
+             21.0 * K * K * K + 2.0 * (m + n) * K * k;
+    bytes += es * (double)(m + n) * (K + k);
   }
-  if (tid == 0) *reinterpret_cast<int32_t*>(U.rankp) = k;
-  const double es = U.dt == DT_F64 ? 8.0 : 4.0;
-  const double flops = 2.0 * (m + n) * K * K - 4.0 * K * K * K / 3.0 + 2.0 * K * K * K +
-                       21.0 * K * K * K + 2.0 * (m + n) * K * k;
-  put_cost(op, flops, es * (double)(m + n) * (K + k), (double)sh.capped, (double)k, (double)K);
+  put_cost(op, flops, bytes, (double)capped_any, (double)sh.k, (double)Kmax);
 }
 
 // ---------------------------------------------------------------- matvec
@@ -981,9 +1041,7 @@ __global__ void k_set_int(int32_t* p, int v) {
 // types (one launch per wave of the schedule).  Each op type carves its
 // tiles out of the same dynamic LDS buffer, so a launch requests the
 // largest footprint among the types it contains.
-__global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
-  extern __shared__ __align__(16) char smem[];
-  const Op& op = ops[blockIdx.x];
+__device__ __forceinline__ void run_op(const Op& op, char* smem) {
   start_tick(op);
   switch (op.type) {
     case OP_GETRF: d_getrf(op, smem); break;
@@ -995,6 +1053,86 @@ __global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
     case OP_ADDD: d_addd(op, smem); break;
     case OP_ZERO: d_zero(op); break;
     default: break;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
+  extern __shared__ __align__(16) char smem[];
+  run_op(ops[blockIdx.x], smem);
+}
+
+// ---------------------------------------------------------------- dataflow
+// Persistent executor of the whole factor schedule: the device analogue of
+// running nested tasks with weak dependencies and early release (Sec. 4.3)
+// -- an op starts as soon as its own predecessors have finished, across
+// recursion levels, instead of waiting for a whole wave.
+//   ctrl[0]: next queue slot to take, ctrl[1]: next slot to fill,
+//   ctrl[2]: error flag (a wait exceeded the time limit).
+// Every op is pushed exactly once (when its last predecessor finishes), so
+// the queue has one slot per op; a workgroup that takes a slot >= n exits.
+// Waits are bounded by `timeout` ticks of the constant-rate wall clock, after
+// which the error flag is raised and every waiting workgroup exits.
+__global__ void k_df_reset(int* indeg, const int* indeg0, int* queue, const int* ready0,
+                           int nready, int n, int* ctrl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    indeg[i] = indeg0[i];
+    queue[i] = i < nready ? ready0[i] : -1;
+  }
+  if (i == 0) {
+    ctrl[0] = 0;
+    ctrl[1] = nready;
+    ctrl[2] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
+                                                 const int* __restrict__ succ_off,
+                                                 const int* __restrict__ succ, int* indeg,
+                                                 int* queue, int* ctrl, int n,
+                                                 long long timeout) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_op;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      int v = -1;
+      const int s = __hip_atomic_fetch_add(&ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (s < n) {
+        const long long t0 = (long long)wall_clock64();
+        for (;;) {
+          v = __hip_atomic_load(&queue[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if (v >= 0) break;
+          if (__hip_atomic_load(&ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          if ((long long)wall_clock64() - t0 > timeout) {
+            __hip_atomic_store(&ctrl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      s_op = v;
+    }
+    __syncthreads();
+    const int idx = s_op;
+    if (idx < 0) break;
+    run_op(ops[idx], smem);
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      for (int e = succ_off[idx]; e < succ_off[idx + 1]; ++e) {
+        const int t = succ[e];
+        if (__hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+          const int slot =
+              __hip_atomic_fetch_add(&ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (slot < n)
+            __hip_atomic_store(&queue[slot], t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          else
+            __hip_atomic_store(&ctrl[2], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1033,6 +1171,80 @@ static hipError_t launch_ops(int type, const Op* ops, int count, hipStream_t s) 
 }  // namespace hlu
 
 extern "C" size_t hlu_lds_bytes(int type) { return hlu::lds_bytes(type); }
+
+// Dataflow execution of a schedule: reset kernel + persistent kernel with
+// `workers` workgroups (LDS of the largest op type).
+static hipError_t df_attr() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hlu::k_dataflow),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sizeof(hlu::TruncShared));
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+extern "C" hipError_t hlu_launch_dataflow(const void* ops, const int* succ_off, const int* succ,
+                                          const int* indeg0, int* indeg, int* queue,
+                                          const int* ready0, int nready, int* ctrl, int n,
+                                          int workers, long long timeout, hipStream_t s) {
+  hipError_t e = df_attr();
+  if (e != hipSuccess) return e;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hlu::k_df_reset, dim3((n + 255) / 256), dim3(256), 0, s, indeg, indeg0,
+                     queue, ready0, nready, n, ctrl);
+  hipLaunchKernelGGL(hlu::k_dataflow, dim3(workers), dim3(NT), sizeof(hlu::TruncShared), s,
+                     reinterpret_cast<const hlu::Op*>(ops), succ_off, succ, indeg, queue, ctrl, n,
+                     timeout);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off, const int* succ,
+                                         const int* indeg0, int* indeg, int* queue,
+                                         const int* ready0, int nready, int* ctrl, int n,
+                                         int workers, long long timeout, int32_t* status,
+                                         hipGraphExec_t* out) {
+  *out = nullptr;
+  hipError_t e = df_attr();
+  if (e != hipSuccess) return e;
+  hipGraph_t g;
+  e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t n0, n1, n2;
+  {
+    int zero = 0;
+    void* args[] = {&status, &zero};
+    hipKernelNodeParams p = {};
+    p.func = reinterpret_cast<void*>(&hlu::k_set_int);
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(64);
+    p.kernelParams = args;
+    e = hipGraphAddKernelNode(&n0, g, nullptr, 0, &p);
+  }
+  if (e == hipSuccess) {
+    void* args[] = {&indeg, &indeg0, &queue, &ready0, &nready, &n, &ctrl};
+    hipKernelNodeParams p = {};
+    p.func = reinterpret_cast<void*>(&hlu::k_df_reset);
+    p.gridDim = dim3((n + 255) / 256);
+    p.blockDim = dim3(256);
+    p.kernelParams = args;
+    e = hipGraphAddKernelNode(&n1, g, &n0, 1, &p);
+  }
+  if (e == hipSuccess) {
+    const hlu::Op* ops = reinterpret_cast<const hlu::Op*>(ops_p);
+    void* args[] = {&ops, &succ_off, &succ, &indeg, &queue, &ctrl, &n, &timeout};
+    hipKernelNodeParams p = {};
+    p.func = reinterpret_cast<void*>(&hlu::k_dataflow);
+    p.gridDim = dim3(workers);
+    p.blockDim = dim3(NT);
+    p.sharedMemBytes = (unsigned)sizeof(hlu::TruncShared);
+    p.kernelParams = args;
+    e = hipGraphAddKernelNode(&n2, g, &n1, 1, &p);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
 
 // A graph that replays a schedule: a kernel node resetting the status word
 // (when given), then one k_wave node per wave, each depending on the

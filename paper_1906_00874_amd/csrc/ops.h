@@ -37,8 +37,9 @@ enum OpType : int32_t {
   OP_PGEMM = 4,    // p3 += d0 * op(M) p2; i0 = 0: M dense p0;
                    // i0 = 1: M = p0 p1^T (low-rank); i1: transpose M
   OP_TRUNC = 5,    // C = p0 p1^T (rank at p0.rankp, capacity i2 & 0xffff,
-                   // fixed rank i2 >> 16); C := best approx of C - X Y^T with
-                   // X = p2 placed at row i0 of C, Y = p3 at row i1; d0 = eps
+                   // fixed rank i2 >> 16); C := best approx of C - sum X Y^T
+                   // over the terms [i0, i0 + i1) of the term table at
+                   // p2.ptr (X placed at row xo of C, Y at row yo); d0 = eps
   OP_ADDD = 6,     // p0 (dense FP64) -= p1 p2^T
   OP_ZERO = 7,     // p0 := 0 (static columns)
   OP_NTYPES = 8
@@ -56,6 +57,14 @@ struct Op {
   double d0;
   uint64_t cost;   // device address of this op's {flops, bytes} record (0: none)
   PRef p[4];
+};
+
+// One low-rank update term of a truncation: C -= X Y^T with X at row xo of
+// C and Y at row yo (zero elsewhere).
+struct Term {
+  PRef X, Y;
+  int32_t xo, yo;
+  int32_t pad[2];
 };
 
 // Matvec with the refinement copy: per low-rank block, T = V^T X[s];

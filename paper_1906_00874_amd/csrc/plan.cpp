@@ -21,6 +21,9 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <cstdio>
+#include <cstdlib>
+#include <set>
 #include <thread>
 
 namespace hlu {
@@ -496,8 +499,74 @@ class Builder {
     return r;
   }
 
+  // ---- exact dependency edges (for the dataflow executor): per object part
+  // the last writer and the readers since; an op depends on the last writer
+  // of every part it touches and, when it writes, on the readers since.
+  struct EObj {
+    int first_leaf = 0, nparts = 1;
+    std::vector<int> lastW;
+    std::vector<std::vector<int>> readers;
+  };
+  std::vector<EObj> eobjs;
+  std::vector<std::vector<int>> preds;       // emission order
+  bool want_edges = true;
+
+  void eobj_sync() {
+    while (eobjs.size() < objs.size()) {
+      const Obj& o = objs[eobjs.size()];
+      EObj e;
+      e.first_leaf = o.first_leaf;
+      e.nparts = o.whole_only ? 1 : o.nleaves;
+      e.lastW.assign(e.nparts, -1);
+      e.readers.resize(e.nparts);
+      eobjs.push_back(std::move(e));
+    }
+  }
+
+  void edges(const std::vector<Acc>& acc, int self) {
+    eobj_sync();
+    std::vector<int> pr;
+    auto range = [&](const Acc& a, int& p0, int& p1) {
+      const EObj& o = eobjs[a.obj];
+      if (a.l0 < 0 || o.nparts == 1) { p0 = 0; p1 = o.nparts; }
+      else { p0 = a.l0 - o.first_leaf; p1 = a.l1 - o.first_leaf; }
+    };
+    for (const Acc& a : acc) {
+      if (a.obj < 0) continue;
+      int p0, p1;
+      range(a, p0, p1);
+      EObj& o = eobjs[a.obj];
+      for (int p = p0; p < p1; ++p) {
+        if (o.lastW[p] >= 0) pr.push_back(o.lastW[p]);
+        if (a.write) pr.insert(pr.end(), o.readers[p].begin(), o.readers[p].end());
+      }
+    }
+    for (const Acc& a : acc) {
+      if (a.obj < 0 || a.write) continue;
+      int p0, p1;
+      range(a, p0, p1);
+      EObj& o = eobjs[a.obj];
+      for (int p = p0; p < p1; ++p) o.readers[p].push_back(self);
+    }
+    for (const Acc& a : acc) {
+      if (a.obj < 0 || !a.write) continue;
+      int p0, p1;
+      range(a, p0, p1);
+      EObj& o = eobjs[a.obj];
+      for (int p = p0; p < p1; ++p) {
+        o.lastW[p] = self;
+        o.readers[p].clear();
+      }
+    }
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    if (!pr.empty() && pr.back() == self) pr.pop_back();
+    preds.push_back(std::move(pr));
+  }
+
   void emit(Op op, const std::vector<Acc>& acc) {
     int w = schedule(acc);
+    if (want_edges) edges(acc, (int)ops.size());
     if (want_cost) {
       op.cost = cost_cur;
       cost_cur += kCostRecBytes;
@@ -779,25 +848,69 @@ class Builder {
     return r;
   }
 
+  // Terms for low-rank targets are collected during one H-GEMM call and
+  // added by one truncation op per target at the end of the call (the
+  // target is never an operand of its own call, so deferring is exact).
+  struct PendTerm {
+    PV X, Y;
+    int xo, yo;
+  };
+  std::vector<int> pend_order;
+  std::vector<std::vector<PendTerm>> pend;   // indexed by block node
+  static constexpr int kMaxTermsPerOp = 16;
+
   void trunc(int Cb, const PV& X, const PV& Y, int xo, int yo, int c0, int w) {
-    const BNode& C = node(Cb);
-    const LBlock& B = P.blk[C.blk];
-    Op op = blank(OP_TRUNC);
-    op.p[0] = ref(u_panel(C.blk));
-    op.p[1] = ref(v_panel(C.blk));
-    op.p[2] = ref(colwin(X, c0, w));
-    op.p[3] = ref(colwin(Y, c0, w));
-    op.i0 = xo;
-    op.i1 = yo;
-    op.i2 = P.prm.cap_f | (P.prm.fixed_rank << 16);
-    op.d0 = P.prm.eps_f;
-    emit(op, {whole(B.objU, true), whole(B.objV, true), whole(B.objRank, true),
-              acc_of(X, false), acc_of(Y, false), racc(X), racc(Y)});
+    if (pend.size() < P.bn.size()) pend.resize(P.bn.size());
+    if (pend[Cb].empty()) pend_order.push_back(Cb);
+    pend[Cb].push_back(PendTerm{colwin(X, c0, w), colwin(Y, c0, w), xo, yo});
+    trunc_groups.insert(((int64_t)call_id << 24) ^ Cb);
   }
+
+  void flush_truncations() {
+    for (int Cb : pend_order) {
+      const BNode& C = node(Cb);
+      const LBlock& B = P.blk[C.blk];
+      std::vector<PendTerm>& L = pend[Cb];
+      for (size_t t0 = 0; t0 < L.size(); t0 += kMaxTermsPerOp) {
+        size_t t1 = std::min(L.size(), t0 + kMaxTermsPerOp);
+        Op op = blank(OP_TRUNC);
+        op.p[0] = ref(u_panel(C.blk));
+        op.p[1] = ref(v_panel(C.blk));
+        op.i0 = (int32_t)S.terms.size();
+        op.i1 = (int32_t)(t1 - t0);
+        op.i2 = P.prm.cap_f | (P.prm.fixed_rank << 16);
+        op.d0 = P.prm.eps_f;
+        std::vector<Acc> acc = {whole(B.objU, true), whole(B.objV, true),
+                                whole(B.objRank, true)};
+        for (size_t t = t0; t < t1; ++t) {
+          Term tm;
+          std::memset(&tm, 0, sizeof(tm));
+          tm.X = ref(L[t].X);
+          tm.Y = ref(L[t].Y);
+          tm.xo = L[t].xo;
+          tm.yo = L[t].yo;
+          S.terms.push_back(tm);
+          acc.push_back(acc_of(L[t].X, false));
+          acc.push_back(acc_of(L[t].Y, false));
+          acc.push_back(racc(L[t].X));
+          acc.push_back(racc(L[t].Y));
+        }
+        emit(op, acc);
+      }
+      L.clear();
+    }
+    pend_order.clear();
+  }
+  int64_t call_id = 0;
+  std::set<int64_t> trunc_groups;
 
   // C := C - A B   (C at rows xo / columns yo of a low-rank ancestor when
   // lr_target >= 0)
-  void gemm(int Cb, int Ab, int Bb) { gemm_at(Cb, Ab, Bb, 0, 0); }
+  void gemm(int Cb, int Ab, int Bb) {
+    ++call_id;
+    gemm_at(Cb, Ab, Bb, 0, 0);
+    flush_truncations();
+  }
 
   void gemm_at(int Cb, int Ab, int Bb, int xo, int yo) {
     const BNode &C = node(Cb), &A = node(Ab), &B = node(Bb);
@@ -876,6 +989,8 @@ class Builder {
     S.waves = 0;
     for (int k = 0; k < n; ++k) {
       S.ops[k] = ops[idx[k]];
+      // record slots follow the schedule order
+      S.ops[k].cost = want_cost ? (uint64_t)k * kCostRecBytes : 0;
       int w = wave[idx[k]], t = ops[idx[k]].type;
       if (S.batches.empty() || S.batches.back().wave != w || S.batches.back().type != t)
         S.batches.push_back(Batch{w, t, k, 0, 1u << t});
@@ -886,6 +1001,32 @@ class Builder {
       S.waves_list.back().mask |= 1u << t;
       S.waves = std::max(S.waves, w + 1);
     }
+    // successor lists in schedule order
+    S.succ_off.clear();
+    S.succ.clear();
+    S.indeg0.clear();
+    S.ready0.clear();
+    if (!want_edges) return;
+    std::vector<int> pos(n);
+    for (int k = 0; k < n; ++k) pos[idx[k]] = k;
+    std::vector<int32_t> cnt(n + 1, 0);
+    S.indeg0.assign(n, 0);
+    for (int e = 0; e < n; ++e) {
+      S.indeg0[pos[e]] = (int32_t)preds[e].size();
+      for (int p : preds[e]) cnt[pos[p] + 1]++;
+    }
+    for (int k = 0; k < n; ++k) cnt[k + 1] += cnt[k];
+    S.succ_off = cnt;
+    S.succ.assign(cnt[n], 0);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int e = 0; e < n; ++e)
+      for (int p : preds[e]) S.succ[fill[pos[p]]++] = pos[e];
+    for (int k = 0; k < n; ++k)
+      if (S.indeg0[k] == 0) S.ready0.push_back(k);
+    preds.clear();
+    preds.shrink_to_fit();
+    eobjs.clear();
+    eobjs.shrink_to_fit();
   }
 };
 
@@ -1131,6 +1272,9 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     B.lu(p.broot);
     if (!p.err.empty()) return false;
     B.finish();
+    if (std::getenv("HLU_DEBUG"))
+      std::fprintf(stderr, "[hlu] gemm calls %lld, truncation groups (call, target) %zu\n",
+                   (long long)B.call_id, B.trunc_groups.size());
     p.size_scratch = align256(B.scratch_cur);
     cur = align256(p.off_scratch + p.size_scratch);
     p.off_cost = cur;
@@ -1142,6 +1286,7 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     Builder B(p, p.ssched);
     B.P_dt = prm.mixed ? DT_F32 : DT_F64;
     B.want_cost = false;
+    B.want_edges = false;
     for (auto& b : p.blk) {
       if (b.kind == 'F') b.objF = B.new_obj(-1, true);
       else {
@@ -1167,6 +1312,27 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   cur = align256(cur + p.fsched.ops.size() * sizeof(Op));
   p.off_ops_s = cur;
   cur = align256(cur + p.ssched.ops.size() * sizeof(Op));
+  p.off_terms_f = cur;
+  cur = align256(cur + std::max<size_t>(1, p.fsched.terms.size()) * sizeof(Term));
+  for (auto& op : p.fsched.ops)
+    if (op.type == OP_TRUNC) op.p[2].ptr = p.off_terms_f;
+  {
+    const uint64_t N = p.fsched.ops.size();
+    p.off_df_succ_off = cur;
+    cur = align256(cur + (N + 1) * 4);
+    p.off_df_succ = cur;
+    cur = align256(cur + std::max<uint64_t>(1, p.fsched.succ.size()) * 4);
+    p.off_df_indeg0 = cur;
+    cur = align256(cur + std::max<uint64_t>(1, N) * 4);
+    p.off_df_indeg = cur;
+    cur = align256(cur + std::max<uint64_t>(1, N) * 4);
+    p.off_df_queue = cur;
+    cur = align256(cur + std::max<uint64_t>(1, N) * 4);
+    p.off_df_ready0 = cur;
+    cur = align256(cur + std::max<uint64_t>(1, p.fsched.ready0.size()) * 4);
+    p.off_df_ctrl = cur;
+    cur = align256(cur + 256);
+  }
   p.off_mv_lr = cur;
   cur = align256(cur + p.mv_lr.size() * sizeof(MvLR));
   p.off_mv_terms = cur;

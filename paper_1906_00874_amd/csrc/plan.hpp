@@ -61,7 +61,12 @@ struct Schedule {
   std::vector<Op> ops;     // sorted by (wave, type); pointers are byte offsets
   std::vector<Batch> batches;      // one per (wave, type)
   std::vector<Batch> waves_list;   // one per wave (all types)
+  std::vector<Term> terms;         // term table of the truncation ops
   int waves = 0;
+  // dependency graph in schedule order (for the dataflow executor):
+  // successors of op i are succ[succ_off[i] .. succ_off[i+1]), indeg0[i]
+  // its number of predecessors; ready0 lists the ops without any
+  std::vector<int32_t> succ_off, succ, indeg0, ready0;
 };
 
 struct Plan {
@@ -87,7 +92,10 @@ struct Plan {
   uint64_t off_nrhs = 0;           // int32 nrhs slot used by solve panels
   uint64_t off_Y = 0, off_X = 0, off_B = 0, off_eta = 0;
   uint64_t off_mvT = 0;
-  uint64_t off_ops_f = 0, off_ops_s = 0;
+  uint64_t off_ops_f = 0, off_ops_s = 0, off_terms_f = 0;
+  // dataflow executor state of the factor schedule
+  uint64_t off_df_succ_off = 0, off_df_succ = 0, off_df_indeg0 = 0, off_df_indeg = 0,
+           off_df_queue = 0, off_df_ready0 = 0, off_df_ctrl = 0;
   uint64_t off_mv_lr = 0, off_mv_terms = 0, off_mv_rows = 0, off_perm = 0;
   uint64_t total = 0;
 

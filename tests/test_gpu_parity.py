@@ -123,6 +123,22 @@ def test_truncate_fixed_rank_and_cap(P):
     assert np.linalg.norm(D - Ug @ Vg.T) == pytest.approx(math.sqrt(np.sum(sig[5:] ** 2)), rel=1e-6)
 
 
+@pytest.mark.parametrize("kx,eps", [(100, 1e-6), (64, 1e-5), (33, 1e-6)])
+def test_truncate_multi_term_passes(P, kx, eps):
+    """An update wider than the stack admits is added in several passes;
+    each pass discards at most eps of the norm of its own sum (ranks stay
+    below the capacity here, so no pass is capped)."""
+    _say("truncate multi-term", kx, eps)
+    k, Ug, Vg, Uo, Vo, D, rule = _trunc_case(P, 300, 250, 8, kx, 32, eps, seed=kx, decay=0.5)
+    assert not any(l[3] for l in rule.log)
+    nd = np.linalg.norm(D)
+    passes = math.ceil(kx / 32)
+    err = np.linalg.norm(D - Ug @ Vg.T)
+    assert err <= passes * 1.5 * eps * nd + 1e-12 * nd
+    # the rank is never below the single-shot optimum for the same tolerance
+    assert k >= Uo.shape[1] - 1
+
+
 # ---------------------------------------------------------------- H-LU
 def _hlu(P, level, leaf, **kw):
     xyz, area = icosphere(level)
@@ -268,6 +284,30 @@ def test_graph_replays_match_eager(P, prec):
         assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
         assert np.array_equal(x, x0), rep
         del junk
+
+
+@pytest.mark.parametrize("level,prec,graph", [(3, 0, 0), (3, 1, 1), (4, 1, 1)])
+def test_dataflow_executor_matches_waves(P, level, prec, graph):
+    """The persistent dataflow executor runs the same ops on the same inputs
+    (every read/write conflict is an edge), so its factors are bitwise the
+    wave executor's; replayed twice."""
+    import torch
+    xyz, area, h = _hlu(P, level, 32, eps=1e-6, precision=prec, max_nrhs=4)
+    h.set_graph(graph)
+    h.set_executor(0)
+    h.factor()
+    h.sync()
+    L0, U0 = h.export_factors()
+    p0 = h.export_pivots()
+    h.set_executor(1)
+    for rep in range(2):
+        h.reset()
+        h.factor()
+        st, inf = h.sync(check=False)
+        assert st == 0, (rep, P.lib.hlu_last_error())
+        L, U = h.export_factors()
+        assert np.array_equal(h.export_pivots(), p0)
+        assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
 
 
 def test_refinement_not_converged_is_reported(P):
