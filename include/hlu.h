@@ -188,6 +188,11 @@ hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches);
  * and second operand).  recs: ops_factor*8, info: ops_factor*4.  Synchronous. */
 hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info);
 
+/* Diagnostics: the dependency graph of the factor schedule in schedule
+ * order as CSR successor lists (succ_off: ops_factor+1 int32, succ: edges
+ * int32); *nedges receives the edge count (call with succ == NULL first). */
+hlu_status hlu_factor_graph(hlu_handle h, int32_t* succ_off, int32_t* succ, int64_t* nedges);
+
 /* Cluster-order permutation: perm[p] = original index of position p (host
  * array of n int64). */
 hlu_status hlu_get_perm(hlu_handle h, int64_t* perm);

@@ -63,6 +63,7 @@ _sig = {
     "hlu_set_graph": (C.c_int, [_P, C.c_int]),
     "hlu_set_executor": (C.c_int, [_P, C.c_int]),
     "hlu_factor_records": (C.c_int, [_P, _P, _P]),
+    "hlu_factor_graph": (C.c_int, [_P, _P, _P, _P]),
     "hlu_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_sync": (C.c_int, [_P, _P, C.POINTER(Info)]),
@@ -244,6 +245,16 @@ class HLU:
         i = np.zeros((no, 4), dtype=np.int32)
         _check(lib.hlu_factor_records(self.h, r.ctypes.data_as(_P), i.ctypes.data_as(_P)))
         return r, i
+
+    def factor_graph(self):
+        """(succ_off, succ) of the factor schedule's dependency graph."""
+        ne = C.c_int64()
+        _check(lib.hlu_factor_graph(self.h, None, None, C.byref(ne)))
+        off = np.zeros(self.stats()["ops_factor"] + 1, dtype=np.int32)
+        su = np.zeros(max(1, ne.value), dtype=np.int32)
+        _check(lib.hlu_factor_graph(self.h, off.ctypes.data_as(_P), su.ctypes.data_as(_P),
+                                    C.byref(ne)))
+        return off, su[:ne.value]
 
     def export_factors(self, stream=None):
         """(Lhat, U) dense in cluster order (numpy, n <= 8192)."""

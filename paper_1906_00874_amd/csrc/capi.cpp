@@ -785,6 +785,18 @@ hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info) {
   return HLU_OK;
 }
 
+// Dependency graph of the factor schedule in schedule order (CSR):
+// succ_off (ops+1 int32) and succ (edges int32); returns the edge count in
+// *nedges (pass succ = NULL to query it).
+hlu_status hlu_factor_graph(hlu_handle h, int32_t* succ_off, int32_t* succ, int64_t* nedges) {
+  if (!h || !nedges) return fail(HLU_ERR_ARG, "NULL argument");
+  const hlu::Schedule& sc = h->plan.fsched;
+  *nedges = (int64_t)sc.succ.size();
+  if (succ_off) std::memcpy(succ_off, sc.succ_off.data(), sc.succ_off.size() * 4);
+  if (succ) std::memcpy(succ, sc.succ.data(), sc.succ.size() * 4);
+  return HLU_OK;
+}
+
 // Number of launches per op type in the factor schedule (array of 8).
 hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches) {
   if (!h || !launches) return fail(HLU_ERR_ARG, "NULL argument");

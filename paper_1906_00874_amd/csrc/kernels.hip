@@ -454,234 +454,551 @@ __device__ void d_zero(const Op& op) {
 // passes whose stacked width K = kc + sum k_t stays <= 64 (live ranks read at
 // run time); every pass replaces C by the best approximation of
 // [U, -X_a, ..., -X_b] [V, Y_a, ..., Y_b]^T:
-//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys in FP64 (rows streamed in
-//      chunks of 64, only the K live columns, 4x4 blocks per thread over
-//      row groups);
+//   1. Gram matrices Gx = Xs^T Xs, Gy = Ys^T Ys in FP64, both sides in one
+//      sweep over row chunks of 64 (4x4 blocks per thread over row groups);
 //   2. column balancing so that |x_j| = |y_j|;
-//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T, Gy = Pi_y S^T S Pi_y^T,
-//      stopping at pivots below 1e-14 of the largest diagonal;
+//   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T and Gy = Pi_y S^T S Pi_y^T,
+//      one wavefront each (concurrently, no barriers), stopping at pivots
+//      below 1e-14 of the largest diagonal;
 //   4. M = R S^T and its one-sided Jacobi SVD M = W Sig Z^T;
 //   5. rank choice (fixed, or the smallest k with discarded Frobenius norm
 //      <= eps |Sig|, capped);
-//   6. Tx = D Pi_x R11^{-1} W_k Sig_k, Ty = D^{-1} Pi_y S11^{-1} Z_k;
+//   6. Tx = D Pi_x R11^{-1} W_k Sig_k, Ty = D^{-1} Pi_y S11^{-1} Z_k, one
+//      wavefront each;
 //   7. U := Xs Tx, V := Ys Ty streamed in place (each row chunk is read
 //      before it is written).
 #define KM 64
 #define TMAX 16
-struct TruncShared {
-  double gx[KM][KM + 1];    // Gx -> R -> (after step 6) Ty
-  double gy[KM][KM + 1];    // Gy -> S
-  double m[KM][KM + 1];     // row chunks / M -> W Sig / row chunks
-  double z[KM][KM + 1];     // Gram partials / Z
-  double tt[KM][33];        // Tx
-  double dsc[KM];
-  double sig[KM];
-  Term tm[TMAX];            // terms of the current pass
-  int px[KM], py[KM], posx[KM], posy[KM], ord[KM];
-  int8_t colt[KM], colj[KM];   // stacked column -> (term, column in term)
-  int rx, ry, k, rot, capped, sp, K, kc, tb, te;
-  double sdmax, mnorm;
+
+// Stacked column j of one side: element i is sign * base[(i - r0) * stride]
+// for r0 <= i < r0 + rows and zero elsewhere; an identity column (ident)
+// holds a single one at row r0 + irow.
+struct ColDesc {
+  uint64_t base;
+  int32_t stride, r0, rows, irow;
+  uint8_t dt, ident;
+  int8_t sign;
+  uint8_t pad[5];
 };
 
-// element (i, j) of the stacked panel of one side (0: [U, -X..], 1: [V, Y..])
-__device__ __forceinline__ double stk(const TruncShared& sh, const PRef& F, int side, int i,
-                                      int j) {
-  if (j < sh.kc) return pget(F, i, j);
-  const Term& t = sh.tm[sh.colt[j]];
-  const int ii = i - (side ? t.yo : t.xo);
-  const PRef& T = side ? t.Y : t.X;
-  if (ii < 0 || ii >= T.rows) return 0.0;
-  const double v = pget(T, ii, sh.colj[j]);
-  return side ? v : -v;
+struct TruncShared {
+  double lv[2][KM];         // pivot rows broadcast by the two Cholesky waves (16-byte aligned)
+  double gx[KM][KM + 1];    // Gx -> R (row s: pivot step s) / X-side apply chunk
+  double gy[KM][KM + 1];    // Y-side Gram chunk / Gy -> S / Y-side apply chunk
+  double m[KM][KM + 1];     // X-side Gram chunk / M -> W Sig -> Tx
+  double z[KM][KM + 1];     // Gram partials / Z -> Ty
+  ColDesc cd[2][KM];
+  double dsc[KM];
+  double sig[KM];
+  double nrm[KM];           // squared column norms during Jacobi
+  double red[4];
+  Term tm[TMAX];
+  int px[KM], py[KM], ord[KM];
+  int8_t colt[KM], colj[KM];
+  int rx, ry, k, capped, K, kc, te;
+  double mnorm;
+};
+
+// cross-lane helpers (64-wide wavefronts)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ void trunc_load_chunk(TruncShared& sh, const PRef& F, int side, int r0,
-                                                 int h, int K) {
-  for (int e = threadIdx.x; e < 64 * K; e += NT) {
-    int i = e % 64, j = e / 64;
-    sh.m[i][j] = i < h ? stk(sh, F, side, r0 + i, j) : 0.0;
+// sum over aligned groups of g consecutive lanes (g = 8, 16, 32 or 64)
+__device__ __forceinline__ double group_sum(double v, int g) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  if (g >= 16) v += dpp_d<0x140>(v);   // row_mirror
+  if (g >= 32) v += __shfl_xor(v, 16);
+  if (g >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// v[p] for a wave-uniform p (a branch tree, no per-element selects)
+#define HLU_C8(C, b) C(b) C(b + 1) C(b + 2) C(b + 3) C(b + 4) C(b + 5) C(b + 6) C(b + 7)
+#define HLU_C64(C) HLU_C8(C, 0) HLU_C8(C, 8) HLU_C8(C, 16) HLU_C8(C, 24) \
+  HLU_C8(C, 32) HLU_C8(C, 40) HLU_C8(C, 48) HLU_C8(C, 56)
+__device__ __forceinline__ double pick64(const double (&v)[KM], int p) {
+  double r = 0.0;
+  switch (p) {
+#define HLU_PICK(i) case i: r = v[i]; break;
+    HLU_C64(HLU_PICK)
+#undef HLU_PICK
+    default: break;
+  }
+  return r;
+}
+__device__ __forceinline__ void put64(double (&v)[KM], int p, double x) {
+  switch (p) {
+#define HLU_PUT(i) case i: v[i] = x; break;
+    HLU_C64(HLU_PUT)
+#undef HLU_PUT
+    default: break;
   }
 }
 
-// G (K x K) = S^T S of the stacked panel of one side
-__device__ void trunc_gram(TruncShared& sh, double (*G)[KM + 1], const PRef& F, int side,
-                           int rows, int K) {
+// one step of a wave argmax (largest value, smallest index among equals)
+// through a DPP lane permutation; lanes outside row_mask keep their own
+template <int CTRL, int RM>
+__device__ __forceinline__ void amax_dpp(double& v, int& ix) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, RM, 0xf,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, RM, 0xf,
+                                             false);
+  const int i2 = __builtin_amdgcn_update_dpp(ix, ix, CTRL, RM, 0xf, false);
+  const double v2 = __hiloint2double(hi, lo);
+  if (v2 > v || (v2 == v && i2 < ix)) {
+    v = v2;
+    ix = i2;
+  }
+}
+
+// wave-wide argmax; the result (read from lane 63) is wave-uniform
+__device__ __forceinline__ void wave_argmax(double& v, int& ix) {
+  amax_dpp<0xB1, 0xf>(v, ix);    // quad_perm [1,0,3,2]
+  amax_dpp<0x4E, 0xf>(v, ix);    // quad_perm [2,3,0,1]
+  amax_dpp<0x141, 0xf>(v, ix);   // row_half_mirror
+  amax_dpp<0x140, 0xf>(v, ix);   // row_mirror: every lane holds its row's result
+  amax_dpp<0x142, 0xa>(v, ix);   // row_bcast:15 into rows 1 and 3
+  amax_dpp<0x143, 0xc>(v, ix);   // row_bcast:31 into rows 2 and 3: lane 63 holds all
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  ix = __builtin_amdgcn_readlane(ix, 63);
+  v = __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double block_sum(TruncShared& sh, double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = sh.red[0] + sh.red[1] + sh.red[2] + sh.red[3];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double block_max(TruncShared& sh, double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = fmax(fmax(sh.red[0], sh.red[1]), fmax(sh.red[2], sh.red[3]));
+  __syncthreads();
+  return s;
+}
+
+// descriptors of the K stacked columns of both sides ([U, -X..] and [V, Y..])
+__device__ __forceinline__ void trunc_coldesc(TruncShared& sh, const PRef& U, const PRef& V) {
+  const int K = sh.K, kc = sh.kc;
+  for (int e = threadIdx.x; e < 2 * K; e += NT) {
+    const int side = e >= K, j = e - side * K;
+    // fields copied one by one (a reference chosen between two local
+    // panels would force both into private memory)
+    uint64_t ptr;
+    int32_t ld, rows, r0, cj, sg;
+    uint8_t dt, trans, kind;
+    if (j < kc) {
+      ptr = side ? V.ptr : U.ptr;
+      ld = side ? V.ld : U.ld;
+      rows = side ? V.rows : U.rows;
+      dt = side ? V.dt : U.dt;
+      trans = side ? V.trans : U.trans;
+      kind = side ? V.kind : U.kind;
+      r0 = 0;
+      cj = j;
+      sg = 1;
+    } else {
+      const Term& t = sh.tm[sh.colt[j]];
+      const PRef& F = side ? t.Y : t.X;   // LDS: no copy
+      ptr = F.ptr;
+      ld = F.ld;
+      rows = F.rows;
+      dt = F.dt;
+      trans = F.trans;
+      kind = F.kind;
+      r0 = side ? t.yo : t.xo;
+      cj = sh.colj[j];
+      sg = side ? 1 : -1;
+    }
+    ColDesc d;
+    const int64_t es = dt == DT_F64 ? 8 : 4;
+    d.base = ptr + (uint64_t)((trans ? (int64_t)cj : (int64_t)cj * ld) * es);
+    d.stride = trans ? ld : 1;
+    d.r0 = r0;
+    d.rows = rows;
+    d.irow = cj - ld;   // identity: (ii, cj) is one iff cj == ii + ld
+    d.dt = dt;
+    d.ident = kind == PK_IDENT;
+    d.sign = (int8_t)sg;
+    sh.cd[side][j] = d;
+  }
+}
+
+__device__ __forceinline__ double cd_get(const ColDesc& d, int i) {
+  const int ii = i - d.r0;
+  if (ii < 0 || ii >= d.rows) return 0.0;
+  double v;
+  if (d.ident) v = ii == d.irow ? 1.0 : 0.0;
+  else if (d.dt == DT_F64) v = reinterpret_cast<const double*>(d.base)[(int64_t)ii * d.stride];
+  else v = (double)reinterpret_cast<const float*>(d.base)[(int64_t)ii * d.stride];
+  return d.sign < 0 ? -v : v;
+}
+
+// rows [r0, r0 + 64) of both stacked panels into d0 (X side, m rows) and d1
+// (Y side, n rows); every thread issues all its loads before its stores
+__device__ __forceinline__ void trunc_load2(TruncShared& sh, double (*d0)[KM + 1],
+                                            double (*d1)[KM + 1], int r0, int m, int n, int K) {
   const int tid = threadIdx.x;
-  const int B = (K + 3) / 4;
-  const int BB = B * B;
-  const int NG = BB > 0 ? min(NT / BB, 16) : 1;
-  const int grp = BB > 0 ? tid / BB : 0, blk = BB > 0 ? tid % BB : 0;
-  const bool act = BB > 0 && grp < NG;
-  const int bi = act ? blk / B : 0, bj = act ? blk % B : 0;
-  double acc[4][4];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int rows = side ? n : m;
+    double (*d)[KM + 1] = side ? d1 : d0;
+#pragma unroll
+    for (int u0 = 0; u0 < 16; u0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + NT * (u0 + u), i = e & 63, j = e >> 6;   // j is wave-uniform
+        v[u] = (j < K && r0 + i < rows) ? cd_get(sh.cd[side][j], r0 + i) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + NT * (u0 + u), i = e & 63, j = e >> 6;
+        if (j < K) d[i][j] = v[u];
+      }
+    }
+  }
+}
+
+// Gx into gx and Gy into gy: threads 0-127 take the X side (chunks staged in
+// m), threads 128-255 the Y side (chunks staged in gy)
+__device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K) {
+  const int tid = threadIdx.x;
+  const int side = tid >> 7, t = tid & 127;
+  const int rows_side = side ? n : m;
+  double (*C)[KM + 1] = side ? sh.gy : sh.m;
+  double (*G)[KM + 1] = side ? sh.gy : sh.gx;
+  const int B = (K + 3) >> 2, BB = B * B;
+  int NG, grp, blk0, blk1;
+  if (BB == 0) {
+    NG = 1; grp = 0; blk0 = -1; blk1 = -1;
+  } else if (BB <= 128) {
+    NG = min(128 / BB, 16);
+    grp = t / BB;
+    blk0 = grp < NG ? t % BB : -1;
+    blk1 = -1;
+  } else {
+    NG = 1;
+    grp = 0;
+    blk0 = t;
+    blk1 = t + 128 < BB ? t + 128 : -1;
+  }
+  const int a0 = blk0 >= 0 ? 4 * (blk0 / B) : 0, b0 = blk0 >= 0 ? 4 * (blk0 % B) : 0;
+  const int a1 = blk1 >= 0 ? 4 * (blk1 / B) : 0, b1 = blk1 >= 0 ? 4 * (blk1 % B) : 0;
+  double acc0[4][4], acc1[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int v = 0; v < 4; ++v) acc0[u][v] = acc1[u][v] = 0.0;
+  const int rows = max(m, n);
   for (int r0 = 0; r0 < rows; r0 += 64) {
-    const int h = min(64, rows - r0);
-    trunc_load_chunk(sh, F, side, r0, h, K);
+    trunc_load2(sh, sh.m, sh.gy, r0, m, n, K);
     __syncthreads();
-    if (act) {
+    const int h = min(64, rows_side - r0);
+    if (blk0 >= 0) {
       for (int i = grp; i < h; i += NG) {
         double av[4], bv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          int a = 4 * bi + u, b = 4 * bj + u;
-          av[u] = a < K ? sh.m[i][a] : 0.0;
-          bv[u] = b < K ? sh.m[i][b] : 0.0;
+          av[u] = a0 + u < K ? C[i][a0 + u] : 0.0;
+          bv[u] = b0 + u < K ? C[i][b0 + u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+          for (int v = 0; v < 4; ++v) acc0[u][v] += av[u] * bv[v];
+        if (blk1 >= 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            av[u] = a1 + u < K ? C[i][a1 + u] : 0.0;
+            bv[u] = b1 + u < K ? C[i][b1 + u] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc1[u][v] += av[u] * bv[v];
+        }
       }
     }
     __syncthreads();
   }
-  double* part = &sh.z[0][0];
-  if (act) {
+  if (NG == 1) {
+    if (blk0 >= 0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) part[(size_t)(grp * BB + blk) * 16 + u * 4 + v] = acc[u][v];
+        for (int v = 0; v < 4; ++v)
+          if (a0 + u < K && b0 + v < K) G[a0 + u][b0 + v] = acc0[u][v];
+    }
+    if (blk1 >= 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (a1 + u < K && b1 + v < K) G[a1 + u][b1 + v] = acc1[u][v];
+    }
+    __syncthreads();
+  } else {
+    double* part = &sh.z[0][0] + side * 2048;
+    if (blk0 >= 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[(grp * BB + blk0) * 16 + u * 4 + v] = acc0[u][v];
+    }
+    __syncthreads();
+    for (int e = t; e < K * K; e += 128) {
+      const int a = e % K, b = e / K;
+      const int q = ((a >> 2) * B + (b >> 2)) * 16 + (a & 3) * 4 + (b & 3);
+      double s = 0.0;
+      for (int g = 0; g < NG; ++g) s += part[g * BB * 16 + q];
+      G[a][b] = s;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += NT) {
-    int a = e % K, b = e / K;
-    int q = ((a / 4) * B + (b / 4)) * 16 + (a % 4) * 4 + (b % 4);
-    double s = 0.0;
-    for (int g = 0; g < NG; ++g) s += part[(size_t)g * BB * 16 + q];
-    G[a][b] = s;
-  }
-  __syncthreads();
 }
 
-// In-place pivoted Cholesky of G (K x K).  On exit rows piv[0..r) of G hold
-// the rows of R in stacked-column order (entries of columns eliminated
-// before a row's own pivot are zero), pos[c] is the pivot position of
-// column c, and r the numerical rank.
-__device__ void trunc_pchol(TruncShared& sh, double (*G)[KM + 1], int* piv, int* pos, int K,
-                            int* r_out) {
-  const int tid = threadIdx.x;
-  for (int j = tid; j < KM; j += NT) piv[j] = j;
-  __syncthreads();
-  double dmax0 = 0.0;
-  for (int j = 0; j < K; ++j) dmax0 = fmax(dmax0, G[j][j]);
+// Pivoted Cholesky of the K x K matrix G by one wavefront; lane j keeps
+// column j of the trailing matrix in registers.  On exit row s of G holds
+// row s of R in stacked-column order (zero in the columns pivoted before
+// step s), piv[0..r) are the pivots in order, piv[r..K) the remaining
+// columns, and r is the numerical rank.  lv (64 doubles, 16-byte aligned)
+// carries each step's row of R to every lane.
+__device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv, int* piv, int K,
+                                                 int* r_out) {
+  const int lane = threadIdx.x & 63;
+  const bool in = lane < K;
+  double g[KM];
+#pragma unroll
+  for (int i = 0; i < KM; ++i) g[i] = (in && i < K) ? G[i][lane] : 0.0;
+  double d = in ? G[lane][lane] : 0.0;
+  double dmax0 = d;
+  int dummy = lane;
+  wave_argmax(dmax0, dummy);
+  bool alive = in;
   int r = 0;
-  for (int step = 0; step < K; ++step) {
-    if (tid < 64) {
-      const int q = tid;
-      double v = (q >= step && q < K) ? G[piv[q]][piv[q]] : -1.0;
-      int ix = q;
-      for (int o = 32; o > 0; o >>= 1) {
-        double v2 = __shfl_xor(v, o);
-        int i2 = __shfl_xor(ix, o);
-        if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
+  for (int s = 0; s < K; ++s) {
+    double v = alive ? d : -1.0;
+    int p = lane;
+    wave_argmax(v, p);
+    if (!(v > 1e-14 * dmax0) || !(dmax0 > 0.0)) break;
+    const double rp = sqrt(v), inv = 1.0 / rp;
+    const double l = alive ? (lane == p ? rp : pick64(g, p) * inv) : 0.0;
+    if (in) G[s][lane] = l;
+    lv[lane] = l;
+    if (lane == 0) piv[s] = p;
+    if (lane == p) alive = false;
+    // rank-one update of the trailing columns (same wavefront: the loads
+    // below see the stores above)
+    const double2* l2 = reinterpret_cast<const double2*>(lv);
+#pragma unroll
+    for (int i = 0; i < KM; i += 2) {
+      if (i < K) {
+        const double2 li = l2[i >> 1];
+        g[i] -= li.x * l;
+        g[i + 1] -= li.y * l;
       }
-      if (tid == 0) {
-        int t = piv[step];
-        piv[step] = piv[ix];
-        piv[ix] = t;
-        sh.sdmax = v;
-        sh.sp = piv[step];
-      }
     }
-    __syncthreads();
-    if (!(sh.sdmax > 1e-14 * dmax0) || !(dmax0 > 0.0)) break;
-    const int p = sh.sp;
-    const double rp = sqrt(sh.sdmax);
-    for (int q = step + tid; q < K; q += NT) {
-      int c = piv[q];
-      G[p][c] = (q == step) ? rp : G[p][c] / rp;
-    }
-    __syncthreads();
-    const int rem = K - step - 1;
-    for (int e = tid; e < rem * rem; e += NT) {
-      int a = piv[step + 1 + e % rem], b = piv[step + 1 + e / rem];
-      G[a][b] -= G[p][a] * G[p][b];
-    }
-    __syncthreads();
+    d -= l * l;
     ++r;
   }
-  for (int q = tid; q < K; q += NT) pos[piv[q]] = q;
-  __syncthreads();
-  for (int e = tid; e < r * K; e += NT) {
-    int i = e % r, c = e / r;
-    if (pos[c] < i) G[piv[i]][c] = 0.0;
-  }
-  if (tid == 0) *r_out = r;
-  __syncthreads();
+  const unsigned long long mask = __ballot(alive);
+  if (alive) piv[r + __popcll(mask & ((1ull << lane) - 1ull))] = lane;
+  if (lane == 0) *r_out = r;
 }
 
-// Column-oriented back substitution: out[c2][c] (stacked column c2, kept
-// singular vector c) = D^{+-1} Pi R11^{-1} src[:, ord[c]].
-__device__ void trunc_backsub(TruncShared& sh, double (*G)[KM + 1], const int* pv, int r,
-                              double (*src)[KM + 1], double (*out)[33], int K, int k,
-                              bool scale_mul) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < KM * 33; e += NT) out[e % KM][e / KM] = 0.0;
-  __syncthreads();
-  for (int e = tid; e < r * k; e += NT) {
-    int i = e % r, c = e / r;
-    out[pv[i]][c] = src[i][sh.ord[c]];
-  }
-  __syncthreads();
+// One wavefront; lane c < k forms column c of D^{+-1} Pi R11^{-1} buf[:, ord[c]]
+// (R11[i][t] = G[i][pv[t]]) in column c of buf (rows = stacked columns),
+// the solve running on a register copy of the column.  All lanes read their
+// sources before any lane writes.
+__device__ __forceinline__ void trunc_backsub_wave(TruncShared& sh, double (*G)[KM + 1],
+                                                   const int* pv, int r, double (*buf)[KM + 1],
+                                                   int K, int k, bool mul) {
+  const int c = threadIdx.x & 63;
+  const bool act = c < k;
+  const int oc = act ? sh.ord[c] : 0;
+  double v[KM];
+#pragma unroll
+  for (int i = 0; i < KM; ++i) v[i] = (act && i < r) ? buf[i][oc] : 0.0;
   for (int i = r - 1; i >= 0; --i) {
     const int pi = pv[i];
-    if (tid < k) out[pi][tid] /= G[pi][pi];
-    __syncthreads();
-    for (int e = tid; e < i * k; e += NT) {
-      int j = e % i, c = e / i;
-      out[pv[j]][c] -= G[pv[j]][pi] * out[pi][c];
+    const double xi = pick64(v, i) / G[i][pi];
+    put64(v, i, xi);
+#pragma unroll
+    for (int t0 = 0; t0 < KM; t0 += 8) {
+      if (t0 < i) {
+#pragma unroll
+        for (int t = t0; t < t0 + 8; ++t)
+          if (t < i) v[t] -= G[t][pi] * xi;
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
   }
-  for (int e = tid; e < K * k; e += NT) {
-    int c2 = e % K, c = e / K;
-    double dd = sh.dsc[c2];
-    out[c2][c] = scale_mul ? out[c2][c] * dd : (dd > 0.0 ? out[c2][c] / dd : 0.0);
+#pragma unroll
+  for (int i = 0; i < KM; ++i) {
+    if (i < K) {
+      const int row = pv[i];
+      const double dd = sh.dsc[row];
+      const double sc = mul ? dd : (dd > 0.0 ? 1.0 / dd : 0.0);
+      if (act) buf[row][c] = i < r ? v[i] * sc : 0.0;
+    }
   }
-  __syncthreads();
 }
 
-// rows of F := stacked rows . T  (T: K x k, in place, chunks of 64 rows)
-__device__ void trunc_apply(TruncShared& sh, const PRef& F, int side, int rows, int K, int k,
-                            double (*T)[33]) {
+// new rows of U (threads 0-127, Tx in m) and V (threads 128-255, Ty in z),
+// chunks staged in gx / gy
+__device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, const PRef& V, int m, int n, int K,
+                             int k) {
   const int tid = threadIdx.x;
-  const int i = tid % 64, cb = tid / 64;
+  const int side = tid >> 7, t = tid & 127;
+  const int i = t & 63, c0 = (t >> 6) * 16;
+  const int rows_side = side ? n : m;
+  double (*C)[KM + 1] = side ? sh.gy : sh.gx;
+  double (*T)[KM + 1] = side ? sh.z : sh.m;
+  const int rows = max(m, n);
   for (int r0 = 0; r0 < rows; r0 += 64) {
-    const int h = min(64, rows - r0);
-    trunc_load_chunk(sh, F, side, r0, h, K);
+    trunc_load2(sh, sh.gx, sh.gy, r0, m, n, K);
     __syncthreads();
-    if (i < h && cb * 8 < k) {
-      const int c0 = cb * 8;
-      double o[8];
+    if (r0 + i < rows_side && c0 < k) {
+      double o[16];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) o[v] = 0.0;
+      for (int v = 0; v < 16; ++v) o[v] = 0.0;
       for (int c2 = 0; c2 < K; ++c2) {
-        const double a = sh.m[i][c2];
+        const double a = C[i][c2];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) o[v] += a * T[c2][c0 + v];
+        for (int v = 0; v < 16; ++v) o[v] += a * T[c2][c0 + v];
       }
+      if (side) {   // wave-uniform branch
 #pragma unroll
-      for (int v = 0; v < 8; ++v)
-        if (c0 + v < k) pset(F, r0 + i, c0 + v, o[v]);
+        for (int v = 0; v < 16; ++v)
+          if (c0 + v < k) pset(V, r0 + i, c0 + v, o[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          if (c0 + v < k) pset(U, r0 + i, c0 + v, o[v]);
+      }
     }
     __syncthreads();
+  }
+}
+
+// one-sided Jacobi on the columns of M (rx rows, ry columns), rotations
+// accumulated in Z; round-robin pairing, one pair per group of grp lanes
+// (each lane holds at most 8 rows of both columns of M and Z in registers).
+// Squared column norms are kept in nrm, recomputed at every sweep and
+// carried through the rotations in between, so a round reduces one inner
+// product.
+__device__ __forceinline__ void trunc_jacobi(TruncShared& sh, int rx, int ry, double ms) {
+  const int tid = threadIdx.x;
+  const int ncol = ry + (ry & 1);
+  if (ncol < 2 || rx <= 0 || !(ms > 0.0)) return;
+  const int npair = ncol / 2, nm1 = ncol - 1;
+  int grp = 64;
+  while (grp > 8 && grp * npair > NT) grp >>= 1;
+  const int q = tid / grp, l = tid % grp;
+  const double tiny = 1e-30 * ms;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    {
+      const int j = tid >> 2, part = tid & 3;
+      double s2 = 0.0;
+      if (j < ry)
+        for (int i = part; i < rx; i += 4) s2 += sh.m[i][j] * sh.m[i][j];
+      s2 += dpp_d<0xB1>(s2);
+      s2 += dpp_d<0x4E>(s2);
+      if (part == 0 && j < ry) sh.nrm[j] = s2;
+    }
+    __syncthreads();
+    double mu = 0.0;
+    for (int round = 0; round < nm1; ++round) {
+      if (q < npair) {
+        int x0, x1;
+        if (q == 0) {
+          x0 = nm1;
+          x1 = round;
+        } else {
+          x0 = round + q;
+          if (x0 >= nm1) x0 -= nm1;
+          x1 = round + nm1 - q;
+          if (x1 >= nm1) x1 -= nm1;
+        }
+        const int a = min(x0, x1), b = max(x0, x1);
+        if (b < ry) {
+          double ma[8], mb[8], za[8], zb[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int i = l + grp * t;
+            ma[t] = i < rx ? sh.m[i][a] : 0.0;
+            mb[t] = i < rx ? sh.m[i][b] : 0.0;
+            za[t] = i < ry ? sh.z[i][a] : 0.0;
+            zb[t] = i < ry ? sh.z[i][b] : 0.0;
+          }
+          const double al = sh.nrm[a], be = sh.nrm[b];
+          double ga = 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) ga += ma[t] * mb[t];
+          ga = group_sum(ga, grp);
+          if (al > tiny && be > tiny && ga * ga > 1e-30 * al * be) {
+            mu = fmax(mu, ga * ga / (al * be));
+            // rotation zeroing the (a, b) inner product:
+            // c = sqrt((r + |d|) / 2r), s = sign(d) 2ga / sqrt(2r (r + |d|))
+            const double d = be - al, g2 = 2.0 * ga;
+            const double rr = sqrt(d * d + g2 * g2), ad = fabs(d);
+            const double y = 2.0 * rr * (rr + ad);
+            double qy = __builtin_amdgcn_rsq(y);
+            qy = qy * (1.5 - 0.5 * y * qy * qy);
+            const double sn = (d >= 0.0 ? g2 : -g2) * qy;
+            const double cs = (rr + ad) * qy;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int i = l + grp * t;
+              if (i < rx) {
+                sh.m[i][a] = cs * ma[t] - sn * mb[t];
+                sh.m[i][b] = sn * ma[t] + cs * mb[t];
+              }
+              if (i < ry) {
+                sh.z[i][a] = cs * za[t] - sn * zb[t];
+                sh.z[i][b] = sn * za[t] + cs * zb[t];
+              }
+            }
+            if (l == 0) {
+              const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * ga;
+              sh.nrm[a] = c2 * al - cg + s2 * be;
+              sh.nrm[b] = s2 * al + cg + c2 * be;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // stop once no pair had a cosine above 1e-12
+    if (!(block_max(sh, mu) > 1e-24)) break;
   }
 }
 
 #define LDS_TRUNC (sizeof(TruncShared))
-__device__ void d_trunc(const Op& op, char* smem) {
+__device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
   const PRef U = op.p[0], V = op.p[1];
   const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
   const int nterms = op.i1;
   const int cap = op.i2 & 0xffff, fixed = op.i2 >> 16;
   const double eps = op.d0;
-  const int m = U.rows, n = V.rows;
+  // sizes are the same for every thread: keep them in scalar registers
+  const int m = __builtin_amdgcn_readfirstlane(U.rows);
+  const int n = __builtin_amdgcn_readfirstlane(V.rows);
   TruncShared& sh = *reinterpret_cast<TruncShared*>(smem);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wid = tid >> 6;
   double flops = 0.0, bytes = 0.0;
   const double es = U.dt == DT_F64 ? 8.0 : 4.0;
   int capped_any = 0, Kmax = 0;
@@ -691,7 +1008,7 @@ __device__ void d_trunc(const Op& op, char* smem) {
     // choose this pass's terms and map the stacked columns
     if (tid == 0) {
       const int kc = pcols(U);
-      int K = kc, t = sh.te, c = 0;
+      int K = kc, t = sh.te;
       const int tb = t;
       while (t < nterms && t - tb < TMAX) {
         const int w = pcols(terms[t].X);
@@ -703,38 +1020,40 @@ __device__ void d_trunc(const Op& op, char* smem) {
         sh.tm[t - tb] = terms[t];
         K += w;
         ++t;
-        ++c;
       }
       sh.kc = kc;
       sh.K = K;
-      sh.tb = tb;
       sh.te = t;
       sh.capped = 0;
     }
     __syncthreads();
-    const int K = sh.K, kc = sh.kc;
+    const int K = __builtin_amdgcn_readfirstlane(sh.K);
     Kmax = max(Kmax, K);
+    trunc_coldesc(sh, U, V);
+    __syncthreads();
     // 1. Gram matrices
-    trunc_gram(sh, sh.gx, U, 0, m, K);
-    trunc_gram(sh, sh.gy, V, 1, n, K);
+    trunc_gram2(sh, m, n, K);
     // 2. balancing
     for (int j = tid; j < K; j += NT) {
-      double a = sh.gx[j][j], b = sh.gy[j][j];
+      const double a = sh.gx[j][j], b = sh.gy[j][j];
       sh.dsc[j] = (a > 0.0 && b > 0.0) ? sqrt(sqrt(b / a)) : 0.0;
     }
     __syncthreads();
     for (int e = tid; e < K * K; e += NT) {
-      int a = e % K, b = e / K;
-      double da = sh.dsc[a], db = sh.dsc[b];
+      const int a = e % K, b = e / K;
+      const double da = sh.dsc[a], db = sh.dsc[b];
       sh.gx[a][b] *= da * db;
       sh.gy[a][b] = (da > 0.0 && db > 0.0) ? sh.gy[a][b] / (da * db) : 0.0;
     }
     __syncthreads();
-    // 3. pivoted Cholesky of both sides
-    trunc_pchol(sh, sh.gx, sh.px, sh.posx, K, &sh.rx);
-    trunc_pchol(sh, sh.gy, sh.py, sh.posy, K, &sh.ry);
-    const int rx = sh.rx, ry = sh.ry;
-    // 4. M = R S^T (rows in pivot order), Z = I
+    // 3. pivoted Cholesky of both sides, one wavefront each
+    if (wid == 0) trunc_pchol_wave(sh.gx, sh.lv[0], sh.px, K, &sh.rx);
+    else if (wid == 1) trunc_pchol_wave(sh.gy, sh.lv[1], sh.py, K, &sh.ry);
+    __syncthreads();
+    const int rx = __builtin_amdgcn_readfirstlane(sh.rx);
+    const int ry = __builtin_amdgcn_readfirstlane(sh.ry);
+    // 4. M = R S^T (rows and columns in pivot order), Z = I, |M|_F^2
+    double msq = 0.0;
     {
       const int ti = tid % 16, tj = tid / 16;
       double acc[4][4];
@@ -742,105 +1061,41 @@ __device__ void d_trunc(const Op& op, char* smem) {
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-      int ra[4], sb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ra[u] = (ti + 16 * u < rx) ? sh.px[ti + 16 * u] : -1;
-        sb[u] = (tj + 16 * u < ry) ? sh.py[tj + 16 * u] : -1;
-      }
       for (int c = 0; c < K; ++c) {
         double av[4], bv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) av[u] = ra[u] >= 0 ? sh.gx[ra[u]][c] : 0.0;
+        for (int u = 0; u < 4; ++u) av[u] = ti + 16 * u < rx ? sh.gx[ti + 16 * u][c] : 0.0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) bv[v] = sb[v] >= 0 ? sh.gy[sb[v]][c] : 0.0;
+        for (int v = 0; v < 4; ++v) bv[v] = tj + 16 * v < ry ? sh.gy[tj + 16 * v][c] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
       }
-      __syncthreads();
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sh.m[ti + 16 * u][tj + 16 * v] = acc[u][v];
+        for (int v = 0; v < 4; ++v) {
+          sh.m[ti + 16 * u][tj + 16 * v] = acc[u][v];
+          msq += acc[u][v] * acc[u][v];
+        }
     }
     for (int e = tid; e < KM * KM; e += NT) {
-      int i = e % KM, j = e / KM;
+      const int i = e % KM, j = e / KM;
       sh.z[i][j] = (i == j) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    if (tid < 64) {
-      double s = 0.0;
-      for (int e = tid; e < rx * ry; e += 64) {
-        const double v = sh.m[e % rx][e / rx];
-        s += v * v;
-      }
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-      if (tid == 0) sh.mnorm = s;
-    }
-    __syncthreads();
-    const double ms = sh.mnorm;
-    // one-sided Jacobi on the columns of M (rx rows, ry columns)
-    const int ncol = ry + (ry & 1);
-    const double tiny = 1e-30 * ms;
-    if (ncol >= 2 && rx > 0 && ms > 0.0) {
-      const int npair = ncol / 2;
-      int grp = 64;
-      while (grp > 1 && grp * npair > NT) grp >>= 1;   // threads per pair
-      const int q = tid / grp, l = tid % grp;
-      for (int sweep = 0; sweep < 24; ++sweep) {
-        if (tid == 0) sh.rot = 0;
-        __syncthreads();
-        for (int round = 0; round < ncol - 1; ++round) {
-          if (q < npair) {
-            int x0 = (q == 0) ? ncol - 1 : (round + q) % (ncol - 1);
-            int x1 = (q == 0) ? round % (ncol - 1) : (round + ncol - 1 - q) % (ncol - 1);
-            const int a = min(x0, x1), b = max(x0, x1);
-            double al = 0, be = 0, ga = 0;
-            const bool valid = b < ry;
-            if (valid) {
-              for (int i = l; i < rx; i += grp) {
-                double u = sh.m[i][a], v = sh.m[i][b];
-                al += u * u;
-                be += v * v;
-                ga += u * v;
-              }
-            }
-            for (int o = grp / 2; o > 0; o >>= 1) {
-              al += __shfl_xor(al, o);
-              be += __shfl_xor(be, o);
-              ga += __shfl_xor(ga, o);
-            }
-            if (valid && al > tiny && be > tiny && fabs(ga) > 1e-15 * sqrt(al * be)) {
-              double zeta = (be - al) / (2.0 * ga);
-              double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-              for (int i = l; i < rx; i += grp) {
-                double u = sh.m[i][a], v = sh.m[i][b];
-                sh.m[i][a] = cs * u - sn * v;
-                sh.m[i][b] = sn * u + cs * v;
-              }
-              for (int i = l; i < ry; i += grp) {
-                double u = sh.z[i][a], v = sh.z[i][b];
-                sh.z[i][a] = cs * u - sn * v;
-                sh.z[i][b] = sn * u + cs * v;
-              }
-              if (l == 0) sh.rot = 1;
-            }
-          }
-          __syncthreads();
-        }
-        if (!sh.rot) break;
-        __syncthreads();
-      }
-    }
-    // singular values, descending order (stable), rank choice
+    const double ms = block_sum(sh, msq);
+    trunc_jacobi(sh, rx, ry, ms);
+    // 5. singular values, descending order (stable), rank choice
     const int nr = rx > 0 ? ry : 0;
-    for (int j = tid; j < nr; j += NT) {
+    {
+      const int j = tid >> 2, part = tid & 3;
       double s = 0.0;
-      for (int i = 0; i < rx; ++i) s += sh.m[i][j] * sh.m[i][j];
-      sh.sig[j] = sqrt(s);
+      if (j < nr)
+        for (int i = part; i < rx; i += 4) s += sh.m[i][j] * sh.m[i][j];
+      s += dpp_d<0xB1>(s);
+      s += dpp_d<0x4E>(s);
+      if (part == 0 && j < nr) sh.sig[j] = sqrt(s);
     }
     __syncthreads();
     for (int j = tid; j < nr; j += NT) {
@@ -878,15 +1133,14 @@ __device__ void d_trunc(const Op& op, char* smem) {
       sh.k = k;
     }
     __syncthreads();
-    const int k = sh.k;
+    const int k = __builtin_amdgcn_readfirstlane(sh.k);
     capped_any |= sh.capped;
-    // 6. Tx into tt; Ty into the space of gx (R is no longer needed)
-    trunc_backsub(sh, sh.gx, sh.px, rx, sh.m, sh.tt, K, k, true);
-    double (*ty)[33] = reinterpret_cast<double (*)[33]>(&sh.gx[0][0]);
-    trunc_backsub(sh, sh.gy, sh.py, ry, sh.z, ty, K, k, false);
+    // 6. Tx (in m) and Ty (in z), one wavefront each
+    if (wid == 0) trunc_backsub_wave(sh, sh.gx, sh.px, rx, sh.m, K, k, true);
+    else if (wid == 1) trunc_backsub_wave(sh, sh.gy, sh.py, ry, sh.z, K, k, false);
+    __syncthreads();
     // 7. new factors, streamed in place; then the new rank
-    trunc_apply(sh, U, 0, m, K, k, sh.tt);
-    trunc_apply(sh, V, 1, n, K, k, ty);
+    trunc_apply2(sh, U, V, m, n, K, k);
     if (tid == 0) *reinterpret_cast<int32_t*>(U.rankp) = k;
     __threadfence_block();
     __syncthreads();
