@@ -193,6 +193,13 @@ hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info);
  * int32); *nedges receives the edge count (call with succ == NULL first). */
 hlu_status hlu_factor_graph(hlu_handle h, int32_t* succ_off, int32_t* succ, int64_t* nedges);
 
+/* Diagnostics for either schedule (which: 0 factor, 1 solve): the per-op
+ * records (as hlu_factor_records; the solve's hold its last sweep) and the
+ * dependency graph (as hlu_factor_graph). */
+hlu_status hlu_schedule_records(hlu_handle h, int which, double* recs, int32_t* info);
+hlu_status hlu_schedule_graph(hlu_handle h, int which, int32_t* succ_off, int32_t* succ,
+                              int64_t* nedges);
+
 /* Cluster-order permutation: perm[p] = original index of position p (host
  * array of n int64). */
 hlu_status hlu_get_perm(hlu_handle h, int64_t* perm);

@@ -64,6 +64,8 @@ _sig = {
     "hlu_set_executor": (C.c_int, [_P, C.c_int]),
     "hlu_factor_records": (C.c_int, [_P, _P, _P]),
     "hlu_factor_graph": (C.c_int, [_P, _P, _P, _P]),
+    "hlu_schedule_records": (C.c_int, [_P, C.c_int, _P, _P]),
+    "hlu_schedule_graph": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "hlu_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_sync": (C.c_int, [_P, _P, C.POINTER(Info)]),
@@ -240,11 +242,26 @@ class HLU:
 
     def factor_records(self):
         """(records (ops, 8) float64, info (ops, 4) int32) of the last factor."""
-        no = self.stats()["ops_factor"]
+        return self.schedule_records(0)
+
+    def schedule_records(self, which):
+        """Per-op records of schedule `which` (0: factor, 1: last solve sweep)."""
+        no = self.stats()["ops_solve" if which else "ops_factor"]
         r = np.zeros((no, 8))
         i = np.zeros((no, 4), dtype=np.int32)
-        _check(lib.hlu_factor_records(self.h, r.ctypes.data_as(_P), i.ctypes.data_as(_P)))
+        _check(lib.hlu_schedule_records(self.h, which, r.ctypes.data_as(_P),
+                                        i.ctypes.data_as(_P)))
         return r, i
+
+    def schedule_graph(self, which):
+        """(succ_off, succ) of schedule `which` (0: factor, 1: solve)."""
+        ne = C.c_int64()
+        _check(lib.hlu_schedule_graph(self.h, which, None, None, C.byref(ne)))
+        off = np.zeros(self.stats()["ops_solve" if which else "ops_factor"] + 1, dtype=np.int32)
+        su = np.zeros(max(1, ne.value), dtype=np.int32)
+        _check(lib.hlu_schedule_graph(self.h, which, off.ctypes.data_as(_P),
+                                      su.ctypes.data_as(_P), C.byref(ne)))
+        return off, su[:ne.value]
 
     def factor_graph(self):
         """(succ_off, succ) of the factor schedule's dependency graph."""

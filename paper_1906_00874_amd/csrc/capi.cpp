@@ -161,6 +161,33 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
       case hlu::OP_ZERO:
         if (!panel_ok(o.p[0], T, why) || o.p[0].rankp) return bad(why.c_str());
         break;
+      case hlu::OP_MVT: {
+        const hlu::PRef &V = o.p[0], &X = o.p[2], &Tt = o.p[3];
+        if (!panel_ok(V, T, why) || !panel_ok(X, T, why) || !panel_ok(Tt, T, why))
+          return bad(why.c_str());
+        if (V.cols > 64 || V.trans || X.rows != V.rows || X.cols > 64 || X.dt != hlu::DT_F64 ||
+            X.trans)
+          return bad("V^T X operands");
+        if (Tt.dt != hlu::DT_F64 || Tt.trans || Tt.rankp || Tt.rows < V.cols || Tt.cols < X.cols)
+          return bad("V^T X target");
+        break;
+      }
+      case hlu::OP_MVROW: {
+        const hlu::PRef& Y = o.p[3];
+        if (!panel_ok(Y, T, why)) return bad(why.c_str());
+        if (Y.rows > 64 || Y.cols > 64 || Y.dt != hlu::DT_F64 || Y.trans) return bad("row target");
+        if (o.i1 < 1 || o.i0 < 0 || (size_t)o.i0 + o.i1 > sc.terms.size())
+          return bad("row update term list");
+        if (o.p[2].ptr != p.off_terms_s) return bad("row update term table");
+        for (int t = o.i0; t < o.i0 + o.i1; ++t) {
+          const hlu::Term& tm = sc.terms[t];
+          if (!panel_ok(tm.X, T, why) || !panel_ok(tm.Y, T, why)) return bad(why.c_str());
+          if (tm.X.rows != Y.rows || tm.X.cols > 64 || tm.X.trans) return bad("row term factor");
+          if (tm.Y.dt != hlu::DT_F64 || tm.Y.trans || tm.Y.rows < tm.X.cols || tm.Y.cols < Y.cols)
+            return bad("row term operand");
+        }
+        break;
+      }
       default:
         return bad("unknown op type");
     }
@@ -169,6 +196,20 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
 }
 
 }  // namespace
+
+// Device offsets of one schedule's dataflow arrays.
+struct DfArrays {
+  const hlu::Schedule* sc;
+  uint64_t ops, succ_off, succ, indeg0, indeg, queue, ready0, ctrl;
+};
+static DfArrays df_factor(const hlu::Plan& p) {
+  return {&p.fsched, p.off_ops_f, p.off_df_succ_off, p.off_df_succ, p.off_df_indeg0,
+          p.off_df_indeg, p.off_df_queue, p.off_df_ready0, p.off_df_ctrl};
+}
+static DfArrays df_solve(const hlu::Plan& p) {
+  return {&p.ssched, p.off_ops_s, p.off_dfs_succ_off, p.off_dfs_succ, p.off_dfs_indeg0,
+          p.off_dfs_indeg, p.off_dfs_queue, p.off_dfs_ready0, p.off_dfs_ctrl};
+}
 
 struct hlu_handle_s {
   hlu::Plan plan;
@@ -187,11 +228,13 @@ struct hlu_handle_s {
   hipGraphExec_t graph_f = nullptr;   // factor schedule (with status reset)
   hipGraphExec_t graph_s = nullptr;   // solve schedule
   hipGraphExec_t graph_df = nullptr;  // factor by the dataflow executor
+  hipGraphExec_t graph_dfs = nullptr; // solve by the dataflow executor
   void drop_graphs() {
     if (graph_f) hipGraphExecDestroy(graph_f);
     if (graph_s) hipGraphExecDestroy(graph_s);
     if (graph_df) hipGraphExecDestroy(graph_df);
-    graph_f = graph_s = graph_df = nullptr;
+    if (graph_dfs) hipGraphExecDestroy(graph_dfs);
+    graph_f = graph_s = graph_df = graph_dfs = nullptr;
   }
   ~hlu_handle_s() { drop_graphs(); }
 };
@@ -268,8 +311,8 @@ hlu_status hlu_validate(hlu_handle h) {
   const hlu::Plan& p = h->plan;
   // dependency graph: successors lie later in schedule order (acyclic), and
   // every in-degree equals the number of edges pointing at the op
-  {
-    const hlu::Schedule& sc = p.fsched;
+  for (const hlu::Schedule* scp : {&p.fsched, &p.ssched}) {
+    const hlu::Schedule& sc = *scp;
     const size_t N = sc.ops.size();
     if (sc.succ_off.size() != N + 1 || sc.indeg0.size() != N)
       return fail(HLU_ERR_ARG, "dependency graph size");
@@ -346,28 +389,30 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
   std::vector<hlu::Op> f = p.fsched.ops, s = p.ssched.ops;
   for (auto& op : f) relocate(op, base);
   for (auto& op : s) relocate(op, base);
-  std::vector<hlu::Term> tf = p.fsched.terms;
-  for (auto& t : tf) {
-    relocate(t.X, base);
-    relocate(t.Y, base);
+  for (int q = 0; q < 2; ++q) {
+    std::vector<hlu::Term> tf = q ? p.ssched.terms : p.fsched.terms;
+    for (auto& t : tf) {
+      relocate(t.X, base);
+      relocate(t.Y, base);
+    }
+    if (!tf.empty())
+      HIPCHK(hipMemcpy((char*)dev_ptr + (q ? p.off_terms_s : p.off_terms_f), tf.data(),
+                       tf.size() * sizeof(hlu::Term), hipMemcpyHostToDevice));
   }
-  if (!tf.empty())
-    HIPCHK(hipMemcpy((char*)dev_ptr + p.off_terms_f, tf.data(), tf.size() * sizeof(hlu::Term),
-                     hipMemcpyHostToDevice));
-  {
-    const hlu::Schedule& sc = p.fsched;
+  for (const DfArrays& da : {df_factor(p), df_solve(p)}) {
+    const hlu::Schedule& sc = *da.sc;
     char* d = (char*)dev_ptr;
-    HIPCHK(hipMemcpy(d + p.off_df_succ_off, sc.succ_off.data(), sc.succ_off.size() * 4,
+    HIPCHK(hipMemcpy(d + da.succ_off, sc.succ_off.data(), sc.succ_off.size() * 4,
                      hipMemcpyHostToDevice));
     if (!sc.succ.empty())
-      HIPCHK(hipMemcpy(d + p.off_df_succ, sc.succ.data(), sc.succ.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d + da.succ, sc.succ.data(), sc.succ.size() * 4, hipMemcpyHostToDevice));
     if (!sc.indeg0.empty())
-      HIPCHK(hipMemcpy(d + p.off_df_indeg0, sc.indeg0.data(), sc.indeg0.size() * 4,
+      HIPCHK(hipMemcpy(d + da.indeg0, sc.indeg0.data(), sc.indeg0.size() * 4,
                        hipMemcpyHostToDevice));
     if (!sc.ready0.empty())
-      HIPCHK(hipMemcpy(d + p.off_df_ready0, sc.ready0.data(), sc.ready0.size() * 4,
+      HIPCHK(hipMemcpy(d + da.ready0, sc.ready0.data(), sc.ready0.size() * 4,
                        hipMemcpyHostToDevice));
-    HIPCHK(hipMemset(d + p.off_df_ctrl, 0, 256));
+    HIPCHK(hipMemset(d + da.ctrl, 0, 256));
   }
   std::vector<hlu::MvLR> lr = p.mv_lr;
   for (auto& e : lr) {
@@ -505,35 +550,47 @@ static hlu_status device_facts(int* cus, long long* ticks_per_s) {
   return HLU_OK;
 }
 
-static hlu_status run_dataflow(hlu_handle h, hipStream_t s) {
+// Runs one schedule with the persistent dataflow executor.  The factor
+// schedule also clears the status word first (the solve leaves it alone).
+static hlu_status run_dataflow(hlu_handle h, const DfArrays& da, hipStream_t s,
+                               hipGraphExec_t* graph) {
   hlu::Plan& p = h->plan;
-  const hlu::Schedule& sc = p.fsched;
+  const hlu::Schedule& sc = *da.sc;
   char* b = h->base;
   int cus = 0;
   long long tps = 0;
   hlu_status st = device_facts(&cus, &tps);
   if (st != HLU_OK) return st;
   const long long timeout = 20 * tps;   // no single wait may exceed 20 s
-  int32_t* status = (int32_t*)(b + p.off_status);
-  const int* succ_off = (const int*)(b + p.off_df_succ_off);
-  const int* succ = (const int*)(b + p.off_df_succ);
-  const int* indeg0 = (const int*)(b + p.off_df_indeg0);
-  int* indeg = (int*)(b + p.off_df_indeg);
-  int* queue = (int*)(b + p.off_df_queue);
-  const int* ready0 = (const int*)(b + p.off_df_ready0);
-  int* ctrl = (int*)(b + p.off_df_ctrl);
+  const bool factor = da.sc == &p.fsched;
+  int32_t* status = factor ? (int32_t*)(b + p.off_status) : nullptr;
+  const int* succ_off = (const int*)(b + da.succ_off);
+  const int* succ = (const int*)(b + da.succ);
+  const int* indeg0 = (const int*)(b + da.indeg0);
+  int* indeg = (int*)(b + da.indeg);
+  int* queue = (int*)(b + da.queue);
+  const int* ready0 = (const int*)(b + da.ready0);
+  int* ctrl = (int*)(b + da.ctrl);
   const int n = (int)sc.ops.size(), nready = (int)sc.ready0.size();
+  if (n == 0) return HLU_OK;
   if (h->use_graph) {
-    if (!h->graph_df)
-      HIPCHK(hlu_build_df_graph(b + p.off_ops_f, succ_off, succ, indeg0, indeg, queue, ready0,
-                                nready, ctrl, n, cus, timeout, status, &h->graph_df));
-    HIPCHK(hipGraphLaunch(h->graph_df, s));
+    if (!*graph)
+      HIPCHK(hlu_build_df_graph(b + da.ops, succ_off, succ, indeg0, indeg, queue, ready0, nready,
+                                ctrl, n, cus, timeout, status, graph));
+    HIPCHK(hipGraphLaunch(*graph, s));
     return HLU_OK;
   }
-  HIPCHK(hlu_launch_set_int(status, 0, s));
-  HIPCHK(hlu_launch_dataflow(b + p.off_ops_f, succ_off, succ, indeg0, indeg, queue, ready0, nready,
+  if (status) HIPCHK(hlu_launch_set_int(status, 0, s));
+  HIPCHK(hlu_launch_dataflow(b + da.ops, succ_off, succ, indeg0, indeg, queue, ready0, nready,
                              ctrl, n, cus, timeout, s));
   return HLU_OK;
+}
+
+// One forward/backward sweep of the solve schedule (Y := A_H^{-1} Y).
+static hlu_status run_solve(hlu_handle h, hipStream_t s) {
+  hlu::Plan& p = h->plan;
+  if (h->executor == 1) return run_dataflow(h, df_solve(p), s, &h->graph_dfs);
+  return run_schedule(h, p.ssched, p.off_ops_s, s, nullptr, &h->graph_s);
 }
 
 hlu_status hlu_factor(hlu_handle h, void* stream) {
@@ -542,7 +599,7 @@ hlu_status hlu_factor(hlu_handle h, void* stream) {
   if (h->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
   hipStream_t s = (hipStream_t)stream;
   hlu_status st = h->executor == 1
-                      ? run_dataflow(h, s)
+                      ? run_dataflow(h, df_factor(h->plan), s, &h->graph_df)
                       : run_schedule(h, h->plan.fsched, h->plan.off_ops_f, s,
                                      (int32_t*)(h->base + h->plan.off_status), &h->graph_f);
   if (st != HLU_OK) return st;
@@ -642,7 +699,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
   HIPCHK(hlu_launch_set_int((int32_t*)(b + p.off_nrhs), nrhs, s));
   HIPCHK(hlu_launch_vec(0, b_dev, ld, B, n, perm, n, nrhs, s));        // B = P b
   HIPCHK(hlu_launch_vec(3, B, n, Y, n, nullptr, n, nrhs, s));          // Y = B
-  hlu_status st = run_schedule(h, p.ssched, p.off_ops_s, s, nullptr, &h->graph_s);
+  hlu_status st = run_solve(h, s);
   if (st != HLU_OK) return st;
   HIPCHK(hlu_launch_vec(3, Y, n, X, n, nullptr, n, nrhs, s));          // X = Y
   h->iters = 0;
@@ -671,7 +728,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
       best = std::min(best, eta);
       if (eta <= tol) break;
       if (it >= p.prm.refine_max_iter) { h->not_converged = true; break; }
-      st = run_schedule(h, p.ssched, p.off_ops_s, s, nullptr, &h->graph_s);                    // Y = A_H^{-1} Y
+      st = run_solve(h, s);                                              // Y = A_H^{-1} Y
       if (st != HLU_OK) return st;
       HIPCHK(hlu_launch_vec(2, Y, n, X, n, nullptr, n, nrhs, s));        // X += Y
       h->iters = it + 1;
@@ -713,6 +770,8 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
     HIPCHK(hipMemcpy(&st, h->base + h->plan.off_status, 4, hipMemcpyDeviceToHost));
     if (st > 0) inf.info = h->plan.perm[st - 1] + 1;
     HIPCHK(hipMemcpy(&df_error, h->base + h->plan.off_df_ctrl + 8, 4, hipMemcpyDeviceToHost));
+    if (!df_error)
+      HIPCHK(hipMemcpy(&df_error, h->base + h->plan.off_dfs_ctrl + 8, 4, hipMemcpyDeviceToHost));
   }
   inf.iters = h->iters;
   for (int i = 0; i < 16; ++i) inf.eta_hist[i] = h->eta_hist[i];
@@ -766,13 +825,20 @@ hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* 
 // Per-op records of the last factorisation in schedule order (8 doubles per
 // op) and static op information (type, wave, rows of p0, rows of p1).
 hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info) {
+  return hlu_schedule_records(h, 0, recs, info);
+}
+
+// The same for either schedule (0: factor, 1: solve, whose records hold the
+// last solve sweep).
+hlu_status hlu_schedule_records(hlu_handle h, int which, double* recs, int32_t* info) {
   if (!h || !recs || !info) return fail(HLU_ERR_ARG, "NULL argument");
+  if (which != 0 && which != 1) return fail(HLU_ERR_ARG, "schedule must be 0 or 1");
   if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
-  const hlu::Schedule& sc = h->plan.fsched;
+  const hlu::Schedule& sc = which ? h->plan.ssched : h->plan.fsched;
   size_t no = sc.ops.size();
   if (no)
-    HIPCHK(hipMemcpy(recs, h->base + h->plan.off_cost, no * hlu::kCostRecBytes,
-                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(recs, h->base + (which ? h->plan.off_cost_s : h->plan.off_cost),
+                     no * hlu::kCostRecBytes, hipMemcpyDeviceToHost));
   for (const auto& w : sc.waves_list)
     for (int q = 0; q < w.count; ++q) {
       const hlu::Op& o = sc.ops[w.start + q];
@@ -789,8 +855,14 @@ hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info) {
 // succ_off (ops+1 int32) and succ (edges int32); returns the edge count in
 // *nedges (pass succ = NULL to query it).
 hlu_status hlu_factor_graph(hlu_handle h, int32_t* succ_off, int32_t* succ, int64_t* nedges) {
+  return hlu_schedule_graph(h, 0, succ_off, succ, nedges);
+}
+
+hlu_status hlu_schedule_graph(hlu_handle h, int which, int32_t* succ_off, int32_t* succ,
+                              int64_t* nedges) {
   if (!h || !nedges) return fail(HLU_ERR_ARG, "NULL argument");
-  const hlu::Schedule& sc = h->plan.fsched;
+  if (which != 0 && which != 1) return fail(HLU_ERR_ARG, "schedule must be 0 or 1");
+  const hlu::Schedule& sc = which ? h->plan.ssched : h->plan.fsched;
   *nedges = (int64_t)sc.succ.size();
   if (succ_off) std::memcpy(succ_off, sc.succ_off.data(), sc.succ_off.size() * 4);
   if (succ) std::memcpy(succ, sc.succ.data(), sc.succ.size() * 4);

@@ -13,6 +13,11 @@ namespace hlu {
 
 #define NT 256
 
+// The dynamic LDS of every kernel here.  The op bodies take their tiles from
+// this array rather than from a pointer argument, so their accesses stay LDS
+// accesses even when a body is compiled out of line.
+extern __shared__ __align__(16) char hlu_lds[];
+
 // live column count: ranks change while a schedule runs, so they are read
 // with a device-scope atomic load (never through a cached scalar load)
 __device__ __forceinline__ int pcols(const PRef& r) {
@@ -32,6 +37,14 @@ __device__ __forceinline__ void pset(const PRef& r, int i, int j, double v) {
   size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
   if (r.dt == DT_F64) reinterpret_cast<double*>(r.ptr)[k] = v;
   else reinterpret_cast<float*>(r.ptr)[k] = (float)v;
+}
+
+// cross-lane helpers (64-wide wavefronts)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
 }
 
 // per-op record {model flops, algorithmic bytes, rank-capacity hit, rank,
@@ -61,8 +74,9 @@ __device__ __forceinline__ void start_tick(const Op& op) {
 // Contraction is disabled so that the elimination rounds exactly like the
 // textbook update a - l*u.
 #define LDS_GETRF (64 * 65 * 8 + 16)
-__device__ void d_getrf(const Op& op, char* smem) {
+__device__ void d_getrf(const Op& op) {
 #pragma clang fp contract(off)
+  char* const smem = hlu_lds;
   const PRef A = op.p[0];
   const int b = A.rows;
   double (*a)[65] = reinterpret_cast<double (*)[65]>(smem);
@@ -131,81 +145,116 @@ __device__ void d_getrf(const Op& op, char* smem) {
 // p1 := L^{-1} P p1 (OP_TRSM_L), U^{-T} p1 (OP_TRSM_UT) or U^{-1} p1
 // (OP_TRSM_U) with the factored b x b leaf p0 (b <= 64); the panel is
 // processed in chunks of 64 columns.
-#define LDS_TRSM (2 * 64 * 65 * 8 + 64 * 4)
-__device__ void d_trsm(const Op& op, char* smem) {
+#define LDS_TRSM (64 * 65 * 8 + 64 * 8 + 64 * 4)
+// Substitution on the eight-lane column layout: step s solves row k (k = s,
+// or b-1-s for TRSM_U); the leaf entries a step needs are loaded one step
+// ahead, and every update is a select (no branch per row).  Rows >= b of the
+// LDS leaf hold zeros.
+template <int TYPE>
+__device__ __forceinline__ void trsm_subst(double (&v)[8], const double (*l)[65],
+                                           const double* dinv, int b, int ln) {
+  auto operands = [&](int k, double (&lk)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = ln + 8 * u;
+      lk[u] = TYPE == OP_TRSM_UT ? l[k][i] : l[i][k];
+    }
+  };
+  double lk[8], ln8[8];
+  if (b > 0) operands(TYPE == OP_TRSM_U ? b - 1 : 0, lk);
+  for (int s = 0; s < b; ++s) {
+    const int k = TYPE == OP_TRSM_U ? b - 1 - s : s;
+    const int kn = TYPE == OP_TRSM_U ? (k > 0 ? k - 1 : 0) : (k + 1 < b ? k + 1 : k);
+    operands(kn, ln8);
+    const int lo = k & 7, uo = k >> 3;
+    double own = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) own = u == uo ? v[u] : own;
+    if (TYPE != OP_TRSM_L) own *= dinv[k];
+    own = ln == lo ? own : 0.0;
+    double xk = own;   // broadcast within the eight lanes (a sum of zeros and one value)
+    xk += dpp_d<0xB1>(xk);
+    xk += dpp_d<0x4E>(xk);
+    xk += dpp_d<0x141>(xk);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = ln + 8 * u;
+      const bool upd = TYPE == OP_TRSM_U ? i < k : (i > k && i < b);
+      const double nv = v[u] - lk[u] * xk;
+      v[u] = i == k ? xk : (upd ? nv : v[u]);
+      lk[u] = ln8[u];
+    }
+  }
+}
+// Leaf solves on the columns of Y (b <= 64 rows): TRSM_L Y := L^{-1} P Y
+// (unit lower, LAPACK-style row interchanges), TRSM_UT Y := U^{-T} Y,
+// TRSM_U Y := U^{-1} Y.  The leaf sits in LDS; eight lanes share one column
+// of Y (lane l holds rows l, l + 8, ... in registers) and each solved entry
+// is broadcast within the eight lanes through DPP, so the substitution runs
+// without barriers.  Columns are taken 32 at a time.
+__device__ void d_trsm(const Op& op) {
+  char* const smem = hlu_lds;
   const PRef L = op.p[0];
   const PRef Y = op.p[1];
   const int b = L.rows;
   const int c = pcols(Y);
   const int type = op.type;
   double (*l)[65] = reinterpret_cast<double (*)[65]>(smem);
-  double (*y)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
-  int* pv = reinterpret_cast<int*>(smem + 2 * 64 * 65 * 8);
+  double* dinv = reinterpret_cast<double*>(smem + 64 * 65 * 8);
+  int* pm = reinterpret_cast<int*>(smem + 64 * 65 * 8 + 64 * 8);
   const int tid = threadIdx.x;
-  const double* g = reinterpret_cast<const double*>(L.ptr);
-  for (int e = tid; e < b * b; e += NT) {
-    int i = e % b, j = e / b;
-    l[i][j] = g[i + (size_t)j * L.ld];
+  {
+    const double* g = reinterpret_cast<const double*>(L.ptr);
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      v[u] = (i < b && j < b) ? g[i + (size_t)j * L.ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      l[i][j] = v[u];
+    }
   }
-  if (type == OP_TRSM_L) {
-    const int32_t* piv = reinterpret_cast<const int32_t*>(op.p[2].ptr);
-    for (int i = tid; i < b; i += NT) pv[i] = piv[i];
+  if (tid < 64) {
+    if (type == OP_TRSM_L) {
+      // row permutation of the interchanges applied in order: lane i holds
+      // the source row of position i
+      const int32_t* piv = reinterpret_cast<const int32_t*>(op.p[2].ptr);
+      const int pk = tid < b ? piv[tid] : tid;
+      int pr = tid;
+      for (int k = 0; k < b; ++k) {
+        const int p = __builtin_amdgcn_readlane(pk, k);
+        const int vk = __builtin_amdgcn_readlane(pr, k), vp = __builtin_amdgcn_readlane(pr, p);
+        pr = tid == k ? vp : (tid == p ? vk : pr);
+      }
+      pm[tid] = pr;
+    }
   }
   __syncthreads();
-  for (int c0 = 0; c0 < c; c0 += 64) {
-    const int w = min(64, c - c0);
-    for (int e = tid; e < b * w; e += NT) {
-      int i = e % b, j = e / b;
-      y[i][j] = pget(Y, i, c0 + j);
+  if (type != OP_TRSM_L && tid < b) dinv[tid] = 1.0 / l[tid][tid];
+  __syncthreads();
+  const int col = tid >> 3, ln = tid & 7;
+  for (int c0 = 0; c0 < c; c0 += 32) {
+    const int j = c0 + col;
+    const bool act = j < c;
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = ln + 8 * u;
+      v[u] = (act && i < b) ? pget(Y, type == OP_TRSM_L ? pm[i] : i, j) : 0.0;
     }
-    __syncthreads();
-    if (type == OP_TRSM_L) {
-      if (tid < w) {
-        for (int k = 0; k < b; ++k) {
-          int p = pv[k];
-          if (p != k) {
-            double t = y[k][tid];
-            y[k][tid] = y[p][tid];
-            y[p][tid] = t;
-          }
-        }
-      }
-      __syncthreads();
-      for (int k = 0; k < b - 1; ++k) {
-        const int r = b - k - 1;
-        for (int e = tid; e < r * w; e += NT) {
-          int i = k + 1 + e % r, j = e / r;
-          y[i][j] -= l[i][k] * y[k][j];
-        }
-        __syncthreads();
-      }
-    } else if (type == OP_TRSM_UT) {
-      for (int k = 0; k < b; ++k) {
-        if (tid < w) y[k][tid] = y[k][tid] / l[k][k];
-        __syncthreads();
-        const int r = b - k - 1;
-        for (int e = tid; e < r * w; e += NT) {
-          int i = k + 1 + e % r, j = e / r;
-          y[i][j] -= l[k][i] * y[k][j];
-        }
-        __syncthreads();
-      }
-    } else {
-      for (int k = b - 1; k >= 0; --k) {
-        if (tid < w) y[k][tid] = y[k][tid] / l[k][k];
-        __syncthreads();
-        for (int e = tid; e < k * w; e += NT) {
-          int i = e % k, j = e / k;
-          y[i][j] -= l[i][k] * y[k][j];
-        }
-        __syncthreads();
+    if (type == OP_TRSM_L) trsm_subst<OP_TRSM_L>(v, l, dinv, b, ln);
+    else if (type == OP_TRSM_UT) trsm_subst<OP_TRSM_UT>(v, l, dinv, b, ln);
+    else trsm_subst<OP_TRSM_U>(v, l, dinv, b, ln);
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = ln + 8 * u;
+        if (i < b) pset(Y, i, j, v[u]);
       }
     }
-    for (int e = tid; e < b * w; e += NT) {
-      int i = e % b, j = e / b;
-      pset(Y, i, c0 + j, y[i][j]);
-    }
-    __syncthreads();
   }
   const double es = Y.dt == DT_F64 ? 8.0 : 4.0;
   put_cost(op, (double)b * b * c, 8.0 * b * b / 2 + 2.0 * es * b * c);
@@ -215,7 +264,8 @@ __device__ void d_trsm(const Op& op, char* smem) {
 // p3 += d0 * op(M) p2.  Dense M: tiles of 64 x 64 outputs with 32-deep LDS
 // slabs.  Low-rank M = A B^T: T = B^T X (k x c) in LDS, then Y += d0 A T.
 #define LDS_PGEMM (64 * 33 * 8 + 32 * 65 * 8 + 64 * 65 * 8)
-__device__ void d_pgemm(const Op& op, char* smem) {
+__device__ void d_pgemm(const Op& op) {
+  char* const smem = hlu_lds;
   const PRef X = op.p[2];
   const PRef Y = op.p[3];
   const double sg = op.d0;
@@ -382,7 +432,8 @@ __device__ void d_pgemm(const Op& op, char* smem) {
 // ---------------------------------------------------------------- dense update
 // p0 (FP64 dense, m x n) -= p1 p2^T
 #define LDS_ADDD (64 * 33 * 8 + 32 * 65 * 8)
-__device__ void d_addd(const Op& op, char* smem) {
+__device__ void d_addd(const Op& op) {
+  char* const smem = hlu_lds;
   const PRef C = op.p[0], X = op.p[1], Y = op.p[2];
   const int m = C.rows, n = C.cols;
   const int k = pcols(X);
@@ -460,11 +511,15 @@ __device__ void d_zero(const Op& op) {
 //   3. pivoted Cholesky Gx = Pi_x R^T R Pi_x^T and Gy = Pi_y S^T S Pi_y^T,
 //      one wavefront each (concurrently, no barriers), stopping at pivots
 //      below 1e-14 of the largest diagonal;
-//   4. M = R S^T and its one-sided Jacobi SVD M = W Sig Z^T;
+//   4. M = R S^T and its singular values and left singular vectors W by
+//      one-sided Jacobi on the columns of M;
 //   5. rank choice (fixed, or the smallest k with discarded Frobenius norm
 //      <= eps |Sig|, capped);
-//   6. Tx = D Pi_x R11^{-1} W_k Sig_k, Ty = D^{-1} Pi_y S11^{-1} Z_k, one
-//      wavefront each;
+//   6. Tx = D Pi_x R11^{-1} W_k and Ty = D^{-1} R^T W_k: with
+//      Qx = Xs D Pi_x R11^{-1} the new factors are U = Qx W_k and
+//      V = Ys D^{-1} R^T W_k = C^T Qx W_k, so U V^T = Qx W_k W_k^T Qx^T C is
+//      the projection of C onto its leading k left singular vectors (the
+//      best rank-k approximation, without the right singular vectors);
 //   7. U := Xs Tx, V := Ys Ty streamed in place (each row chunk is read
 //      before it is written).
 #define KM 64
@@ -484,13 +539,14 @@ struct ColDesc {
 struct TruncShared {
   double lv[2][KM];         // pivot rows broadcast by the two Cholesky waves (16-byte aligned)
   double gx[KM][KM + 1];    // Gx -> R (row s: pivot step s) / X-side apply chunk
-  double gy[KM][KM + 1];    // Y-side Gram chunk / Gy -> S / Y-side apply chunk
+  double gy[KM][KM + 1];    // Y-side Gram chunk / Gy -> S / Jacobi buffer / Ty
   double m[KM][KM + 1];     // X-side Gram chunk / M -> W Sig -> Tx
-  double z[KM][KM + 1];     // Gram partials / Z -> Ty
+  double z[KM][KM + 1];     // Gram partials / W_k / Y-side apply chunk
   ColDesc cd[2][KM];
   double dsc[KM];
   double sig[KM];
-  double nrm[KM];           // squared column norms during Jacobi
+  double nrm[2][KM];        // squared column norms by position (Jacobi, double-buffered)
+  double rinv[KM];          // 1 / R11[i][i]
   double red[4];
   Term tm[TMAX];
   int px[KM], py[KM], ord[KM];
@@ -498,14 +554,6 @@ struct TruncShared {
   int rx, ry, k, capped, K, kc, te;
   double mnorm;
 };
-
-// cross-lane helpers (64-wide wavefronts)
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
 
 // sum over aligned groups of g consecutive lanes (g = 8, 16, 32 or 64)
 __device__ __forceinline__ double group_sum(double v, int g) {
@@ -532,15 +580,6 @@ __device__ __forceinline__ double pick64(const double (&v)[KM], int p) {
   }
   return r;
 }
-__device__ __forceinline__ void put64(double (&v)[KM], int p, double x) {
-  switch (p) {
-#define HLU_PUT(i) case i: v[i] = x; break;
-    HLU_C64(HLU_PUT)
-#undef HLU_PUT
-    default: break;
-  }
-}
-
 // one step of a wave argmax (largest value, smallest index among equals)
 // through a DPP lane permutation; lanes outside row_mask keep their own
 template <int CTRL, int RM>
@@ -819,57 +858,65 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
   if (lane == 0) *r_out = r;
 }
 
-// One wavefront; lane c < k forms column c of D^{+-1} Pi R11^{-1} buf[:, ord[c]]
-// (R11[i][t] = G[i][pv[t]]) in column c of buf (rows = stacked columns),
-// the solve running on a register copy of the column.  All lanes read their
-// sources before any lane writes.
-__device__ __forceinline__ void trunc_backsub_wave(TruncShared& sh, double (*G)[KM + 1],
-                                                   const int* pv, int r, double (*buf)[KM + 1],
-                                                   int K, int k, bool mul) {
-  const int c = threadIdx.x & 63;
+// Tx = D Pi_x R11^{-1} W_k into m (rows = stacked columns), W_k in z and
+// R11[i][t] = gx[i][px[t]]: eight lanes per column c < k (k <= 32), lane l
+// holding rows l, l + 8, ... of the column in registers; the solved entry
+// is broadcast within the eight lanes through DPP.
+__device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int k) {
+  const int tid = threadIdx.x;
+  const int c = tid >> 3, l = tid & 7;
   const bool act = c < k;
-  const int oc = act ? sh.ord[c] : 0;
-  double v[KM];
+  double v[8];
 #pragma unroll
-  for (int i = 0; i < KM; ++i) v[i] = (act && i < r) ? buf[i][oc] : 0.0;
-  for (int i = r - 1; i >= 0; --i) {
-    const int pi = pv[i];
-    const double xi = pick64(v, i) / G[i][pi];
-    put64(v, i, xi);
+  for (int u = 0; u < 8; ++u) {
+    const int t = l + 8 * u;
+    v[u] = (act && t < rx) ? sh.z[t][c] : 0.0;
+  }
+  for (int i = rx - 1; i >= 0; --i) {
+    const int pi = sh.px[i];
+    const int lo = i & 7, uo = i >> 3;
+    double own = 0.0;
 #pragma unroll
-    for (int t0 = 0; t0 < KM; t0 += 8) {
-      if (t0 < i) {
+    for (int u = 0; u < 8; ++u) own = u == uo ? v[u] : own;
+    own = l == lo ? own * sh.rinv[i] : 0.0;
+    // broadcast the owner's value within the eight lanes (a sum of zeros
+    // and one value is exact)
+    double xi = own;
+    xi += dpp_d<0xB1>(xi);
+    xi += dpp_d<0x4E>(xi);
+    xi += dpp_d<0x141>(xi);
 #pragma unroll
-        for (int t = t0; t < t0 + 8; ++t)
-          if (t < i) v[t] -= G[t][pi] * xi;
-      }
-      __builtin_amdgcn_sched_barrier(0);
+    for (int u = 0; u < 8; ++u) {
+      const int t = l + 8 * u;
+      if (t == i) v[u] = xi;
+      else if (t < i) v[u] -= sh.gx[t][pi] * xi;
     }
   }
+  if (act) {
 #pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    if (i < K) {
-      const int row = pv[i];
-      const double dd = sh.dsc[row];
-      const double sc = mul ? dd : (dd > 0.0 ? 1.0 / dd : 0.0);
-      if (act) buf[row][c] = i < r ? v[i] * sc : 0.0;
+    for (int u = 0; u < 8; ++u) {
+      const int t = l + 8 * u;
+      if (t < K) {
+        const int row = sh.px[t];
+        sh.m[row][c] = t < rx ? v[u] * sh.dsc[row] : 0.0;
+      }
     }
   }
 }
 
-// new rows of U (threads 0-127, Tx in m) and V (threads 128-255, Ty in z),
-// chunks staged in gx / gy
-__device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, const PRef& V, int m, int n, int K,
-                             int k) {
+// new rows of U (threads 0-127, Tx in m) and V (threads 128-255, Ty in gy),
+// chunks staged in gx / z
+__device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, const PRef& V, int m,
+                                             int n, int K, int k) {
   const int tid = threadIdx.x;
   const int side = tid >> 7, t = tid & 127;
   const int i = t & 63, c0 = (t >> 6) * 16;
   const int rows_side = side ? n : m;
-  double (*C)[KM + 1] = side ? sh.gy : sh.gx;
-  double (*T)[KM + 1] = side ? sh.z : sh.m;
+  double (*C)[KM + 1] = side ? sh.z : sh.gx;
+  double (*T)[KM + 1] = side ? sh.gy : sh.m;
   const int rows = max(m, n);
   for (int r0 = 0; r0 < rows; r0 += 64) {
-    trunc_load2(sh, sh.gx, sh.gy, r0, m, n, K);
+    trunc_load2(sh, sh.gx, sh.z, r0, m, n, K);
     __syncthreads();
     if (r0 + i < rows_side && c0 < k) {
       double o[16];
@@ -894,101 +941,106 @@ __device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, con
   }
 }
 
-// one-sided Jacobi on the columns of M (rx rows, ry columns), rotations
-// accumulated in Z; round-robin pairing, one pair per group of grp lanes
-// (each lane holds at most 8 rows of both columns of M and Z in registers).
-// Squared column norms are kept in nrm, recomputed at every sweep and
-// carried through the rotations in between, so a round reduces one inner
-// product.
-__device__ __forceinline__ void trunc_jacobi(TruncShared& sh, int rx, int ry, double ms) {
+// Physical column of Jacobi position p: consecutive positions land eight
+// columns apart, so the pairs handled by one wavefront read and write
+// disjoint LDS bank windows.
+__device__ __forceinline__ int jphys(int p) { return ((p & 7) << 3) | (p >> 3); }
+
+// One-sided Jacobi on the columns of M (rx rows, ry columns, initially
+// position j = column j of m).  Round-robin ordering by the circle method:
+// position 0 stays, positions 1..n-1 advance by one each round, position p
+// pairs with n-1-p.  Each round reads one buffer and writes the rotated
+// columns to their next positions in the other (m <-> gy); a group of grp
+// lanes handles one pair, each lane at most 8 rows of both columns in
+// registers.  Squared column norms (by position) are recomputed at every
+// sweep and carried through the rotations in between, so a round reduces
+// one inner product.  Returns the buffer holding the result (0: m, 1: gy).
+__device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, double ms) {
   const int tid = threadIdx.x;
   const int ncol = ry + (ry & 1);
-  if (ncol < 2 || rx <= 0 || !(ms > 0.0)) return;
+  if (ncol < 2 || rx <= 0 || !(ms > 0.0)) return 0;
   const int npair = ncol / 2, nm1 = ncol - 1;
   int grp = 64;
   while (grp > 8 && grp * npair > NT) grp >>= 1;
   const int q = tid / grp, l = tid % grp;
+  const bool act = q < npair;
+  const int p0 = q, p1 = nm1 - q;                                    // this pair's positions
+  const int n0 = q == 0 ? 0 : q + 1, n1 = q == 0 ? 1 : ncol - q;     // and the next ones
+  const int f0 = jphys(p0), f1 = jphys(p1), g0 = jphys(n0), g1 = jphys(n1);
   const double tiny = 1e-30 * ms;
+  int cur = 0;
   for (int sweep = 0; sweep < 30; ++sweep) {
     {
+      double (*A)[KM + 1] = cur ? sh.gy : sh.m;
       const int j = tid >> 2, part = tid & 3;
       double s2 = 0.0;
-      if (j < ry)
-        for (int i = part; i < rx; i += 4) s2 += sh.m[i][j] * sh.m[i][j];
+      if (j < ncol) {
+        const int fj = jphys(j);
+        for (int i = part; i < rx; i += 4) s2 += A[i][fj] * A[i][fj];
+      }
       s2 += dpp_d<0xB1>(s2);
       s2 += dpp_d<0x4E>(s2);
-      if (part == 0 && j < ry) sh.nrm[j] = s2;
+      if (part == 0 && j < ncol) sh.nrm[cur][j] = s2;
     }
     __syncthreads();
     double mu = 0.0;
     for (int round = 0; round < nm1; ++round) {
-      if (q < npair) {
-        int x0, x1;
-        if (q == 0) {
-          x0 = nm1;
-          x1 = round;
-        } else {
-          x0 = round + q;
-          if (x0 >= nm1) x0 -= nm1;
-          x1 = round + nm1 - q;
-          if (x1 >= nm1) x1 -= nm1;
+      if (act) {
+        double (*S)[KM + 1] = cur ? sh.gy : sh.m;
+        double (*D)[KM + 1] = cur ? sh.m : sh.gy;
+        double ma[8], mb[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int i = l + grp * t;
+          ma[t] = i < rx ? S[i][f0] : 0.0;
+          mb[t] = i < rx ? S[i][f1] : 0.0;
         }
-        const int a = min(x0, x1), b = max(x0, x1);
-        if (b < ry) {
-          double ma[8], mb[8], za[8], zb[8];
+        const double al = sh.nrm[cur][p0], be = sh.nrm[cur][p1];
+        double ga = 0.0;
 #pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int i = l + grp * t;
-            ma[t] = i < rx ? sh.m[i][a] : 0.0;
-            mb[t] = i < rx ? sh.m[i][b] : 0.0;
-            za[t] = i < ry ? sh.z[i][a] : 0.0;
-            zb[t] = i < ry ? sh.z[i][b] : 0.0;
+        for (int t = 0; t < 8; ++t) ga += ma[t] * mb[t];
+        ga = group_sum(ga, grp);
+        double cs = 1.0, sn = 0.0, al2 = al, be2 = be;
+        if (al > tiny && be > tiny && ga * ga > 1e-30 * al * be) {
+          mu = fmax(mu, ga * ga / (al * be));
+          // rotation zeroing the inner product of the pair:
+          // c = sqrt((r + |d|) / 2r), s = sign(d) 2ga / sqrt(2r (r + |d|))
+          const double d = be - al, g2 = 2.0 * ga;
+          const double rr = sqrt(d * d + g2 * g2), ad = fabs(d);
+          const double y = 2.0 * rr * (rr + ad);
+          double qy = __builtin_amdgcn_rsq(y);
+          qy = qy * (1.5 - 0.5 * y * qy * qy);
+          sn = (d >= 0.0 ? g2 : -g2) * qy;
+          cs = (rr + ad) * qy;
+          const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * ga;
+          al2 = c2 * al - cg + s2 * be;
+          be2 = s2 * al + cg + c2 * be;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int i = l + grp * t;
+          if (i < rx) {
+            D[i][g0] = cs * ma[t] - sn * mb[t];
+            D[i][g1] = sn * ma[t] + cs * mb[t];
           }
-          const double al = sh.nrm[a], be = sh.nrm[b];
-          double ga = 0.0;
-#pragma unroll
-          for (int t = 0; t < 8; ++t) ga += ma[t] * mb[t];
-          ga = group_sum(ga, grp);
-          if (al > tiny && be > tiny && ga * ga > 1e-30 * al * be) {
-            mu = fmax(mu, ga * ga / (al * be));
-            // rotation zeroing the (a, b) inner product:
-            // c = sqrt((r + |d|) / 2r), s = sign(d) 2ga / sqrt(2r (r + |d|))
-            const double d = be - al, g2 = 2.0 * ga;
-            const double rr = sqrt(d * d + g2 * g2), ad = fabs(d);
-            const double y = 2.0 * rr * (rr + ad);
-            double qy = __builtin_amdgcn_rsq(y);
-            qy = qy * (1.5 - 0.5 * y * qy * qy);
-            const double sn = (d >= 0.0 ? g2 : -g2) * qy;
-            const double cs = (rr + ad) * qy;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int i = l + grp * t;
-              if (i < rx) {
-                sh.m[i][a] = cs * ma[t] - sn * mb[t];
-                sh.m[i][b] = sn * ma[t] + cs * mb[t];
-              }
-              if (i < ry) {
-                sh.z[i][a] = cs * za[t] - sn * zb[t];
-                sh.z[i][b] = sn * za[t] + cs * zb[t];
-              }
-            }
-            if (l == 0) {
-              const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * ga;
-              sh.nrm[a] = c2 * al - cg + s2 * be;
-              sh.nrm[b] = s2 * al + cg + c2 * be;
-            }
-          }
+        }
+        if (l == 0) {
+          sh.nrm[cur ^ 1][n0] = al2;
+          sh.nrm[cur ^ 1][n1] = be2;
         }
       }
       __syncthreads();
+      cur ^= 1;
     }
     // stop once no pair had a cosine above 1e-12
     if (!(block_max(sh, mu) > 1e-24)) break;
   }
+  return cur;
 }
 
 #define LDS_TRUNC (sizeof(TruncShared))
-__device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
+__device__ __forceinline__ void d_trunc(const Op& op) {
+  char* const smem = hlu_lds;
   const PRef U = op.p[0], V = op.p[1];
   const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
   const int nterms = op.i1;
@@ -1052,7 +1104,7 @@ __device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
     __syncthreads();
     const int rx = __builtin_amdgcn_readfirstlane(sh.rx);
     const int ry = __builtin_amdgcn_readfirstlane(sh.ry);
-    // 4. M = R S^T (rows and columns in pivot order), Z = I, |M|_F^2
+    // 4. M = R S^T (rows and columns in pivot order), |M|_F^2
     double msq = 0.0;
     {
       const int ti = tid % 16, tj = tid / 16;
@@ -1076,32 +1128,32 @@ __device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          sh.m[ti + 16 * u][tj + 16 * v] = acc[u][v];
+          sh.m[ti + 16 * u][jphys(tj + 16 * v)] = acc[u][v];
           msq += acc[u][v] * acc[u][v];
         }
     }
-    for (int e = tid; e < KM * KM; e += NT) {
-      const int i = e % KM, j = e / KM;
-      sh.z[i][j] = (i == j) ? 1.0 : 0.0;
-    }
     const double ms = block_sum(sh, msq);
-    trunc_jacobi(sh, rx, ry, ms);
-    // 5. singular values, descending order (stable), rank choice
+    double (*MF)[KM + 1] = trunc_jacobi(sh, rx, ry, ms) ? sh.gy : sh.m;
+    // 5. singular values (column norms, by position; an odd ry has one zero
+    // column more), descending order (stable), rank choice
     const int nr = rx > 0 ? ry : 0;
+    const int npos = rx > 0 ? ry + (ry & 1) : 0;
     {
       const int j = tid >> 2, part = tid & 3;
       double s = 0.0;
-      if (j < nr)
-        for (int i = part; i < rx; i += 4) s += sh.m[i][j] * sh.m[i][j];
+      if (j < npos) {
+        const int fj = jphys(j);
+        for (int i = part; i < rx; i += 4) s += MF[i][fj] * MF[i][fj];
+      }
       s += dpp_d<0xB1>(s);
       s += dpp_d<0x4E>(s);
-      if (part == 0 && j < nr) sh.sig[j] = sqrt(s);
+      if (part == 0 && j < npos) sh.sig[j] = sqrt(s);
     }
     __syncthreads();
-    for (int j = tid; j < nr; j += NT) {
+    for (int j = tid; j < npos; j += NT) {
       const double sj = sh.sig[j];
       int c = 0;
-      for (int i = 0; i < nr; ++i) {
+      for (int i = 0; i < npos; ++i) {
         const double si = sh.sig[i];
         c += (si > sj || (si == sj && i < j)) ? 1 : 0;
       }
@@ -1115,7 +1167,7 @@ __device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
         k = min(fixed, lim);
       } else {
         double tot = 0.0;
-        for (int j = 0; j < nr; ++j) tot += sh.sig[j] * sh.sig[j];
+        for (int j = 0; j < npos; ++j) tot += sh.sig[j] * sh.sig[j];
         const double thr = eps * eps * tot;
         double tail = 0.0;
         k = nr;
@@ -1135,9 +1187,47 @@ __device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
     __syncthreads();
     const int k = __builtin_amdgcn_readfirstlane(sh.k);
     capped_any |= sh.capped;
-    // 6. Tx (in m) and Ty (in z), one wavefront each
-    if (wid == 0) trunc_backsub_wave(sh, sh.gx, sh.px, rx, sh.m, K, k, true);
-    else if (wid == 1) trunc_backsub_wave(sh, sh.gy, sh.py, ry, sh.z, K, k, false);
+    // 6. W_k (normalised leading columns) into z, 1 / R11[i][i]; then
+    // Tx = D Pi_x R11^{-1} W_k into m and Ty = D^{-1} R^T W_k into gy
+    for (int e = tid; e < rx * k; e += NT) {
+      const int i = e % rx, c = e / rx;
+      const int j = sh.ord[c];
+      const double sj = sh.sig[j];
+      sh.z[i][c] = sj > 0.0 ? MF[i][jphys(j)] / sj : 0.0;
+    }
+    for (int i = tid; i < rx; i += NT) sh.rinv[i] = 1.0 / sh.gx[i][sh.px[i]];
+    __syncthreads();
+    trunc_trsv8(sh, rx, K, k);
+    {
+      const int tc = tid & 15, tk = tid >> 4;   // 4 stacked columns x 2 output columns
+      double acc[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = 0.0;
+      const int c20 = tc * 4, c0 = tk * 2;
+      if (c0 < k) {
+        for (int i = 0; i < rx; ++i) {
+          double rv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) rv[u] = c20 + u < K ? sh.gx[i][c20 + u] : 0.0;
+          const double w0 = sh.z[i][c0], w1 = sh.z[i][c0 + 1];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            acc[u][0] += rv[u] * w0;
+            acc[u][1] += rv[u] * w1;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c2 = c20 + u;
+          if (c2 < K) {
+            const double dd = sh.dsc[c2];
+            const double sc = dd > 0.0 ? 1.0 / dd : 0.0;
+            sh.gy[c2][c0] = acc[u][0] * sc;
+            if (c0 + 1 < k) sh.gy[c2][c0 + 1] = acc[u][1] * sc;
+          }
+        }
+      }
+    }
     __syncthreads();
     // 7. new factors, streamed in place; then the new rank
     trunc_apply2(sh, U, V, m, n, K, k);
@@ -1149,6 +1239,146 @@ __device__ __forceinline__ void d_trunc(const Op& op, char* smem) {
     bytes += es * (double)(m + n) * (K + k);
   }
   put_cost(op, flops, bytes, (double)capped_any, (double)sh.k, (double)Kmax);
+}
+
+// ---------------------------------------------------------------- solve updates
+// T := V^T X (V: n x k panel, X: n x nrhs FP64, T: FP64 with ld >= k), rows
+// streamed in chunks of 32; each thread prefetches the next chunk into
+// registers while the current one is multiplied.
+#define LDS_MVT (2 * 32 * 65 * 8)
+__device__ void d_mvt(const Op& op) {
+  char* const smem = hlu_lds;
+  const PRef V = op.p[0], X = op.p[2], T = op.p[3];
+  const int n = V.rows, k = pcols(V), nr = pcols(X);
+  double (*sv)[65] = reinterpret_cast<double (*)[65]>(smem);
+  double (*sx)[65] = reinterpret_cast<double (*)[65]>(smem + 32 * 65 * 8);
+  const int tid = threadIdx.x, ti = tid % 16, tj = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  double pv[8], px[8];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = tid + NT * u, i = q & 31, j = q >> 5;
+      const bool in = r0 + i < n;
+      pv[u] = (in && j < k) ? pget(V, r0 + i, j) : 0.0;
+      px[u] = (in && j < nr) ? pget(X, r0 + i, j) : 0.0;
+    }
+  };
+  if (n > 0) fetch(0);
+  for (int r0 = 0; r0 < n; r0 += 32) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = tid + NT * u, i = q & 31, j = q >> 5;
+      sv[i][j] = pv[u];
+      sx[i][j] = px[u];
+    }
+    __syncthreads();
+    if (r0 + 32 < n) fetch(r0 + 32);
+    const int d = min(32, n - r0);
+    for (int i = 0; i < d; ++i) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = sv[i][ti + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = sx[i][tj + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    }
+    __syncthreads();
+  }
+  double* t = reinterpret_cast<double*>(T.ptr);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = ti + 16 * u, b = tj + 16 * v;
+      if (a < k && b < nr) t[a + (size_t)b * T.ld] = acc[u][v];
+    }
+  const double es = V.dt == DT_F64 ? 8.0 : 4.0;
+  put_cost(op, 2.0 * n * k * nr, es * n * k + 8.0 * n * nr + 8.0 * k * nr);
+}
+
+// Y += d0 * sum_t X_t Y_t over the terms of one leaf row cluster (Y: rows
+// <= 64 x nrhs FP64; X_t: rows x kk, kk = live columns <= 64; Y_t: FP64,
+// ld >= kk), summed in term order; the next term's operands are prefetched
+// into registers while the current term is multiplied.
+#define LDS_MVROW (2 * 64 * 65 * 8)
+__device__ void d_mvrow(const Op& op) {
+  char* const smem = hlu_lds;
+  const PRef Y = op.p[3];
+  const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
+  const int nt = op.i1, rows = Y.rows, nr = pcols(Y);
+  double (*sa)[65] = reinterpret_cast<double (*)[65]>(smem);
+  double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
+  const int tid = threadIdx.x, i = tid & 63, c0 = (tid >> 6) * 16;
+  double o[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) o[v] = 0.0;
+  double ra[16], rb[16];
+  int kk = 0;
+  // terms are plain column-major panels (checked on the host): X_t FP32 or
+  // FP64, Y_t FP64; thread (r, cq) loads elements (r, cq + 4u)
+  const int r = tid & 63, cq = tid >> 6;
+  auto fetch = [&](int t) {
+    const Term* tp = terms + t;
+    kk = pcols(tp->X);
+    const int lda = tp->X.ld, ldb = tp->Y.ld;
+    const bool a64 = tp->X.dt == DT_F64;
+    const double* pb = reinterpret_cast<const double*>(tp->Y.ptr) + r + (size_t)cq * ldb;
+    if (a64) {
+      const double* pa = reinterpret_cast<const double*>(tp->X.ptr) + r + (size_t)cq * lda;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        ra[u] = (r < rows && cq + 4 * u < kk) ? pa[(size_t)(4 * u) * lda] : 0.0;
+    } else {
+      const float* pa = reinterpret_cast<const float*>(tp->X.ptr) + r + (size_t)cq * lda;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        ra[u] = (r < rows && cq + 4 * u < kk) ? (double)pa[(size_t)(4 * u) * lda] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      rb[u] = (r < kk && cq + 4 * u < nr) ? pb[(size_t)(4 * u) * ldb] : 0.0;
+  };
+  fetch(0);
+  for (int t = 0; t < nt; ++t) {
+    const int kt = kk;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      sa[r][cq + 4 * u] = ra[u];
+      sb[r][cq + 4 * u] = rb[u];
+    }
+    __syncthreads();
+    if (t + 1 < nt) fetch(t + 1);
+    for (int c = 0; c < kt; ++c) {
+      const double a = sa[i][c];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) o[v] += a * sb[c][c0 + v];
+    }
+    __syncthreads();
+  }
+  if (i < rows) {
+    double* y = reinterpret_cast<double*>(Y.ptr);
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      if (c0 + v < nr) y[i + (size_t)(c0 + v) * Y.ld] += op.d0 * o[v];
+  }
+  if (tid == 0 && op.cost) {
+    double fl = 0.0, by = 16.0 * rows * nr;
+    for (int t = 0; t < nt; ++t) {
+      const PRef A = terms[t].X;
+      const int k = pcols(A);
+      fl += 2.0 * rows * k * nr;
+      by += (A.dt == DT_F64 ? 8.0 : 4.0) * rows * k + 8.0 * k * nr;
+    }
+    put_cost(op, fl, by);
+  }
 }
 
 // ---------------------------------------------------------------- matvec
@@ -1295,28 +1525,29 @@ __global__ void k_set_int(int32_t* p, int v) {
 // types (one launch per wave of the schedule).  Each op type carves its
 // tiles out of the same dynamic LDS buffer, so a launch requests the
 // largest footprint among the types it contains.
-__device__ __forceinline__ void run_op(const Op& op, char* smem) {
+__device__ __forceinline__ void run_op(const Op& op) {
   start_tick(op);
   switch (op.type) {
-    case OP_GETRF: d_getrf(op, smem); break;
+    case OP_GETRF: d_getrf(op); break;
     case OP_TRSM_L:
     case OP_TRSM_UT:
-    case OP_TRSM_U: d_trsm(op, smem); break;
-    case OP_PGEMM: d_pgemm(op, smem); break;
-    case OP_TRUNC: d_trunc(op, smem); break;
-    case OP_ADDD: d_addd(op, smem); break;
+    case OP_TRSM_U: d_trsm(op); break;
+    case OP_PGEMM: d_pgemm(op); break;
+    case OP_TRUNC: d_trunc(op); break;
+    case OP_ADDD: d_addd(op); break;
     case OP_ZERO: d_zero(op); break;
+    case OP_MVT: d_mvt(op); break;
+    case OP_MVROW: d_mvrow(op); break;
     default: break;
   }
 }
 
 __global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
-  extern __shared__ __align__(16) char smem[];
-  run_op(ops[blockIdx.x], smem);
+  run_op(ops[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------- dataflow
-// Persistent executor of the whole factor schedule: the device analogue of
+// Persistent executor of a whole schedule (factor or solve): the device analogue of
 // running nested tasks with weak dependencies and early release (Sec. 4.3)
 // -- an op starts as soon as its own predecessors have finished, across
 // recursion levels, instead of waiting for a whole wave.
@@ -1345,7 +1576,6 @@ __global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
                                                  const int* __restrict__ succ, int* indeg,
                                                  int* queue, int* ctrl, int n,
                                                  long long timeout) {
-  extern __shared__ __align__(16) char smem[];
   __shared__ int s_op;
   const int tid = threadIdx.x;
   for (;;) {
@@ -1354,9 +1584,16 @@ __global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
       const int s = __hip_atomic_fetch_add(&ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (s < n) {
         const long long t0 = (long long)wall_clock64();
+        // spin with relaxed loads: an acquire per iteration would invalidate
+        // this chiplet's L2 under the ops running beside it
         for (;;) {
-          v = __hip_atomic_load(&queue[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          if (v >= 0) break;
+          v = __hip_atomic_load(&queue[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v >= 0) {
+            // pairs with the release store that pushed v: the op's inputs
+            // (every predecessor's writes) are visible from here on
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            break;
+          }
           if (__hip_atomic_load(&ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
           if ((long long)wall_clock64() - t0 > timeout) {
             __hip_atomic_store(&ctrl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1370,13 +1607,19 @@ __global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
     __syncthreads();
     const int idx = s_op;
     if (idx < 0) break;
-    run_op(ops[idx], smem);
+    run_op(ops[idx]);
     __syncthreads();
     if (tid == 0) {
-      __threadfence();
+      // one release fence publishes the op's writes; the in-degree
+      // decrements are relaxed.  The predecessor that brings a successor to
+      // zero acquires (its decrement read the others' through the chain of
+      // read-modify-writes, so their fences synchronise with it) and then
+      // pushes the successor with a release store.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       for (int e = succ_off[idx]; e < succ_off[idx + 1]; ++e) {
         const int t = succ[e];
-        if (__hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+        if (__hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           const int slot =
               __hip_atomic_fetch_add(&ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (slot < n)
@@ -1399,6 +1642,8 @@ static size_t lds_bytes(int type) {
     case OP_PGEMM: return LDS_PGEMM;
     case OP_TRUNC: return LDS_TRUNC;
     case OP_ADDD: return LDS_ADDD;
+    case OP_MVT: return LDS_MVT;
+    case OP_MVROW: return LDS_MVROW;
     default: return 0;
   }
 }
@@ -1465,7 +1710,7 @@ extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off,
   e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
   hipGraphNode_t n0, n1, n2;
-  {
+  if (status) {   // the status word is cleared only when given
     int zero = 0;
     void* args[] = {&status, &zero};
     hipKernelNodeParams p = {};
@@ -1482,7 +1727,7 @@ extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off,
     p.gridDim = dim3((n + 255) / 256);
     p.blockDim = dim3(256);
     p.kernelParams = args;
-    e = hipGraphAddKernelNode(&n1, g, &n0, 1, &p);
+    e = hipGraphAddKernelNode(&n1, g, status ? &n0 : nullptr, status ? 1 : 0, &p);
   }
   if (e == hipSuccess) {
     const hlu::Op* ops = reinterpret_cast<const hlu::Op*>(ops_p);

@@ -745,6 +745,106 @@ class Builder {
     emit(op, acc);
   }
 
+  // ---- solve updates as an H-matvec: Y[rows of M] -= M X for a block node M
+  // off the diagonal.  First T_b := V_b^T X[cols of b] for every low-rank leaf
+  // block b of M (one op each, all independent); then one op per leaf
+  // cluster r of M's rows subtracting every contribution U_b[r] T_b and
+  // F_b[r] X[cols of b] in a fixed order.  Contributions to one row cluster
+  // are summed inside one op instead of being chained op after op.
+  bool solve_mv = false;
+  std::vector<int> Tobj;     // per block: object of its V^T X slot
+  void block_leaves(int nb, std::vector<int>& out) {
+    if (node(nb).kind == 'H') {
+      for (int i = 0; i < 4; ++i) block_leaves(P.bn[nb].son[i], out);
+    } else {
+      out.push_back(nb);
+    }
+  }
+  void cluster_leaves(int c, std::vector<int>& out) {
+    if (P.cl[c].son[0] < 0) {
+      out.push_back(c);
+      return;
+    }
+    cluster_leaves(P.cl[c].son[0], out);
+    cluster_leaves(P.cl[c].son[1], out);
+  }
+  PV tslot(int b, int nrhs_cols) {
+    const LBlock& B = P.blk[b];
+    PV v;
+    v.obj = Tobj[b];
+    v.off = B.offT;
+    v.ld = P.prm.cap_f;
+    v.rows = P.prm.cap_f;
+    v.cols = nrhs_cols;
+    v.dt = DT_F64;
+    return v;
+  }
+  void hupd(const PV& Y, int nb, const PV& X) {
+    if ((int)Tobj.size() < (int)P.blk.size()) Tobj.assign(P.blk.size(), -1);
+    std::vector<int> lv;
+    block_leaves(nb, lv);
+    for (int bn : lv) {
+      const BNode& M = node(bn);
+      if (M.kind != 'R') continue;
+      const LBlock& B = P.blk[M.blk];
+      if (Tobj[M.blk] < 0) Tobj[M.blk] = new_obj(-1, true);
+      PV Xs = sub(X, M.s);
+      PV T = tslot(M.blk, X.cols);
+      Op op = blank(OP_MVT);
+      op.p[0] = ref(v_panel(M.blk));
+      op.p[2] = ref(Xs);
+      op.p[3] = ref(T);
+      emit(op, {whole(B.objV, false), whole(B.objRank, false), acc_of(Xs, false), racc(Xs),
+                whole(T.obj, true)});
+    }
+    std::vector<int> rows;
+    cluster_leaves(node(nb).t, rows);
+    for (int r : rows) {
+      const Cluster& rc = P.cl[r];
+      Op op = blank(OP_MVROW);
+      PV Yr = sub(Y, r);
+      op.p[3] = ref(Yr);
+      op.d0 = -1.0;
+      op.i0 = (int)S.terms.size();
+      std::vector<Acc> acc = {acc_of(Yr, true), racc(Yr)};
+      for (int bn : lv) {
+        const BNode& M = node(bn);
+        const Cluster& tc = P.cl[M.t];
+        if (rc.first_leaf < tc.first_leaf || rc.first_leaf >= tc.first_leaf + tc.nleaves) continue;
+        const LBlock& B = P.blk[M.blk];
+        Term t;
+        std::memset(&t, 0, sizeof(t));
+        if (M.kind == 'R') {
+          t.X = ref(sub(u_panel(M.blk), r));
+          t.Y = ref(tslot(M.blk, X.cols));
+          acc.push_back(whole(B.objU, false));
+          acc.push_back(whole(B.objRank, false));
+          acc.push_back(whole(Tobj[M.blk], false));
+          S.terms.push_back(t);
+        } else {
+          // a dense leaf may be wider than 64 (a leaf cluster against a
+          // larger one): one term per window of at most 64 columns
+          PV Xs = sub(X, M.s);
+          PV Fr = sub(dense_panel(M.blk), r);
+          for (int c0 = 0; c0 < B.n; c0 += 64) {
+            const int w = std::min(64, B.n - c0);
+            PV xw = Xs;
+            xw.off = Xs.off + (uint64_t)c0 * 8;   // rows c0.. of the FP64 vector panel
+            xw.rows = w;
+            t.X = ref(colwin(Fr, c0, w));
+            t.Y = ref(xw);
+            S.terms.push_back(t);
+          }
+          acc.push_back(whole(B.objF, false));
+          acc.push_back(acc_of(Xs, false));
+        }
+      }
+      op.i1 = (int)S.terms.size() - op.i0;
+      if (op.i1 == 0) continue;
+      emit(op, acc);
+    }
+  }
+
   // Y := L^{-1} P Y over the rows of diagonal node nb
   void fwd(int nb, const PV& Y) {
     if (node(nb).kind == 'F') { trsm_leaf(OP_TRSM_L, nb, Y); return; }
@@ -752,7 +852,8 @@ class Builder {
     int t0 = P.cl[L.t].son[0], t1 = P.cl[L.t].son[1];
     PV Y0 = sub(Y, t0), Y1 = sub(Y, t1);
     fwd(son(nb, 0, 0), Y0);
-    pmul(Y1, son(nb, 1, 0), Y0, -1.0, false);
+    if (solve_mv) hupd(Y1, son(nb, 1, 0), Y0);
+    else pmul(Y1, son(nb, 1, 0), Y0, -1.0, false);
     fwd(son(nb, 1, 1), Y1);
   }
   // Y := U^{-T} Y
@@ -772,7 +873,8 @@ class Builder {
     int t0 = P.cl[U.t].son[0], t1 = P.cl[U.t].son[1];
     PV Y0 = sub(Y, t0), Y1 = sub(Y, t1);
     bwd(son(nb, 1, 1), Y1);
-    pmul(Y0, son(nb, 0, 1), Y1, -1.0, false);
+    if (solve_mv) hupd(Y0, son(nb, 0, 1), Y1);
+    else pmul(Y0, son(nb, 0, 1), Y1, -1.0, false);
     bwd(son(nb, 0, 0), Y0);
   }
 
@@ -1190,6 +1292,12 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   cur = align256(cur + (uint64_t)4 * nr * 8 + 64);
   p.off_perm = cur;
   cur = align256(cur + (uint64_t)n * 8);
+  // solve: one V^T X slot per low-rank block of the factor
+  for (auto& b : p.blk)
+    if (b.kind == 'R') {
+      b.offT = cur;
+      cur = align256(cur + (uint64_t)prm.cap_f * nr * 8);
+    }
   // matvec T buffers (k_mv x nrhs per low-rank block)
   p.off_mvT = cur;
   {
@@ -1285,8 +1393,8 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   {
     Builder B(p, p.ssched);
     B.P_dt = prm.mixed ? DT_F32 : DT_F64;
-    B.want_cost = false;
-    B.want_edges = false;
+    B.solve_mv = true;
+    B.cost_cur = 0;
     for (auto& b : p.blk) {
       if (b.kind == 'F') b.objF = B.new_obj(-1, true);
       else {
@@ -1307,6 +1415,9 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     B.fwd(p.broot, Y);
     B.bwd(p.broot, Y);
     B.finish();
+    p.off_cost_s = cur;
+    for (auto& op : p.ssched.ops) op.cost += p.off_cost_s;
+    cur = align256(cur + (uint64_t)p.ssched.ops.size() * kCostRecBytes);
   }
   p.off_ops_f = cur;
   cur = align256(cur + p.fsched.ops.size() * sizeof(Op));
@@ -1316,6 +1427,10 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   cur = align256(cur + std::max<size_t>(1, p.fsched.terms.size()) * sizeof(Term));
   for (auto& op : p.fsched.ops)
     if (op.type == OP_TRUNC) op.p[2].ptr = p.off_terms_f;
+  p.off_terms_s = cur;
+  cur = align256(cur + std::max<size_t>(1, p.ssched.terms.size()) * sizeof(Term));
+  for (auto& op : p.ssched.ops)
+    if (op.type == OP_MVROW) op.p[2].ptr = p.off_terms_s;
   {
     const uint64_t N = p.fsched.ops.size();
     p.off_df_succ_off = cur;
@@ -1331,6 +1446,23 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     p.off_df_ready0 = cur;
     cur = align256(cur + std::max<uint64_t>(1, p.fsched.ready0.size()) * 4);
     p.off_df_ctrl = cur;
+    cur = align256(cur + 256);
+  }
+  {
+    const uint64_t N = p.ssched.ops.size();
+    p.off_dfs_succ_off = cur;
+    cur = align256(cur + (N + 1) * 4);
+    p.off_dfs_succ = cur;
+    cur = align256(cur + std::max<uint64_t>(1, p.ssched.succ.size()) * 4);
+    p.off_dfs_indeg0 = cur;
+    cur = align256(cur + std::max<uint64_t>(1, N) * 4);
+    p.off_dfs_indeg = cur;
+    cur = align256(cur + std::max<uint64_t>(1, N) * 4);
+    p.off_dfs_queue = cur;
+    cur = align256(cur + std::max<uint64_t>(1, N) * 4);
+    p.off_dfs_ready0 = cur;
+    cur = align256(cur + std::max<uint64_t>(1, p.ssched.ready0.size()) * 4);
+    p.off_dfs_ctrl = cur;
     cur = align256(cur + 256);
   }
   p.off_mv_lr = cur;

@@ -45,6 +45,7 @@ struct LBlock {
   int m, n;
   uint64_t offF = 0;       // dense (FP64, ld m)
   uint64_t offU = 0, offV = 0, offRank = 0;   // factor copy (capacity cap_f)
+  uint64_t offT = 0;       // solve: V^T X of this block (cap_f x max_nrhs, FP64)
   int objF = -1, objU = -1, objV = -1, objRank = -1;
   // matvec copy
   uint64_t mvU = 0, mvV = 0;
@@ -61,7 +62,7 @@ struct Schedule {
   std::vector<Op> ops;     // sorted by (wave, type); pointers are byte offsets
   std::vector<Batch> batches;      // one per (wave, type)
   std::vector<Batch> waves_list;   // one per wave (all types)
-  std::vector<Term> terms;         // term table of the truncation ops
+  std::vector<Term> terms;         // term table of the truncation / row-update ops
   int waves = 0;
   // dependency graph in schedule order (for the dataflow executor):
   // successors of op i are succ[succ_off[i] .. succ_off[i+1]), indeg0[i]
@@ -87,15 +88,19 @@ struct Plan {
   uint64_t off_piv = 0;
   uint64_t off_mv = 0, size_mv = 0;
   uint64_t off_scratch = 0, size_scratch = 0;
-  uint64_t off_cost = 0;           // per-op {flops, bytes} (doubles)
+  uint64_t off_cost = 0;           // per-op records of the factor schedule
+  uint64_t off_cost_s = 0;         // per-op records of the solve schedule
   uint64_t off_ws = 0;             // solve / refinement workspace
   uint64_t off_nrhs = 0;           // int32 nrhs slot used by solve panels
   uint64_t off_Y = 0, off_X = 0, off_B = 0, off_eta = 0;
   uint64_t off_mvT = 0;
-  uint64_t off_ops_f = 0, off_ops_s = 0, off_terms_f = 0;
+  uint64_t off_ops_f = 0, off_ops_s = 0, off_terms_f = 0, off_terms_s = 0;
   // dataflow executor state of the factor schedule
   uint64_t off_df_succ_off = 0, off_df_succ = 0, off_df_indeg0 = 0, off_df_indeg = 0,
            off_df_queue = 0, off_df_ready0 = 0, off_df_ctrl = 0;
+  // the same arrays for the solve schedule
+  uint64_t off_dfs_succ_off = 0, off_dfs_succ = 0, off_dfs_indeg0 = 0, off_dfs_indeg = 0,
+           off_dfs_queue = 0, off_dfs_ready0 = 0, off_dfs_ctrl = 0;
   uint64_t off_mv_lr = 0, off_mv_terms = 0, off_mv_rows = 0, off_perm = 0;
   uint64_t total = 0;
 

@@ -289,16 +289,20 @@ def test_graph_replays_match_eager(P, prec):
 @pytest.mark.parametrize("level,prec,graph", [(3, 0, 0), (3, 1, 1), (4, 1, 1)])
 def test_dataflow_executor_matches_waves(P, level, prec, graph):
     """The persistent dataflow executor runs the same ops on the same inputs
-    (every read/write conflict is an edge), so its factors are bitwise the
-    wave executor's; replayed twice."""
+    (every read/write conflict is an edge, and writers of the same rows keep
+    their program order), so its factors and its solutions (with refinement)
+    are bitwise the wave executor's; replayed twice."""
     import torch
     xyz, area, h = _hlu(P, level, 32, eps=1e-6, precision=prec, max_nrhs=4)
+    b = torch.tensor(rhs_normal(5, h.n, 3), device="cuda")
     h.set_graph(graph)
     h.set_executor(0)
     h.factor()
     h.sync()
     L0, U0 = h.export_factors()
     p0 = h.export_pivots()
+    x0 = h.solve(b).cpu().numpy()
+    st0, inf0 = h.sync(check=False)
     h.set_executor(1)
     for rep in range(2):
         h.reset()
@@ -308,6 +312,10 @@ def test_dataflow_executor_matches_waves(P, level, prec, graph):
         L, U = h.export_factors()
         assert np.array_equal(h.export_pivots(), p0)
         assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
+        x = h.solve(b).cpu().numpy()
+        st, inf = h.sync(check=False)
+        assert st == st0 and inf.iters == inf0.iters, (rep, P.lib.hlu_last_error())
+        assert np.array_equal(x, x0), rep
 
 
 def test_refinement_not_converged_is_reported(P):
