@@ -176,7 +176,7 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
         const hlu::PRef& Y = o.p[3];
         if (!panel_ok(Y, T, why)) return bad(why.c_str());
         if (Y.rows > 64 || Y.cols > 64 || Y.dt != hlu::DT_F64 || Y.trans) return bad("row target");
-        if (o.i1 < 1 || o.i0 < 0 || (size_t)o.i0 + o.i1 > sc.terms.size())
+        if (o.i1 < 1 || o.i1 > 256 || o.i0 < 0 || (size_t)o.i0 + o.i1 > sc.terms.size())
           return bad("row update term list");
         if (o.p[2].ptr != p.off_terms_s) return bad("row update term table");
         for (int t = o.i0; t < o.i0 + o.i1; ++t) {

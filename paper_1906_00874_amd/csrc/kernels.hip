@@ -1305,77 +1305,115 @@ __device__ void d_mvt(const Op& op) {
 }
 
 // Y += d0 * sum_t X_t Y_t over the terms of one leaf row cluster (Y: rows
-// <= 64 x nrhs FP64; X_t: rows x kk, kk = live columns <= 64; Y_t: FP64,
-// ld >= kk), summed in term order; the next term's operands are prefetched
-// into registers while the current term is multiplied.
-#define LDS_MVROW (2 * 64 * 65 * 8)
+// <= 64 x nrhs <= 64, FP64; X_t: rows x kk_t, kk_t = live columns <= 64,
+// FP32 or FP64; Y_t: FP64, ld >= kk_t; all plain column-major, checked on
+// the host).  The work items are the 16-column chunks of the terms, dealt to
+// the four wavefronts in turn; a wavefront stages its chunk in its own LDS
+// slice (no block barrier inside the loop) and lane r accumulates row r of
+// its partial in registers.  The four partials are summed once at the end.
+#define MVR_TMAX 256
+#define MVR_STAGE (4 * (64 * 17 + 16 * 65) * 8)
+#define LDS_MVROW (MVR_STAGE + 2 * MVR_TMAX * 4)
 __device__ void d_mvrow(const Op& op) {
   char* const smem = hlu_lds;
   const PRef Y = op.p[3];
   const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
-  const int nt = op.i1, rows = Y.rows, nr = pcols(Y);
-  double (*sa)[65] = reinterpret_cast<double (*)[65]>(smem);
-  double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
-  const int tid = threadIdx.x, i = tid & 63, c0 = (tid >> 6) * 16;
-  double o[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) o[v] = 0.0;
-  double ra[16], rb[16];
-  int kk = 0;
-  // terms are plain column-major panels (checked on the host): X_t FP32 or
-  // FP64, Y_t FP64; thread (r, cq) loads elements (r, cq + 4u)
-  const int r = tid & 63, cq = tid >> 6;
-  auto fetch = [&](int t) {
-    const Term* tp = terms + t;
-    kk = pcols(tp->X);
-    const int lda = tp->X.ld, ldb = tp->Y.ld;
-    const bool a64 = tp->X.dt == DT_F64;
-    const double* pb = reinterpret_cast<const double*>(tp->Y.ptr) + r + (size_t)cq * ldb;
-    if (a64) {
-      const double* pa = reinterpret_cast<const double*>(tp->X.ptr) + r + (size_t)cq * lda;
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        ra[u] = (r < rows && cq + 4 * u < kk) ? pa[(size_t)(4 * u) * lda] : 0.0;
-    } else {
-      const float* pa = reinterpret_cast<const float*>(tp->X.ptr) + r + (size_t)cq * lda;
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        ra[u] = (r < rows && cq + 4 * u < kk) ? (double)pa[(size_t)(4 * u) * lda] : 0.0;
+  const int nt = min(op.i1, MVR_TMAX), rows = Y.rows, nr = pcols(Y);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  double (*sa)[17] = reinterpret_cast<double (*)[17]>(smem + w * (64 * 17 + 16 * 65) * 8);
+  double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + w * (64 * 17 + 16 * 65) * 8 +
+                                                      64 * 17 * 8);
+  int* kk = reinterpret_cast<int*>(smem + MVR_STAGE);
+  int* first = kk + MVR_TMAX;   // first work item of each term
+  for (int t = tid; t < nt; t += NT) kk[t] = pcols(terms[t].X);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int t = 0; t < nt; ++t) {
+      first[t] = acc;
+      acc += (kk[t] + 15) >> 4;
     }
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      rb[u] = (r < kk && cq + 4 * u < nr) ? pb[(size_t)(4 * u) * ldb] : 0.0;
-  };
-  fetch(0);
-  for (int t = 0; t < nt; ++t) {
-    const int kt = kk;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      sa[r][cq + 4 * u] = ra[u];
-      sb[r][cq + 4 * u] = rb[u];
-    }
-    __syncthreads();
-    if (t + 1 < nt) fetch(t + 1);
-    for (int c = 0; c < kt; ++c) {
-      const double a = sa[i][c];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) o[v] += a * sb[c][c0 + v];
-    }
-    __syncthreads();
   }
-  if (i < rows) {
-    double* y = reinterpret_cast<double*>(Y.ptr);
+  __syncthreads();
+  const int nitems = nt > 0 ? first[nt - 1] + ((kk[nt - 1] + 15) >> 4) : 0;
+  // item -> (term, first column): a short scan over the terms
+  auto locate = [&](int item, int& t, int& c0) {
+    t = 0;
+    while (t + 1 < nt && first[t + 1] <= item) ++t;
+    c0 = (item - first[t]) * 16;
+  };
+  double (*pb2)[33] = reinterpret_cast<double (*)[33]>(smem);   // 2 x 64 rows x 32
+  // right-hand sides in groups of 32 (one group when nrhs <= 32)
+  for (int h0 = 0; h0 < nr; h0 += 32) {
+    const int nh = min(32, nr - h0);
+    double o[32];
 #pragma unroll
-    for (int v = 0; v < 16; ++v)
-      if (c0 + v < nr) y[i + (size_t)(c0 + v) * Y.ld] += op.d0 * o[v];
+    for (int v = 0; v < 32; ++v) o[v] = 0.0;
+    for (int item = w; item < nitems; item += 4) {
+      int t, c0;
+      locate(item, t, c0);
+      const Term* tp = terms + t;
+      const int kc = min(16, kk[t] - c0);
+      const int lda = tp->X.ld, ldb = tp->Y.ld;
+      double ra[16], rb[16];
+      // A chunk: lane = row, 16 columns; B chunk: lane = right-hand side (< nh), 16 rows
+      if (tp->X.dt == DT_F64) {
+        const double* pa = reinterpret_cast<const double*>(tp->X.ptr) + lane + (size_t)c0 * lda;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ra[u] = (lane < rows && u < kc) ? pa[(size_t)u * lda] : 0.0;
+      } else {
+        const float* pa = reinterpret_cast<const float*>(tp->X.ptr) + lane + (size_t)c0 * lda;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          ra[u] = (lane < rows && u < kc) ? (double)pa[(size_t)u * lda] : 0.0;
+      }
+      const double* pb = reinterpret_cast<const double*>(tp->Y.ptr) + c0 + (size_t)(h0 + lane) * ldb;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) rb[u] = (lane < nh && u < kc) ? pb[u] : 0.0;
+      // the slices were last read by this wavefront's previous chunk (program order)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        sa[lane][u] = ra[u];
+        sb[u][lane] = rb[u];
+      }
+      for (int c = 0; c < kc; ++c) {
+        const double a = sa[lane][c];
+#pragma unroll
+        for (int v = 0; v < 32; ++v) o[v] += a * sb[c][v];
+      }
+    }
+    // sum the four partials pairwise through the (now free) staging area:
+    // wavefronts 2, 3 hand theirs to 0, 1, then 1 to 0, which updates Y
+    __syncthreads();
+    if (w >= 2) {
+#pragma unroll
+      for (int v = 0; v < 32; ++v) pb2[(w - 2) * 64 + lane][v] = o[v];
+    }
+    __syncthreads();
+    if (w < 2) {
+#pragma unroll
+      for (int v = 0; v < 32; ++v) o[v] += pb2[w * 64 + lane][v];
+    }
+    __syncthreads();
+    if (w == 1) {
+#pragma unroll
+      for (int v = 0; v < 32; ++v) pb2[lane][v] = o[v];
+    }
+    __syncthreads();
+    if (w == 0 && lane < rows) {
+      double* y = reinterpret_cast<double*>(Y.ptr) + lane + (size_t)h0 * Y.ld;
+#pragma unroll
+      for (int v = 0; v < 32; ++v)
+        if (v < nh) y[(size_t)v * Y.ld] += op.d0 * (o[v] + pb2[lane][v]);
+    }
+    __syncthreads();
   }
   if (tid == 0 && op.cost) {
     double fl = 0.0, by = 16.0 * rows * nr;
     for (int t = 0; t < nt; ++t) {
       const PRef A = terms[t].X;
-      const int k = pcols(A);
-      fl += 2.0 * rows * k * nr;
-      by += (A.dt == DT_F64 ? 8.0 : 4.0) * rows * k + 8.0 * k * nr;
+      fl += 2.0 * rows * kk[t] * nr;
+      by += (A.dt == DT_F64 ? 8.0 : 4.0) * rows * kk[t] + 8.0 * kk[t] * nr;
     }
     put_cost(op, fl, by);
   }

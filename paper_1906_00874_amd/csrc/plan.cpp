@@ -839,9 +839,15 @@ class Builder {
           acc.push_back(acc_of(Xs, false));
         }
       }
-      op.i1 = (int)S.terms.size() - op.i0;
-      if (op.i1 == 0) continue;
-      emit(op, acc);
+      // at most 256 terms per op (the row kernel's table); longer lists
+      // become several ops on the same rows, ordered by their writes
+      const int tend = (int)S.terms.size();
+      for (int t0 = op.i0; t0 < tend; t0 += 256) {
+        Op o2 = op;
+        o2.i0 = t0;
+        o2.i1 = std::min(256, tend - t0);
+        emit(o2, acc);
+      }
     }
   }
 
