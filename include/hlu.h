@@ -143,9 +143,31 @@ hlu_status hlu_set_executor(hlu_handle h, int mode);
 hlu_status hlu_factor_profile(hlu_handle h, void* stream, double* ms_per_type,
                               int64_t* launches_per_type);
 
-/* Factor `count` handles with their schedules merged wave by wave, so ops
- * of every matrix in a wave share one launch per kernel type. */
-hlu_status hlu_factor_batched(hlu_handle* hs, int count, void* stream);
+/* Batched factorisation of independent matrices: the union of the handles'
+ * factor schedules (the recursive H-LU of Sec. 3.1 for each matrix) run by
+ * one launch of the persistent dataflow executor, so ops of every matrix
+ * share the machine as soon as their own predecessors are done.
+ *
+ * hlu_batch_create: host only; `hs` are planned handles, each listed at most
+ * once (a handle's in-degree counters are consumed by the run, so a handle
+ * must not be factored elsewhere while its batch runs).  The batch copies
+ * the handle list; the handles must outlive it.
+ * hlu_batch_required_bytes: device bytes of the batch workspace (part table,
+ * queue over all ops, initial ready list).
+ * hlu_batch_bind: caller-owned, 256-byte aligned device buffer; every handle
+ * must already be bound.  Synchronous.
+ * hlu_batch_factor: every handle assembled and not factored (hlu_reset in
+ * between); asynchronous on `stream`.  Zero pivots are reported per handle
+ * by hlu_sync(h).
+ * hlu_batch_sync: waits for `stream`; HLU_ERR_DEVICE if the executor
+ * stopped on its time limit or a queue overflow. */
+typedef struct hlu_batch_s* hlu_batch;
+hlu_status hlu_batch_create(const hlu_handle* hs, int count, hlu_batch* out);
+size_t hlu_batch_required_bytes(hlu_batch b);
+hlu_status hlu_batch_bind(hlu_batch b, void* dev_ptr, size_t bytes);
+hlu_status hlu_batch_factor(hlu_batch b, void* stream);
+hlu_status hlu_batch_sync(hlu_batch b, void* stream);
+void hlu_batch_destroy(hlu_batch b);
 
 /* x = A^{-1} b for nrhs right-hand sides (b_dev, x_dev: n x nrhs, leading
  * dimension ld, original order; they may alias).  With refine_tol > 0 the

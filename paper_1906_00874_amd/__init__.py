@@ -6,10 +6,10 @@ every step on the device).  PyTorch provides the device buffer and the
 stream.  If the shared library is missing the import fails loudly; there is
 no fallback.
 """
-from .binding import (HLU, HLUError, Params, Info, PlanStats, lib, build_lib_path,
+from .binding import (HLU, Batch, HLUError, Params, Info, PlanStats, lib, build_lib_path,
                       getrf_batched, truncate_add, KERNEL_WEIGHTED, KERNEL_POINT,
                       PREC_FP64, PREC_MIXED)
 
-__all__ = ["HLU", "HLUError", "Params", "Info", "PlanStats", "lib", "build_lib_path",
+__all__ = ["HLU", "Batch", "HLUError", "Params", "Info", "PlanStats", "lib", "build_lib_path",
            "getrf_batched", "truncate_add", "KERNEL_WEIGHTED", "KERNEL_POINT",
            "PREC_FP64", "PREC_MIXED"]

@@ -58,7 +58,12 @@ _sig = {
     "hlu_assemble": (C.c_int, [_P, _P]),
     "hlu_reset": (C.c_int, [_P, _P]),
     "hlu_factor": (C.c_int, [_P, _P]),
-    "hlu_factor_batched": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "hlu_batch_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(_P)]),
+    "hlu_batch_required_bytes": (C.c_size_t, [_P]),
+    "hlu_batch_bind": (C.c_int, [_P, _P, C.c_size_t]),
+    "hlu_batch_factor": (C.c_int, [_P, _P]),
+    "hlu_batch_sync": (C.c_int, [_P, _P]),
+    "hlu_batch_destroy": (None, [_P]),
     "hlu_factor_profile": (C.c_int, [_P, _P, _P, _P]),
     "hlu_set_graph": (C.c_int, [_P, C.c_int]),
     "hlu_set_executor": (C.c_int, [_P, C.c_int]),
@@ -287,9 +292,32 @@ class HLU:
         return p
 
 
-def factor_batched(hs, stream=None):
-    arr = (C.c_void_p * len(hs))(*[h.h.value for h in hs])
-    _check(lib.hlu_factor_batched(arr, len(hs), _stream(stream)))
+class Batch:
+    """Batched factorisation of several HLU handles by one persistent launch
+    (hlu_batch_*); the workspace is a torch uint8 tensor."""
+
+    def __init__(self, handles, device="cuda"):
+        self.handles = list(handles)   # keep them alive as long as the batch
+        arr = (_P * len(self.handles))(*[h.h for h in self.handles])
+        b = C.c_void_p()
+        _check(lib.hlu_batch_create(arr, len(self.handles), C.byref(b)))
+        self.b = b
+        nb = int(lib.hlu_batch_required_bytes(self.b))
+        self.buf = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        ptr = (self.buf.data_ptr() + 255) & ~255
+        _check(lib.hlu_batch_bind(self.b, C.c_void_p(ptr), nb))
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and b.value:
+            lib.hlu_batch_destroy(b)
+            self.b = None
+
+    def factor(self, stream=None):
+        _check(lib.hlu_batch_factor(self.b, _stream(stream)))
+
+    def sync(self, stream=None):
+        _check(lib.hlu_batch_sync(self.b, _stream(stream)))
 
 
 def getrf_batched(a, stream=None):

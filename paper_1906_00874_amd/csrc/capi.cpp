@@ -28,14 +28,13 @@ extern "C" size_t hlu_lds_bytes(int type);
 extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* starts,
                                            const int* counts, const size_t* lds, int nwaves,
                                            int32_t* status, hipGraphExec_t* out);
-extern "C" hipError_t hlu_launch_dataflow(const void* ops, const int* succ_off, const int* succ,
-                                          const int* indeg0, int* indeg, int* queue,
+extern "C" hipError_t hlu_launch_dataflow(const void* parts, int np, int* queue,
                                           const int* ready0, int nready, int* ctrl, int n,
-                                          int workers, long long timeout, hipStream_t s);
-extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off, const int* succ,
-                                         const int* indeg0, int* indeg, int* queue,
-                                         const int* ready0, int nready, int* ctrl, int n,
-                                         int workers, long long timeout, int32_t* status,
+                                          int workers, long long timeout, int32_t* status,
+                                          hipStream_t s);
+extern "C" hipError_t hlu_build_df_graph(const void* parts, int np, int* queue, const int* ready0,
+                                         int nready, int* ctrl, int n, int workers,
+                                         long long timeout, int32_t* status,
                                          hipGraphExec_t* out);
 
 namespace {
@@ -198,9 +197,11 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
 }  // namespace
 
 // Device offsets of one schedule's dataflow arrays.
+// (the schedule's DfPart descriptor lives at ctrl + 64)
 struct DfArrays {
   const hlu::Schedule* sc;
   uint64_t ops, succ_off, succ, indeg0, indeg, queue, ready0, ctrl;
+  uint64_t part() const { return ctrl + 64; }
 };
 static DfArrays df_factor(const hlu::Plan& p) {
   return {&p.fsched, p.off_ops_f, p.off_df_succ_off, p.off_df_succ, p.off_df_indeg0,
@@ -413,6 +414,15 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
       HIPCHK(hipMemcpy(d + da.ready0, sc.ready0.data(), sc.ready0.size() * 4,
                        hipMemcpyHostToDevice));
     HIPCHK(hipMemset(d + da.ctrl, 0, 256));
+    hlu::DfPart pt;
+    pt.ops = base + da.ops;
+    pt.succ_off = base + da.succ_off;
+    pt.succ = base + da.succ;
+    pt.indeg0 = base + da.indeg0;
+    pt.indeg = base + da.indeg;
+    pt.base = 0;
+    pt.n = (int32_t)sc.ops.size();
+    HIPCHK(hipMemcpy(d + da.part(), &pt, sizeof(pt), hipMemcpyHostToDevice));
   }
   std::vector<hlu::MvLR> lr = p.mv_lr;
   for (auto& e : lr) {
@@ -564,25 +574,20 @@ static hlu_status run_dataflow(hlu_handle h, const DfArrays& da, hipStream_t s,
   const long long timeout = 20 * tps;   // no single wait may exceed 20 s
   const bool factor = da.sc == &p.fsched;
   int32_t* status = factor ? (int32_t*)(b + p.off_status) : nullptr;
-  const int* succ_off = (const int*)(b + da.succ_off);
-  const int* succ = (const int*)(b + da.succ);
-  const int* indeg0 = (const int*)(b + da.indeg0);
-  int* indeg = (int*)(b + da.indeg);
   int* queue = (int*)(b + da.queue);
   const int* ready0 = (const int*)(b + da.ready0);
   int* ctrl = (int*)(b + da.ctrl);
+  const void* part = b + da.part();
   const int n = (int)sc.ops.size(), nready = (int)sc.ready0.size();
   if (n == 0) return HLU_OK;
   if (h->use_graph) {
     if (!*graph)
-      HIPCHK(hlu_build_df_graph(b + da.ops, succ_off, succ, indeg0, indeg, queue, ready0, nready,
-                                ctrl, n, cus, timeout, status, graph));
+      HIPCHK(hlu_build_df_graph(part, 1, queue, ready0, nready, ctrl, n, cus, timeout, status,
+                                graph));
     HIPCHK(hipGraphLaunch(*graph, s));
     return HLU_OK;
   }
-  if (status) HIPCHK(hlu_launch_set_int(status, 0, s));
-  HIPCHK(hlu_launch_dataflow(b + da.ops, succ_off, succ, indeg0, indeg, queue, ready0, nready,
-                             ctrl, n, cus, timeout, s));
+  HIPCHK(hlu_launch_dataflow(part, 1, queue, ready0, nready, ctrl, n, cus, timeout, status, s));
   return HLU_OK;
 }
 
@@ -653,34 +658,137 @@ hlu_status hlu_factor_profile(hlu_handle h, void* stream, double* ms_per_type,
   return HLU_OK;
 }
 
-hlu_status hlu_factor_batched(hlu_handle* hs, int count, void* stream) {
-  if (!hs || count < 1) return fail(HLU_ERR_ARG, "bad handle list");
-  // schedules of different handles live in different buffers, so the merged
-  // execution interleaves their batches wave by wave on the stream
-  int maxw = 0;
+// ---- batched factorisation: the union of several handles' factor
+// schedules run by one persistent executor launch.  The batch owns only the
+// part table, a queue over all ops and the initial ready list; every op keeps
+// reading and writing its own handle's buffer.
+struct hlu_batch_s {
+  std::vector<hlu_handle> hs;
+  std::vector<int32_t> base;
+  std::vector<int32_t> ready0;    // global indices, the handles' ready lists interleaved
+  int64_t ntot = 0;
+  uint64_t off_parts = 0, off_queue = 0, off_ready0 = 0, off_ctrl = 0, total = 0;
+  char* dev = nullptr;
+};
+
+hlu_status hlu_batch_create(const hlu_handle* hs, int count, hlu_batch* out) {
+  if (!hs || !out || count < 1) return fail(HLU_ERR_ARG, "bad handle list");
+  *out = nullptr;
+  auto* b = new (std::nothrow) hlu_batch_s;
+  if (!b) return fail(HLU_ERR_NOMEM, "host allocation failed");
+  int64_t tot = 0;
   for (int i = 0; i < count; ++i) {
-    if (!hs[i]) return fail(HLU_ERR_ARG, "NULL handle");
-    if (!hs[i]->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
-    if (hs[i]->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
-    maxw = std::max(maxw, hs[i]->plan.fsched.waves);
+    if (!hs[i]) {
+      delete b;
+      return fail(HLU_ERR_ARG, "NULL handle");
+    }
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) {
+        delete b;
+        return fail(HLU_ERR_ARG, "a handle appears twice in the batch");
+      }
+    b->hs.push_back(hs[i]);
+    b->base.push_back((int32_t)tot);
+    tot += (int64_t)hs[i]->plan.fsched.ops.size();
+    if (tot >= (int64_t)1 << 31) {
+      delete b;
+      return fail(HLU_ERR_ARG, "too many ops in one batch");
+    }
   }
-  hipStream_t s = (hipStream_t)stream;
+  b->ntot = tot;
+  // round-robin over the handles so that every matrix starts at once
   std::vector<size_t> cur(count, 0);
-  for (int i = 0; i < count; ++i)
-    HIPCHK(hlu_launch_set_int((int32_t*)(hs[i]->base + hs[i]->plan.off_status), 0, s));
-  for (int w = 0; w < maxw; ++w)
+  for (bool more = true; more;) {
+    more = false;
     for (int i = 0; i < count; ++i) {
-      const hlu::Schedule& sc = hs[i]->plan.fsched;
-      const char* ops = hs[i]->base + hs[i]->plan.off_ops_f;
-      while (cur[i] < sc.waves_list.size() && sc.waves_list[cur[i]].wave == w) {
-        const hlu::Batch& bt = sc.waves_list[cur[i]++];
-        HIPCHK(hlu_launch_wave(ops + (size_t)bt.start * sizeof(hlu::Op), bt.count,
-                               wave_lds(bt.mask), s));
+      const auto& r = hs[i]->plan.fsched.ready0;
+      if (cur[i] < r.size()) {
+        b->ready0.push_back(b->base[i] + r[cur[i]++]);
+        more = true;
       }
     }
-  for (int i = 0; i < count; ++i) hs[i]->factored = true;
+  }
+  uint64_t c = 0;
+  auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+  b->off_parts = c;
+  c = al(c + (uint64_t)count * sizeof(hlu::DfPart));
+  b->off_queue = c;
+  c = al(c + (uint64_t)std::max<int64_t>(1, tot) * 4);
+  b->off_ready0 = c;
+  c = al(c + (uint64_t)std::max<size_t>(1, b->ready0.size()) * 4);
+  b->off_ctrl = c;
+  c = al(c + 256);
+  b->total = c;
+  *out = b;
   return HLU_OK;
 }
+
+size_t hlu_batch_required_bytes(hlu_batch b) { return b ? (size_t)b->total : 0; }
+
+hlu_status hlu_batch_bind(hlu_batch b, void* dev_ptr, size_t bytes) {
+  if (!b || !dev_ptr) return fail(HLU_ERR_ARG, "NULL argument");
+  if (bytes < b->total) return fail(HLU_ERR_ARG, "buffer smaller than hlu_batch_required_bytes");
+  if (((uint64_t)dev_ptr & 255) != 0) return fail(HLU_ERR_ARG, "buffer not 256-byte aligned");
+  std::vector<hlu::DfPart> parts(b->hs.size());
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    hlu_handle h = b->hs[i];
+    if (!h->base) return fail(HLU_ERR_STATE, "every handle must be bound first");
+    const hlu::Plan& p = h->plan;
+    const uint64_t hb = (uint64_t)h->base;
+    parts[i].ops = hb + p.off_ops_f;
+    parts[i].succ_off = hb + p.off_df_succ_off;
+    parts[i].succ = hb + p.off_df_succ;
+    parts[i].indeg0 = hb + p.off_df_indeg0;
+    parts[i].indeg = hb + p.off_df_indeg;
+    parts[i].base = b->base[i];
+    parts[i].n = (int32_t)p.fsched.ops.size();
+  }
+  char* d = (char*)dev_ptr;
+  HIPCHK(hipMemcpy(d + b->off_parts, parts.data(), parts.size() * sizeof(hlu::DfPart),
+                   hipMemcpyHostToDevice));
+  if (!b->ready0.empty())
+    HIPCHK(hipMemcpy(d + b->off_ready0, b->ready0.data(), b->ready0.size() * 4,
+                     hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(d + b->off_ctrl, 0, 256));
+  b->dev = d;
+  return HLU_OK;
+}
+
+hlu_status hlu_batch_factor(hlu_batch b, void* stream) {
+  if (!b) return fail(HLU_ERR_ARG, "NULL batch");
+  if (!b->dev) return fail(HLU_ERR_STATE, "hlu_batch_bind first");
+  for (hlu_handle h : b->hs) {
+    if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
+    if (h->factored) return fail(HLU_ERR_STATE, "already factored: hlu_reset first");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int cus = 0;
+  long long tps = 0;
+  hlu_status st = device_facts(&cus, &tps);
+  if (st != HLU_OK) return st;
+  for (hlu_handle h : b->hs)
+    HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
+  HIPCHK(hlu_launch_dataflow(b->dev + b->off_parts, (int)b->hs.size(), (int*)(b->dev + b->off_queue),
+                             (const int*)(b->dev + b->off_ready0), (int)b->ready0.size(),
+                             (int*)(b->dev + b->off_ctrl), (int)b->ntot, cus, 20 * tps, nullptr,
+                             s));
+  for (hlu_handle h : b->hs) h->factored = true;
+  return HLU_OK;
+}
+
+hlu_status hlu_batch_sync(hlu_batch b, void* stream) {
+  if (!b) return fail(HLU_ERR_ARG, "NULL batch");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  if (!b->dev) return HLU_OK;
+  int32_t err = 0;
+  HIPCHK(hipMemcpy(&err, b->dev + b->off_ctrl + 8, 4, hipMemcpyDeviceToHost));
+  if (err)
+    return fail(HLU_ERR_DEVICE, err == 2 ? "dataflow executor: queue overflow"
+                                         : "dataflow executor: a wait exceeded its time limit");
+  return HLU_OK;
+}
+
+void hlu_batch_destroy(hlu_batch b) { delete b; }
 
 hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs, int64_t ld,
                      void* stream) {

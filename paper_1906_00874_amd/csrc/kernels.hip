@@ -1595,11 +1595,24 @@ __global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
 // the queue has one slot per op; a workgroup that takes a slot >= n exits.
 // Waits are bounded by `timeout` ticks of the constant-rate wall clock, after
 // which the error flag is raised and every waiting workgroup exits.
-__global__ void k_df_reset(int* indeg, const int* indeg0, int* queue, const int* ready0,
-                           int nready, int n, int* ctrl) {
+// part owning global op index g (the last part whose base is <= g)
+__device__ __forceinline__ int df_part(const DfPart* parts, int np, int g) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (parts[mid].base <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_df_reset(const DfPart* parts, int np, int* queue, const int* ready0, int nready,
+                           int n, int* ctrl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    indeg[i] = indeg0[i];
+    const DfPart& pt = parts[df_part(parts, np, i)];
+    const int l = i - pt.base;
+    reinterpret_cast<int*>(pt.indeg)[l] = reinterpret_cast<const int*>(pt.indeg0)[l];
     queue[i] = i < nready ? ready0[i] : -1;
   }
   if (i == 0) {
@@ -1609,9 +1622,7 @@ __global__ void k_df_reset(int* indeg, const int* indeg0, int* queue, const int*
   }
 }
 
-__global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
-                                                 const int* __restrict__ succ_off,
-                                                 const int* __restrict__ succ, int* indeg,
+__global__ void __launch_bounds__(NT) k_dataflow(const DfPart* __restrict__ parts, int np,
                                                  int* queue, int* ctrl, int n,
                                                  long long timeout) {
   __shared__ int s_op;
@@ -1643,9 +1654,11 @@ __global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
       s_op = v;
     }
     __syncthreads();
-    const int idx = s_op;
-    if (idx < 0) break;
-    run_op(ops[idx]);
+    const int g = s_op;
+    if (g < 0) break;
+    const DfPart& pt = parts[np == 1 ? 0 : df_part(parts, np, g)];
+    const int idx = g - pt.base;
+    run_op(reinterpret_cast<const Op*>(pt.ops)[idx]);
     __syncthreads();
     if (tid == 0) {
       // one release fence publishes the op's writes; the in-degree
@@ -1654,6 +1667,9 @@ __global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
       // read-modify-writes, so their fences synchronise with it) and then
       // pushes the successor with a release store.
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const int* succ_off = reinterpret_cast<const int*>(pt.succ_off);
+      const int* succ = reinterpret_cast<const int*>(pt.succ);
+      int* indeg = reinterpret_cast<int*>(pt.indeg);
       for (int e = succ_off[idx]; e < succ_off[idx + 1]; ++e) {
         const int t = succ[e];
         if (__hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
@@ -1661,7 +1677,8 @@ __global__ void __launch_bounds__(NT) k_dataflow(const Op* __restrict__ ops,
           const int slot =
               __hip_atomic_fetch_add(&ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (slot < n)
-            __hip_atomic_store(&queue[slot], t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue[slot], pt.base + t, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
           else
             __hip_atomic_store(&ctrl[2], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1721,25 +1738,30 @@ static hipError_t df_attr() {
   return e;
 }
 
-extern "C" hipError_t hlu_launch_dataflow(const void* ops, const int* succ_off, const int* succ,
-                                          const int* indeg0, int* indeg, int* queue,
+// Runs the union of np schedule parts (n ops in all) with `workers`
+// persistent workgroups: reset of the in-degrees and the queue (seeded with
+// the nready globally numbered ops in ready0), then the executor.  When
+// `status` is given, it is cleared first.
+extern "C" hipError_t hlu_launch_dataflow(const void* parts, int np, int* queue,
                                           const int* ready0, int nready, int* ctrl, int n,
-                                          int workers, long long timeout, hipStream_t s) {
+                                          int workers, long long timeout, int32_t* status,
+                                          hipStream_t s) {
   hipError_t e = df_attr();
   if (e != hipSuccess) return e;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hlu::k_df_reset, dim3((n + 255) / 256), dim3(256), 0, s, indeg, indeg0,
-                     queue, ready0, nready, n, ctrl);
-  hipLaunchKernelGGL(hlu::k_dataflow, dim3(workers), dim3(NT), sizeof(hlu::TruncShared), s,
-                     reinterpret_cast<const hlu::Op*>(ops), succ_off, succ, indeg, queue, ctrl, n,
-                     timeout);
+  const hlu::DfPart* pp = reinterpret_cast<const hlu::DfPart*>(parts);
+  if (status) hipLaunchKernelGGL(hlu::k_set_int, dim3(1), dim3(64), 0, s, status, 0);
+  hipLaunchKernelGGL(hlu::k_df_reset, dim3((n + 255) / 256), dim3(256), 0, s, pp, np, queue, ready0,
+                     nready, n, ctrl);
+  hipLaunchKernelGGL(hlu::k_dataflow, dim3(workers), dim3(NT), sizeof(hlu::TruncShared), s, pp, np,
+                     queue, ctrl, n, timeout);
   return hipGetLastError();
 }
 
-extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off, const int* succ,
-                                         const int* indeg0, int* indeg, int* queue,
-                                         const int* ready0, int nready, int* ctrl, int n,
-                                         int workers, long long timeout, int32_t* status,
+// The same run as a graph (status clear, reset, executor), built explicitly.
+extern "C" hipError_t hlu_build_df_graph(const void* parts, int np, int* queue, const int* ready0,
+                                         int nready, int* ctrl, int n, int workers,
+                                         long long timeout, int32_t* status,
                                          hipGraphExec_t* out) {
   *out = nullptr;
   hipError_t e = df_attr();
@@ -1747,6 +1769,7 @@ extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off,
   hipGraph_t g;
   e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
+  const hlu::DfPart* pp = reinterpret_cast<const hlu::DfPart*>(parts);
   hipGraphNode_t n0, n1, n2;
   if (status) {   // the status word is cleared only when given
     int zero = 0;
@@ -1759,7 +1782,7 @@ extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off,
     e = hipGraphAddKernelNode(&n0, g, nullptr, 0, &p);
   }
   if (e == hipSuccess) {
-    void* args[] = {&indeg, &indeg0, &queue, &ready0, &nready, &n, &ctrl};
+    void* args[] = {&pp, &np, &queue, &ready0, &nready, &n, &ctrl};
     hipKernelNodeParams p = {};
     p.func = reinterpret_cast<void*>(&hlu::k_df_reset);
     p.gridDim = dim3((n + 255) / 256);
@@ -1768,8 +1791,7 @@ extern "C" hipError_t hlu_build_df_graph(const void* ops_p, const int* succ_off,
     e = hipGraphAddKernelNode(&n1, g, status ? &n0 : nullptr, status ? 1 : 0, &p);
   }
   if (e == hipSuccess) {
-    const hlu::Op* ops = reinterpret_cast<const hlu::Op*>(ops_p);
-    void* args[] = {&ops, &succ_off, &succ, &indeg, &queue, &ctrl, &n, &timeout};
+    void* args[] = {&pp, &np, &queue, &ctrl, &n, &timeout};
     hipKernelNodeParams p = {};
     p.func = reinterpret_cast<void*>(&hlu::k_dataflow);
     p.gridDim = dim3(workers);

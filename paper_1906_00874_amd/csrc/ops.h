@@ -71,6 +71,18 @@ struct Term {
   int32_t pad[2];
 };
 
+// One schedule of a dataflow run.  Ops, successor lists and in-degrees use
+// the schedule's own numbering; the run numbers all ops of all its parts
+// consecutively, part i owning [base, base + n).
+struct DfPart {
+  uint64_t ops;        // const Op[n]
+  uint64_t succ_off;   // const int32[n + 1]
+  uint64_t succ;       // const int32[edges] (local indices)
+  uint64_t indeg0;     // const int32[n]
+  uint64_t indeg;      // int32[n], consumed by the run
+  int32_t base, n;
+};
+
 // Matvec with the refinement copy: per low-rank block, T = V^T X[s];
 // per leaf row cluster, y = b - sum(F X[s]) - sum(U T).
 struct MvLR {        // one low-rank block of the matvec copy (FP64)

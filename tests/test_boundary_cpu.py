@@ -92,6 +92,28 @@ def test_state_errors_without_device():
     assert P.lib.hlu_required_bytes(None) == 0
 
 
+def test_batch_arguments_without_device():
+    """The batch is built on the host from planned handles: an empty list or
+    a handle listed twice is refused; a valid batch needs a workspace, and
+    factoring before binding is a state error."""
+    P = _lib()
+    xyz, area = icosphere(1)
+    h1 = P.HLU(xyz, area, assemble=False)
+    h2 = P.HLU(xyz, area, assemble=False)
+    out = C.c_void_p()
+    arr = (C.c_void_p * 2)(h1.h, h1.h)
+    assert P.lib.hlu_batch_create(arr, 2, C.byref(out)) == 1
+    assert P.lib.hlu_batch_create(arr, 0, C.byref(out)) == 1
+    arr = (C.c_void_p * 2)(h1.h, h2.h)
+    assert P.lib.hlu_batch_create(arr, 2, C.byref(out)) == 0
+    nb = P.lib.hlu_batch_required_bytes(out)
+    # queue over both schedules' ops at least
+    assert nb >= 4 * 2 * h1.stats()["ops_factor"]
+    assert P.lib.hlu_batch_factor(out, None) == 6
+    assert P.lib.hlu_batch_bind(out, C.c_void_p(256), 16) == 1
+    P.lib.hlu_batch_destroy(out)
+
+
 def test_schedule_statistics_scale():
     P = _lib()
     xyz, area = icosphere(3)

@@ -318,6 +318,38 @@ def test_dataflow_executor_matches_waves(P, level, prec, graph):
         assert np.array_equal(x, x0), rep
 
 
+def test_batched_factor_matches_alone(P):
+    """One persistent launch over the union of several matrices' schedules
+    (sphere and ellipsoids of different sizes) gives, matrix by matrix, the
+    factors and pivots of factoring each alone (the same ops on the same
+    data); repeated after a reset."""
+    from hlu_inputs.geometry import ellipsoid_surface
+    geo = [icosphere(3), ellipsoid_surface(3, (1.5, 0.7, 1.0)), icosphere(4),
+           ellipsoid_surface(2, (0.6, 1.8, 1.2))]
+    hs = [P.HLU(x, a, leaf=32, eta=2.0, eps=1e-6, cap=32, precision=P.PREC_MIXED, max_nrhs=1)
+          for x, a in geo]
+    ref = []
+    for h in hs:
+        h.set_executor(1)
+        h.factor()
+        st, inf = h.sync(check=False)
+        assert st == 0
+        ref.append((h.export_factors(), h.export_pivots()))
+    _say("batched", [h.n for h in hs])
+    bt = P.Batch(hs)
+    for rep in range(2):
+        for h in hs:
+            h.reset()
+        bt.factor()
+        bt.sync()
+        for h, ((L0, U0), p0) in zip(hs, ref):
+            st, inf = h.sync(check=False)
+            assert st == 0, P.lib.hlu_last_error()
+            L, U = h.export_factors()
+            assert np.array_equal(h.export_pivots(), p0)
+            assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
+
+
 def test_refinement_not_converged_is_reported(P):
     """A very loose factorisation with one refinement step cannot reach the
     target: the solve reports NOT_CONVERGED instead of a silent answer."""
