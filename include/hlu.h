@@ -67,12 +67,18 @@ typedef struct {
     double eps_factor;        /* truncation tolerance of the factored copy      */
     int rank_cap_factor;      /* rank capacity of the factored copy (<= 32)     */
     double eps_matvec;        /* tolerance of the refinement operator copy      */
-    int rank_cap_matvec;      /* rank capacity of that copy (<= 64)             */
+    int rank_cap_matvec;      /* rank capacity of that copy (<= 64); 0: no copy
+                                 (then refine_tol must be 0 and hlu_matvec is
+                                 unavailable)                                   */
     hlu_precision precision;
     double refine_tol;        /* backward-error target of hlu_solve (0: no IR)  */
     int refine_max_iter;      /* at most this many refinement steps              */
     int max_nrhs;             /* largest nrhs hlu_solve / hlu_matvec will see   */
     uint64_t seed;            /* reserved for randomised construction           */
+    int64_t scratch_cap_bytes;/* 0: every H-GEMM temporary has its own region;
+                                 > 0: temporaries share a ring of this many
+                                 bytes (a region is reused only after every op
+                                 touching its previous tenant has run)          */
 } hlu_params;
 
 typedef struct {
@@ -221,6 +227,12 @@ hlu_status hlu_factor_graph(hlu_handle h, int32_t* succ_off, int32_t* succ, int6
 hlu_status hlu_schedule_records(hlu_handle h, int which, double* recs, int32_t* info);
 hlu_status hlu_schedule_graph(hlu_handle h, int which, int32_t* succ_off, int32_t* succ,
                               int64_t* nedges);
+/* Diagnostics: the op descriptors (struct Op of the kernels' header, offsets
+ * relative to the device buffer), the wave of each op (int32) and the term
+ * table of a schedule, in schedule order; pass NULL buffers to query the
+ * counts. */
+hlu_status hlu_schedule_ops(hlu_handle h, int which, void* ops, int32_t* waves, int64_t* nops,
+                            void* terms, int64_t* nterms);
 
 /* Cluster-order permutation: perm[p] = original index of position p (host
  * array of n int64). */

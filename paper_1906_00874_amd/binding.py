@@ -32,7 +32,8 @@ class Params(C.Structure):
                 ("rank_cap_factor", C.c_int), ("eps_matvec", C.c_double),
                 ("rank_cap_matvec", C.c_int), ("precision", C.c_int),
                 ("refine_tol", C.c_double), ("refine_max_iter", C.c_int),
-                ("max_nrhs", C.c_int), ("seed", C.c_uint64)]
+                ("max_nrhs", C.c_int), ("seed", C.c_uint64),
+                ("scratch_cap_bytes", C.c_int64)]
 
 
 class Info(C.Structure):
@@ -48,6 +49,17 @@ class PlanStats(C.Structure):
                 ("bytes_factor_region", C.c_int64), ("bytes_matvec_region", C.c_int64),
                 ("bytes_scratch", C.c_int64), ("bytes_total", C.c_int64)]
 
+
+# Host views of the schedule descriptors (struct PRef / Op / Term of the
+# kernels' header), as returned by HLU.schedule_ops.
+PREF_DTYPE = np.dtype([("ptr", "<u8"), ("rankp", "<u8"), ("ld", "<i4"), ("rows", "<i4"),
+                       ("cols", "<i4"), ("dt", "u1"), ("trans", "u1"), ("kind", "u1"),
+                       ("pad", "u1")])
+OP_DTYPE = np.dtype([("type", "<i4"), ("i0", "<i4"), ("i1", "<i4"), ("i2", "<i4"),
+                     ("d0", "<f8"), ("cost", "<u8"), ("p", PREF_DTYPE, (4,))])
+TERM_DTYPE = np.dtype([("X", PREF_DTYPE), ("Y", PREF_DTYPE), ("xo", "<i4"), ("yo", "<i4"),
+                       ("pad", "<i4", (2,))])
+assert PREF_DTYPE.itemsize == 32 and OP_DTYPE.itemsize == 160 and TERM_DTYPE.itemsize == 80
 
 _P = C.c_void_p
 _sig = {
@@ -71,6 +83,7 @@ _sig = {
     "hlu_factor_graph": (C.c_int, [_P, _P, _P, _P]),
     "hlu_schedule_records": (C.c_int, [_P, C.c_int, _P, _P]),
     "hlu_schedule_graph": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "hlu_schedule_ops": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     "hlu_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_matvec": (C.c_int, [_P, _P, _P, C.c_int, C.c_int64, _P]),
     "hlu_sync": (C.c_int, [_P, _P, C.POINTER(Info)]),
@@ -115,9 +128,9 @@ def _ptr(t):
 
 def make_params(kernel=KERNEL_WEIGHTED, eta=2.0, leaf=32, fixed_rank=0, eps=1e-6, cap=32,
                 eps_mv=1e-12, cap_mv=64, precision=PREC_FP64, refine_tol=0.0,
-                refine_max_iter=10, max_nrhs=32, seed=0):
+                refine_max_iter=10, max_nrhs=32, seed=0, scratch_cap=0):
     return Params(kernel, eta, leaf, fixed_rank, eps, cap, eps_mv, cap_mv, precision,
-                  refine_tol, refine_max_iter, max_nrhs, seed)
+                  refine_tol, refine_max_iter, max_nrhs, seed, scratch_cap)
 
 
 class HLU:
@@ -257,6 +270,20 @@ class HLU:
         _check(lib.hlu_schedule_records(self.h, which, r.ctypes.data_as(_P),
                                         i.ctypes.data_as(_P)))
         return r, i
+
+    def schedule_ops(self, which):
+        """(ops, waves, terms) of schedule `which` (0: factor, 1: solve) in
+        schedule order: OP_DTYPE / int32 / TERM_DTYPE arrays, device
+        addresses given relative to the handle's buffer."""
+        no, nt = C.c_int64(), C.c_int64()
+        _check(lib.hlu_schedule_ops(self.h, which, None, None, C.byref(no), None, C.byref(nt)))
+        ops = np.zeros(no.value, OP_DTYPE)
+        waves = np.zeros(no.value, np.int32)
+        terms = np.zeros(max(1, nt.value), TERM_DTYPE)
+        _check(lib.hlu_schedule_ops(self.h, which, ops.ctypes.data_as(_P),
+                                    waves.ctypes.data_as(_P), C.byref(no),
+                                    terms.ctypes.data_as(_P), C.byref(nt)))
+        return ops, waves, terms[:nt.value]
 
     def schedule_graph(self, which):
         """(succ_off, succ) of schedule `which` (0: factor, 1: solve)."""

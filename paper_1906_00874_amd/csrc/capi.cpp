@@ -258,13 +258,17 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
   if (!(p->eta >= 0) || !std::isfinite(p->eta)) return fail(HLU_ERR_ARG, "eta must be >= 0");
   if (p->rank_cap_factor < 1 || p->rank_cap_factor > 32)
     return fail(HLU_ERR_ARG, "rank_cap_factor must be in [1, 32]");
-  if (p->rank_cap_matvec < 1 || p->rank_cap_matvec > 64)
-    return fail(HLU_ERR_ARG, "rank_cap_matvec must be in [1, 64]");
+  if (p->rank_cap_matvec < 0 || p->rank_cap_matvec > 64)
+    return fail(HLU_ERR_ARG, "rank_cap_matvec must be in [0, 64]");
+  if (p->rank_cap_matvec == 0 && p->refine_tol != 0.0)
+    return fail(HLU_ERR_ARG, "refinement needs the operator copy (rank_cap_matvec > 0)");
+  if (p->scratch_cap_bytes < 0) return fail(HLU_ERR_ARG, "scratch_cap_bytes must be >= 0");
   if (p->fixed_rank < 0 || p->fixed_rank > p->rank_cap_factor)
     return fail(HLU_ERR_ARG, "fixed_rank must be in [0, rank_cap_factor]");
   if (p->fixed_rank == 0 && !(p->eps_factor > 0 && p->eps_factor < 1))
     return fail(HLU_ERR_ARG, "eps_factor must be in (0, 1)");
-  if (!(p->eps_matvec > 0 && p->eps_matvec < 1)) return fail(HLU_ERR_ARG, "eps_matvec must be in (0, 1)");
+  if (p->rank_cap_matvec > 0 && !(p->eps_matvec > 0 && p->eps_matvec < 1))
+    return fail(HLU_ERR_ARG, "eps_matvec must be in (0, 1)");
   if (p->max_nrhs < 1 || p->max_nrhs > 64) return fail(HLU_ERR_ARG, "max_nrhs must be in [1, 64]");
   if (p->kernel != HLU_KERNEL_LAPLACE3D_WEIGHTED && p->kernel != HLU_KERNEL_LAPLACE3D_POINT)
     return fail(HLU_ERR_ARG, "unknown kernel");
@@ -288,6 +292,7 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
   prm.refine_tol = p->refine_tol;
   prm.refine_max_iter = p->refine_max_iter;
   prm.max_nrhs = p->max_nrhs;
+  prm.scratch_cap = (uint64_t)p->scratch_cap_bytes;
   try {
     if (!hlu::build_plan(h->plan, xyz, area, n, prm)) {
       std::string e = h->plan.err;
@@ -317,11 +322,17 @@ hlu_status hlu_validate(hlu_handle h) {
     const size_t N = sc.ops.size();
     if (sc.succ_off.size() != N + 1 || sc.indeg0.size() != N)
       return fail(HLU_ERR_ARG, "dependency graph size");
+    // wave of every op (the wave executor runs a wave's ops concurrently,
+    // so every dependency edge must cross waves)
+    std::vector<int32_t> wv(N, 0);
+    for (const auto& w : sc.waves_list)
+      for (int q = 0; q < w.count; ++q) wv[w.start + q] = w.wave;
     std::vector<int32_t> cnt(N, 0);
     for (size_t i = 0; i < N; ++i)
       for (int32_t e = sc.succ_off[i]; e < sc.succ_off[i + 1]; ++e) {
         int32_t s = sc.succ[e];
         if (s <= (int64_t)i || s >= (int64_t)N) return fail(HLU_ERR_ARG, "dependency edge order");
+        if (wv[s] <= wv[i]) return fail(HLU_ERR_ARG, "dependency edge inside one wave");
         cnt[s]++;
       }
     size_t nready = 0;
@@ -851,6 +862,7 @@ hlu_status hlu_matvec(hlu_handle h, const double* x_dev, double* y_dev, int nrhs
   if (!h || !x_dev || !y_dev) return fail(HLU_ERR_ARG, "NULL argument");
   if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
   hlu::Plan& p = h->plan;
+  if (p.prm.cap_mv == 0) return fail(HLU_ERR_STATE, "planned without the operator copy");
   if (nrhs < 1 || nrhs > p.prm.max_nrhs) return fail(HLU_ERR_ARG, "nrhs out of range");
   if (ld < p.n) return fail(HLU_ERR_ARG, "ld < n");
   hipStream_t s = (hipStream_t)stream;
@@ -964,6 +976,24 @@ hlu_status hlu_schedule_records(hlu_handle h, int which, double* recs, int32_t* 
 // *nedges (pass succ = NULL to query it).
 hlu_status hlu_factor_graph(hlu_handle h, int32_t* succ_off, int32_t* succ, int64_t* nedges) {
   return hlu_schedule_graph(h, 0, succ_off, succ, nedges);
+}
+
+// The op descriptors of a schedule in schedule order (offsets relative to
+// the device buffer), the wave of each op and the term table; sizes in
+// *nops / *nterms.
+hlu_status hlu_schedule_ops(hlu_handle h, int which, void* ops, int32_t* waves, int64_t* nops,
+                            void* terms, int64_t* nterms) {
+  if (!h || !nops || !nterms) return fail(HLU_ERR_ARG, "NULL argument");
+  if (which != 0 && which != 1) return fail(HLU_ERR_ARG, "schedule must be 0 or 1");
+  const hlu::Schedule& sc = which ? h->plan.ssched : h->plan.fsched;
+  *nops = (int64_t)sc.ops.size();
+  *nterms = (int64_t)sc.terms.size();
+  if (ops) std::memcpy(ops, sc.ops.data(), sc.ops.size() * sizeof(hlu::Op));
+  if (waves)
+    for (const auto& w : sc.waves_list)
+      for (int q = 0; q < w.count; ++q) waves[w.start + q] = w.wave;
+  if (terms) std::memcpy(terms, sc.terms.data(), sc.terms.size() * sizeof(hlu::Term));
+  return HLU_OK;
 }
 
 hlu_status hlu_schedule_graph(hlu_handle h, int which, int32_t* succ_off, int32_t* succ,

@@ -17,6 +17,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <map>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -447,7 +448,8 @@ class Builder {
   Acc whole(int obj, bool write) { return Acc{obj, -1, -1, write}; }
 
   int schedule(const std::vector<Acc>& acc) {
-    int dep = -1;
+    int dep = extra_wave;
+    extra_wave = -1;
     for (const Acc& a : acc) {
       if (a.obj < 0) continue;
       Obj& o = objs[a.obj];
@@ -526,6 +528,7 @@ class Builder {
   void edges(const std::vector<Acc>& acc, int self) {
     eobj_sync();
     std::vector<int> pr;
+    pr.swap(extra_pred);
     auto range = [&](const Acc& a, int& p0, int& p1) {
       const EObj& o = eobjs[a.obj];
       if (a.l0 < 0 || o.nparts == 1) { p0 = 0; p1 = o.nparts; }
@@ -665,15 +668,88 @@ class Builder {
     v.dt = DT_F64;
     return v;
   }
+  // ---- reuse of the scratch region as a ring (when ring_cap > 0).  Live
+  // allocations are kept by address.  A new allocation evicts every tenant it
+  // overlaps and takes over the whole extent of each (so no byte a retired
+  // tenant touched is ever free without a successor that orders after its
+  // ops); its first op (the zeroing) then depends on every op that touched
+  // them.  At a wrap the tail tenants stay live until the ring reaches them
+  // again.  Tenants still referenced by deferred truncation terms are
+  // consumed (flushed) first.
+  struct Live {
+    uint64_t off, end;
+    int obj;
+  };
+  std::map<uint64_t, Live> live;    // keyed by off
+  uint64_t ring_cap = 0, ring_cur = 0;
+  int extra_wave = -1;              // lower bound for the next op's wave
+  std::vector<int> extra_pred;      // extra predecessors of the next op
+  std::vector<char> pend_obj;       // object referenced by a pending term
+  void retire(int obj) {
+    const Obj& o = objs[obj];
+    extra_wave = std::max(extra_wave, std::max(o.mW, o.mR));
+    if (!want_edges) return;
+    eobj_sync();
+    const EObj& e = eobjs[obj];
+    for (int q = 0; q < e.nparts; ++q) {
+      if (e.lastW[q] >= 0) extra_pred.push_back(e.lastW[q]);
+      extra_pred.insert(extra_pred.end(), e.readers[q].begin(), e.readers[q].end());
+    }
+  }
+  bool is_pending(int obj) const { return obj >= 0 && obj < (int)pend_obj.size() && pend_obj[obj]; }
+  std::map<uint64_t, Live>::iterator first_overlap(uint64_t off) {
+    auto it = live.upper_bound(off);
+    if (it != live.begin()) {
+      auto p = std::prev(it);
+      if (p->second.end > off) return p;
+    }
+    return it;
+  }
+  // Returns the data offset of a new allocation of `bytes`; `ext` receives
+  // the extent the new tenant owns (the data plus absorbed evicted ranges).
+  uint64_t ring_alloc(uint64_t bytes, Live& ext) {
+    if (bytes > ring_cap) {
+      P.err = "scratch_cap_bytes is smaller than one H-GEMM temporary (" + std::to_string(bytes) +
+              " bytes)";
+      ext = Live{0, 0, -1};
+      return 0;
+    }
+    const uint64_t off = ring_cur + bytes > ring_cap ? 0 : ring_cur;
+    uint64_t lo = off, hi = off + bytes;
+    bool flush = false;
+    for (auto it = first_overlap(off); it != live.end() && it->first < hi; ++it)
+      flush |= is_pending(it->second.obj);
+    if (flush) flush_truncations();
+    for (auto it = first_overlap(off); it != live.end() && it->first < hi;) {
+      lo = std::min(lo, it->second.off);
+      hi = std::max(hi, it->second.end);
+      retire(it->second.obj);
+      it = live.erase(it);
+    }
+    ring_cur = hi;
+    scratch_cur = std::max(scratch_cur, hi);
+    ext = Live{lo, hi, -1};
+    return off;
+  }
+
   PV scratch(int cl, int cols, uint64_t rank, int dt, int robj = -1) {
     PV v;
     v.robj = robj;
-    v.obj = new_obj(cl, false);
     int es = dt == DT_F64 ? 8 : 4;
     uint64_t bytes = (uint64_t)P.cl[cl].size * cols * es;
     bytes = (bytes + 255) & ~(uint64_t)255;
-    v.off = scratch_base + scratch_cur;
-    scratch_cur += bytes;
+    if (ring_cap > 0) {
+      Live ext;
+      const uint64_t off = ring_alloc(bytes, ext);
+      v.obj = new_obj(cl, false);
+      ext.obj = v.obj;
+      live[ext.off] = ext;
+      v.off = scratch_base + off;
+    } else {
+      v.obj = new_obj(cl, false);
+      v.off = scratch_base + scratch_cur;
+      scratch_cur += bytes;
+    }
     v.ld = P.cl[cl].size;
     v.rows = P.cl[cl].size;
     v.cols = cols;
@@ -971,6 +1047,11 @@ class Builder {
     if (pend.size() < P.bn.size()) pend.resize(P.bn.size());
     if (pend[Cb].empty()) pend_order.push_back(Cb);
     pend[Cb].push_back(PendTerm{colwin(X, c0, w), colwin(Y, c0, w), xo, yo});
+    for (int ob : {X.obj, Y.obj})
+      if (ob >= 0) {
+        if ((int)pend_obj.size() <= ob) pend_obj.resize(ob + 1, 0);
+        pend_obj[ob] = 1;
+      }
     trunc_groups.insert(((int64_t)call_id << 24) ^ Cb);
   }
 
@@ -1005,6 +1086,9 @@ class Builder {
         }
         emit(op, acc);
       }
+      for (const PendTerm& t : L)
+        for (int ob : {t.X.obj, t.Y.obj})
+          if (ob >= 0 && ob < (int)pend_obj.size()) pend_obj[ob] = 0;
       L.clear();
     }
     pend_order.clear();
@@ -1216,7 +1300,10 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   });
   std::vector<std::vector<double>> mvU(p.blk.size()), mvV(p.blk.size());
   std::atomic<int64_t> cap_hits{0};
-  double eps_aca = std::min(prm.eps_mv, prm.fixed_rank > 0 ? 1e-12 : prm.eps_f) * 0.1;
+  // cross approximation to a tenth of the tightest tolerance any copy needs
+  double eps_need = prm.fixed_rank > 0 ? 1e-12 : prm.eps_f;
+  if (prm.cap_mv > 0) eps_need = std::min(eps_need, prm.eps_mv);
+  double eps_aca = eps_need * 0.1;
   char* img = p.img_work.data();
   parallel_for((int)rids.size(), [&](int q) {
     LBlock& b = p.blk[rids[q]];
@@ -1240,7 +1327,7 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     bool capped;
     int kf = choose_rank(sig, prm.eps_f, prm.cap_f, prm.fixed_rank, &capped);
     if (capped) cap_hits++;
-    int kmv = choose_rank(sig, prm.eps_mv, prm.cap_mv, 0, &capped);
+    int kmv = prm.cap_mv > 0 ? choose_rank(sig, prm.eps_mv, prm.cap_mv, 0, &capped) : 0;
     b.kf = kf;
     b.mvk = kmv;
     int32_t* rk = (int32_t*)(img + (b.offRank - p.off_work));
@@ -1373,6 +1460,7 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     B.P_dt = prm.mixed ? DT_F32 : DT_F64;
     B.chunk_cols = std::max(1, 64 - prm.cap_f);
     B.scratch_base = p.off_scratch;
+    B.ring_cap = prm.scratch_cap & ~(uint64_t)255;
     for (auto& b : p.blk) {
       int rows_cl = b.t;
       if (b.kind == 'F') b.objF = B.new_obj(-1, true);

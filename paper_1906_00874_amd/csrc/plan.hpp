@@ -22,6 +22,7 @@ struct Params {
   double refine_tol = 0.0;
   int refine_max_iter = 10;
   int max_nrhs = 32;
+  uint64_t scratch_cap = 0;   // 0: no reuse of H-GEMM temporaries
 };
 
 struct Cluster {

@@ -350,6 +350,46 @@ def test_batched_factor_matches_alone(P):
             assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
 
 
+def test_scratch_ring_reuse(P):
+    """H-GEMM temporaries sharing a ring: a ring that never wraps changes
+    nothing (bitwise); a tight ring (regions reused, deferred truncations
+    flushed early) keeps the factor accurate, and the wave and dataflow
+    executors, which take the reuse order from the same program order,
+    agree bitwise."""
+    xyz, area = icosphere(4)
+    A = O.dense_matrix(xyz, area)
+    kw = dict(leaf=32, eta=2.0, eps=1e-6, cap=32, precision=P.PREC_MIXED, max_nrhs=1,
+              cap_mv=0, refine_tol=0.0)
+    h0 = P.HLU(xyz, area, **kw)
+    big = int(h0.stats()["bytes_scratch"]) * 2 + (1 << 20)
+    h0.set_executor(1)
+    h0.factor()
+    h0.sync()
+    L0, U0 = h0.export_factors()
+    h2 = P.HLU(xyz, area, scratch_cap=big, **kw)
+    h2.set_executor(1)
+    h2.factor()
+    h2.sync()
+    L2, U2 = h2.export_factors()
+    assert np.array_equal(L2, L0) and np.array_equal(U2, U0)
+    h1 = P.HLU(xyz, area, scratch_cap=2 << 20, **kw)
+    _say("ring", h1.stats()["bytes_scratch"], "vs", h0.stats()["bytes_scratch"])
+    assert h1.stats()["bytes_scratch"] <= 2 << 20
+    h1.set_executor(0)
+    h1.factor()
+    h1.sync()
+    Lw, Uw = h1.export_factors()
+    h1.set_executor(1)
+    h1.reset()
+    h1.factor()
+    h1.sync()
+    Ld, Ud = h1.export_factors()
+    assert np.array_equal(Lw, Ld) and np.array_equal(Uw, Ud)
+    perm = h1.perm()
+    rel = np.linalg.norm(A[np.ix_(perm, perm)] - Ld @ Ud) / np.linalg.norm(A)
+    assert rel <= 11 * 1e-6, rel
+
+
 def test_refinement_not_converged_is_reported(P):
     """A very loose factorisation with one refinement step cannot reach the
     target: the solve reports NOT_CONVERGED instead of a silent answer."""
