@@ -28,18 +28,26 @@ extern "C" size_t hlu_lds_bytes(int type);
 extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* starts,
                                            const int* counts, const size_t* lds, int nwaves,
                                            int32_t* status, hipGraphExec_t* out);
-extern "C" hipError_t hlu_launch_dataflow(const void* parts, int np, int* queue,
+extern "C" hipError_t hlu_launch_dataflow(int kind, const void* parts, int np, int* queue,
                                           const int* ready0, int nready, int* ctrl, int n,
                                           int workers, long long timeout, int32_t* status,
                                           hipStream_t s);
-extern "C" hipError_t hlu_build_df_graph(const void* parts, int np, int* queue, const int* ready0,
-                                         int nready, int* ctrl, int n, int workers,
-                                         long long timeout, int32_t* status,
+extern "C" hipError_t hlu_build_df_graph(int kind, const void* parts, int np, int* queue,
+                                         const int* ready0, int nready, int* ctrl, int n,
+                                         int workers, long long timeout, int32_t* status,
                                          hipGraphExec_t* out);
 
 namespace {
 
 thread_local std::string g_err;
+
+const char* df_error_text(int32_t e) {
+  switch (e) {
+    case 2: return "dataflow executor: queue overflow";
+    case 3: return "dataflow executor: op type outside the executor's set";
+    default: return "dataflow executor: a wait exceeded its time limit";
+  }
+}
 
 hlu_status fail(hlu_status st, const std::string& msg) {
   g_err = msg;
@@ -322,6 +330,18 @@ hlu_status hlu_validate(hlu_handle h) {
     const size_t N = sc.ops.size();
     if (sc.succ_off.size() != N + 1 || sc.indeg0.size() != N)
       return fail(HLU_ERR_ARG, "dependency graph size");
+    // op types the dataflow executor of this schedule runs
+    const unsigned allowed =
+        scp == &p.fsched
+            ? (1u << hlu::OP_GETRF) | (1u << hlu::OP_TRSM_L) | (1u << hlu::OP_TRSM_UT) |
+                  (1u << hlu::OP_TRSM_U) | (1u << hlu::OP_PGEMM) | (1u << hlu::OP_TRUNC) |
+                  (1u << hlu::OP_ADDD) | (1u << hlu::OP_ZERO)
+            : (1u << hlu::OP_TRSM_L) | (1u << hlu::OP_TRSM_UT) | (1u << hlu::OP_TRSM_U) |
+                  (1u << hlu::OP_MVT) | (1u << hlu::OP_MVROW);
+    for (const auto& op : sc.ops)
+      if (!((allowed >> op.type) & 1))
+        return fail(HLU_ERR_ARG, "op type " + std::to_string(op.type) + " outside the " +
+                                     (scp == &p.fsched ? "factor" : "solve") + " executor's set");
     // wave of every op (the wave executor runs a wave's ops concurrently,
     // so every dependency edge must cross waves)
     std::vector<int32_t> wv(N, 0);
@@ -593,12 +613,14 @@ static hlu_status run_dataflow(hlu_handle h, const DfArrays& da, hipStream_t s,
   if (n == 0) return HLU_OK;
   if (h->use_graph) {
     if (!*graph)
-      HIPCHK(hlu_build_df_graph(part, 1, queue, ready0, nready, ctrl, n, cus, timeout, status,
+      HIPCHK(hlu_build_df_graph(factor ? 0 : 1, part, 1, queue, ready0, nready, ctrl, n, cus,
+                                timeout, status,
                                 graph));
     HIPCHK(hipGraphLaunch(*graph, s));
     return HLU_OK;
   }
-  HIPCHK(hlu_launch_dataflow(part, 1, queue, ready0, nready, ctrl, n, cus, timeout, status, s));
+  HIPCHK(hlu_launch_dataflow(factor ? 0 : 1, part, 1, queue, ready0, nready, ctrl, n, cus, timeout,
+                             status, s));
   return HLU_OK;
 }
 
@@ -779,7 +801,7 @@ hlu_status hlu_batch_factor(hlu_batch b, void* stream) {
   if (st != HLU_OK) return st;
   for (hlu_handle h : b->hs)
     HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
-  HIPCHK(hlu_launch_dataflow(b->dev + b->off_parts, (int)b->hs.size(), (int*)(b->dev + b->off_queue),
+  HIPCHK(hlu_launch_dataflow(0, b->dev + b->off_parts, (int)b->hs.size(), (int*)(b->dev + b->off_queue),
                              (const int*)(b->dev + b->off_ready0), (int)b->ready0.size(),
                              (int*)(b->dev + b->off_ctrl), (int)b->ntot, cus, 20 * tps, nullptr,
                              s));
@@ -794,8 +816,7 @@ hlu_status hlu_batch_sync(hlu_batch b, void* stream) {
   int32_t err = 0;
   HIPCHK(hipMemcpy(&err, b->dev + b->off_ctrl + 8, 4, hipMemcpyDeviceToHost));
   if (err)
-    return fail(HLU_ERR_DEVICE, err == 2 ? "dataflow executor: queue overflow"
-                                         : "dataflow executor: a wait exceeded its time limit");
+    return fail(HLU_ERR_DEVICE, df_error_text(err));
   return HLU_OK;
 }
 
@@ -914,8 +935,7 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
   }
   if (out) *out = inf;
   if (df_error)
-    return fail(HLU_ERR_DEVICE, df_error == 2 ? "dataflow executor: queue overflow"
-                                              : "dataflow executor: a wait exceeded its time limit");
+    return fail(HLU_ERR_DEVICE, df_error_text(df_error));
   if (inf.info) return fail(HLU_ERR_SINGULAR, "zero pivot");
   if (h->not_converged) return fail(HLU_ERR_NOT_CONVERGED, "refinement did not converge");
   return HLU_OK;

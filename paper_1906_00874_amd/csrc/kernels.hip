@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ops.h"
 
 namespace hlu {
@@ -192,7 +194,7 @@ __device__ __forceinline__ void trsm_subst(double (&v)[8], const double (*l)[65]
 // of Y (lane l holds rows l, l + 8, ... in registers) and each solved entry
 // is broadcast within the eight lanes through DPP, so the substitution runs
 // without barriers.  Columns are taken 32 at a time.
-__device__ void d_trsm(const Op& op) {
+__device__ __forceinline__ void trsm_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef L = op.p[0];
   const PRef Y = op.p[1];
@@ -1246,7 +1248,7 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
 // streamed in chunks of 32; each thread prefetches the next chunk into
 // registers while the current one is multiplied.
 #define LDS_MVT (2 * 32 * 65 * 8)
-__device__ void d_mvt(const Op& op) {
+__device__ __forceinline__ void mvt_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef V = op.p[0], X = op.p[2], T = op.p[3];
   const int n = V.rows, k = pcols(V), nr = pcols(X);
@@ -1314,7 +1316,7 @@ __device__ void d_mvt(const Op& op) {
 #define MVR_TMAX 256
 #define MVR_STAGE (4 * (64 * 17 + 16 * 65) * 8)
 #define LDS_MVROW (MVR_STAGE + 2 * MVR_TMAX * 4)
-__device__ void d_mvrow(const Op& op) {
+__device__ __forceinline__ void mvrow_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef Y = op.p[3];
   const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
@@ -1558,6 +1560,14 @@ __global__ void k_set_int(int32_t* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Out-of-line entries of the leaf solve and the H-matvec update bodies (the
+// wave kernel and the factor executor call these; the solve executor, which
+// runs only these types, takes the bodies inline and so saves no registers
+// across a call).
+__device__ __noinline__ void d_trsm(const Op& op) { trsm_body(op); }
+__device__ __noinline__ void d_mvt(const Op& op) { mvt_body(op); }
+__device__ __noinline__ void d_mvrow(const Op& op) { mvrow_body(op); }
+
 // ---------------------------------------------------------------- launchers
 // One workgroup per descriptor; the descriptors of a launch may mix op
 // types (one launch per wave of the schedule).  Each op type carves its
@@ -1590,7 +1600,8 @@ __global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
 // -- an op starts as soon as its own predecessors have finished, across
 // recursion levels, instead of waiting for a whole wave.
 //   ctrl[0]: next queue slot to take, ctrl[1]: next slot to fill,
-//   ctrl[2]: error flag (a wait exceeded the time limit).
+//   ctrl[2]: error flag (1: a wait exceeded the time limit, 2: queue
+//   overflow, 3: an op type this executor does not run).
 // Every op is pushed exactly once (when its last predecessor finishes), so
 // the queue has one slot per op; a workgroup that takes a slot >= n exits.
 // Waits are bounded by `timeout` ticks of the constant-rate wall clock, after
@@ -1622,9 +1633,56 @@ __global__ void k_df_reset(const DfPart* parts, int np, int* queue, const int* r
   }
 }
 
-__global__ void __launch_bounds__(NT) k_dataflow(const DfPart* __restrict__ parts, int np,
-                                                 int* queue, int* ctrl, int n,
-                                                 long long timeout) {
+// Op types each executor instantiation runs: the factor schedule's and the
+// solve schedule's (the host validates every schedule against its mask; an op
+// outside it raises error 3).
+constexpr unsigned DF_FACTOR_TYPES = (1u << OP_GETRF) | (1u << OP_TRSM_L) | (1u << OP_TRSM_UT) |
+                                     (1u << OP_TRSM_U) | (1u << OP_PGEMM) | (1u << OP_TRUNC) |
+                                     (1u << OP_ADDD) | (1u << OP_ZERO);
+constexpr unsigned DF_SOLVE_TYPES = (1u << OP_TRSM_L) | (1u << OP_TRSM_UT) | (1u << OP_TRSM_U) |
+                                    (1u << OP_MVT) | (1u << OP_MVROW);
+
+template <unsigned MASK>
+__device__ __forceinline__ bool run_op_masked(const Op& op) {
+  constexpr bool kInlineSolveOps = MASK == DF_SOLVE_TYPES;
+  start_tick(op);
+  switch (op.type) {
+    case OP_GETRF: if constexpr ((MASK >> OP_GETRF) & 1) { d_getrf(op); return true; } break;
+    case OP_TRSM_L:
+    case OP_TRSM_UT:
+    case OP_TRSM_U:
+      if constexpr (MASK & ((1u << OP_TRSM_L) | (1u << OP_TRSM_UT) | (1u << OP_TRSM_U))) {
+        if constexpr (kInlineSolveOps) trsm_body(op);
+        else d_trsm(op);
+        return true;
+      }
+      break;
+    case OP_PGEMM: if constexpr ((MASK >> OP_PGEMM) & 1) { d_pgemm(op); return true; } break;
+    case OP_TRUNC: if constexpr ((MASK >> OP_TRUNC) & 1) { d_trunc(op); return true; } break;
+    case OP_ADDD: if constexpr ((MASK >> OP_ADDD) & 1) { d_addd(op); return true; } break;
+    case OP_ZERO: if constexpr ((MASK >> OP_ZERO) & 1) { d_zero(op); return true; } break;
+    case OP_MVT:
+      if constexpr ((MASK >> OP_MVT) & 1) {
+        if constexpr (kInlineSolveOps) mvt_body(op);
+        else d_mvt(op);
+        return true;
+      }
+      break;
+    case OP_MVROW:
+      if constexpr ((MASK >> OP_MVROW) & 1) {
+        if constexpr (kInlineSolveOps) mvrow_body(op);
+        else d_mvrow(op);
+        return true;
+      }
+      break;
+    default: break;
+  }
+  return false;
+}
+
+template <unsigned MASK>
+__device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np, int* queue,
+                                       int* ctrl, int n, long long timeout) {
   __shared__ int s_op;
   const int tid = threadIdx.x;
   for (;;) {
@@ -1658,7 +1716,8 @@ __global__ void __launch_bounds__(NT) k_dataflow(const DfPart* __restrict__ part
     if (g < 0) break;
     const DfPart& pt = parts[np == 1 ? 0 : df_part(parts, np, g)];
     const int idx = g - pt.base;
-    run_op(reinterpret_cast<const Op*>(pt.ops)[idx]);
+    if (!run_op_masked<MASK>(reinterpret_cast<const Op*>(pt.ops)[idx]) && tid == 0)
+      __hip_atomic_store(&ctrl[2], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (tid == 0) {
       // one release fence publishes the op's writes; the in-degree
@@ -1686,6 +1745,19 @@ __global__ void __launch_bounds__(NT) k_dataflow(const DfPart* __restrict__ part
     }
     __syncthreads();
   }
+}
+
+// The executor over factor schedules (one or several parts) and over solve
+// schedules.
+__global__ void __launch_bounds__(NT) k_df_factor(const DfPart* __restrict__ parts, int np,
+                                                  int* queue, int* ctrl, int n,
+                                                  long long timeout) {
+  df_run<DF_FACTOR_TYPES>(parts, np, queue, ctrl, n, timeout);
+}
+__global__ void __launch_bounds__(NT) k_df_solve(const DfPart* __restrict__ parts, int np,
+                                                 int* queue, int* ctrl, int n,
+                                                 long long timeout) {
+  df_run<DF_SOLVE_TYPES>(parts, np, queue, ctrl, n, timeout);
 }
 
 static size_t lds_bytes(int type) {
@@ -1727,14 +1799,24 @@ static hipError_t launch_ops(int type, const Op* ops, int count, hipStream_t s) 
 extern "C" size_t hlu_lds_bytes(int type) { return hlu::lds_bytes(type); }
 
 // Dataflow execution of a schedule: reset kernel + persistent kernel with
-// `workers` workgroups (LDS of the largest op type).
-static hipError_t df_attr() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hlu::k_dataflow),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sizeof(hlu::TruncShared));
-  if (e == hipSuccess) done = true;
+// `workers` workgroups.  kind 0 runs factor schedules (LDS of the largest
+// factor op), kind 1 solve schedules.
+static size_t df_lds(int kind) {
+  if (kind == 0) return sizeof(hlu::TruncShared);
+  size_t m = 0;
+  for (int t : {hlu::OP_TRSM_L, hlu::OP_MVT, hlu::OP_MVROW}) m = std::max(m, hlu::lds_bytes(t));
+  return m;
+}
+static const void* df_kernel(int kind) {
+  return kind == 0 ? reinterpret_cast<const void*>(&hlu::k_df_factor)
+                   : reinterpret_cast<const void*>(&hlu::k_df_solve);
+}
+static hipError_t df_attr(int kind) {
+  static bool done[2] = {false, false};
+  if (done[kind]) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(df_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)df_lds(kind));
+  if (e == hipSuccess) done[kind] = true;
   return e;
 }
 
@@ -1742,29 +1824,35 @@ static hipError_t df_attr() {
 // persistent workgroups: reset of the in-degrees and the queue (seeded with
 // the nready globally numbered ops in ready0), then the executor.  When
 // `status` is given, it is cleared first.
-extern "C" hipError_t hlu_launch_dataflow(const void* parts, int np, int* queue,
+extern "C" hipError_t hlu_launch_dataflow(int kind, const void* parts, int np, int* queue,
                                           const int* ready0, int nready, int* ctrl, int n,
                                           int workers, long long timeout, int32_t* status,
                                           hipStream_t s) {
-  hipError_t e = df_attr();
+  if (kind != 0 && kind != 1) return hipErrorInvalidValue;
+  hipError_t e = df_attr(kind);
   if (e != hipSuccess) return e;
   if (n <= 0) return hipSuccess;
   const hlu::DfPart* pp = reinterpret_cast<const hlu::DfPart*>(parts);
   if (status) hipLaunchKernelGGL(hlu::k_set_int, dim3(1), dim3(64), 0, s, status, 0);
   hipLaunchKernelGGL(hlu::k_df_reset, dim3((n + 255) / 256), dim3(256), 0, s, pp, np, queue, ready0,
                      nready, n, ctrl);
-  hipLaunchKernelGGL(hlu::k_dataflow, dim3(workers), dim3(NT), sizeof(hlu::TruncShared), s, pp, np,
-                     queue, ctrl, n, timeout);
+  if (kind == 0)
+    hipLaunchKernelGGL(hlu::k_df_factor, dim3(workers), dim3(NT), df_lds(0), s, pp, np, queue,
+                       ctrl, n, timeout);
+  else
+    hipLaunchKernelGGL(hlu::k_df_solve, dim3(workers), dim3(NT), df_lds(1), s, pp, np, queue,
+                       ctrl, n, timeout);
   return hipGetLastError();
 }
 
 // The same run as a graph (status clear, reset, executor), built explicitly.
-extern "C" hipError_t hlu_build_df_graph(const void* parts, int np, int* queue, const int* ready0,
-                                         int nready, int* ctrl, int n, int workers,
-                                         long long timeout, int32_t* status,
+extern "C" hipError_t hlu_build_df_graph(int kind, const void* parts, int np, int* queue,
+                                         const int* ready0, int nready, int* ctrl, int n,
+                                         int workers, long long timeout, int32_t* status,
                                          hipGraphExec_t* out) {
   *out = nullptr;
-  hipError_t e = df_attr();
+  if (kind != 0 && kind != 1) return hipErrorInvalidValue;
+  hipError_t e = df_attr(kind);
   if (e != hipSuccess) return e;
   hipGraph_t g;
   e = hipGraphCreate(&g, 0);
@@ -1793,10 +1881,10 @@ extern "C" hipError_t hlu_build_df_graph(const void* parts, int np, int* queue, 
   if (e == hipSuccess) {
     void* args[] = {&pp, &np, &queue, &ctrl, &n, &timeout};
     hipKernelNodeParams p = {};
-    p.func = reinterpret_cast<void*>(&hlu::k_dataflow);
+    p.func = const_cast<void*>(df_kernel(kind));
     p.gridDim = dim3(workers);
     p.blockDim = dim3(NT);
-    p.sharedMemBytes = (unsigned)sizeof(hlu::TruncShared);
+    p.sharedMemBytes = (unsigned)df_lds(kind);
     p.kernelParams = args;
     e = hipGraphAddKernelNode(&n2, g, &n1, 1, &p);
   }
