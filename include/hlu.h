@@ -123,6 +123,28 @@ hlu_status hlu_assemble(hlu_handle h, void* stream);
 /* Restore the factor copy from the pristine copy (device-to-device). */
 hlu_status hlu_reset(hlu_handle h, void* stream);
 
+/* A second handle over the same plan (cluster tree, block tree, schedules
+ * and host images are shared, read-only, not copied): it needs a buffer of
+ * its own (hlu_bind) and is filled either by hlu_assemble or, without any
+ * host-to-device traffic, by hlu_assemble_from.  Executor, graph and worker
+ * settings are copied.  Clones and the original may be used concurrently on
+ * different streams; each is destroyed by hlu_destroy (the plan lives until
+ * the last one is gone). */
+hlu_status hlu_clone(hlu_handle src, hlu_handle* out);
+
+/* Fill h's bound buffer from the assembled handle src of the same plan: the
+ * factor copy and its pristine copy from src's pristine copy, and the
+ * matvec copy, device to device on `stream`.  src's pristine and matvec
+ * copies are only read (src may be factoring meanwhile).  HLU_ERR_ARG if
+ * the two do not share a plan, HLU_ERR_STATE if h is unbound or src is not
+ * assembled. */
+hlu_status hlu_assemble_from(hlu_handle h, hlu_handle src, void* stream);
+
+/* Workgroups of the dataflow executor for this handle's factor and solve
+ * launches: 0 (the default) one per compute unit; a smaller count leaves
+ * compute units to launches of other handles on other streams. */
+hlu_status hlu_set_workers(hlu_handle h, int workers);
+
 /* H-LU of the factor copy in place (Sec. 3.1 sequence, recursive), one
  * launch per kernel type per wave of the static schedule.  Zero pivots are
  * recorded on the device and reported by hlu_sync. */
@@ -179,7 +201,9 @@ void hlu_batch_destroy(hlu_batch b);
  * dimension ld, original order; they may alias).  With refine_tol > 0 the
  * solution is refined with FP64 residuals of the matvec copy until the
  * backward error max_j |r_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf) <=
- * refine_tol (this call then synchronises the stream once per step).
+ * refine_tol (this call then synchronises the stream once per step).  Each
+ * column is corrected only while its own backward error exceeds refine_tol,
+ * so a column's result is the same whatever other columns share the call.
  * HLU_ERR_STATE before hlu_factor; HLU_ERR_ARG if nrhs > max_nrhs. */
 hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
                      int64_t ld, void* stream);

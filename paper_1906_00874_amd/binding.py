@@ -69,6 +69,9 @@ _sig = {
     "hlu_bind": (C.c_int, [_P, _P, C.c_size_t]),
     "hlu_assemble": (C.c_int, [_P, _P]),
     "hlu_reset": (C.c_int, [_P, _P]),
+    "hlu_clone": (C.c_int, [_P, C.POINTER(_P)]),
+    "hlu_assemble_from": (C.c_int, [_P, _P, _P]),
+    "hlu_set_workers": (C.c_int, [_P, C.c_int]),
     "hlu_factor": (C.c_int, [_P, _P]),
     "hlu_batch_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(_P)]),
     "hlu_batch_required_bytes": (C.c_size_t, [_P]),
@@ -150,6 +153,25 @@ class HLU:
         self.buf = None
         if assemble:
             self.bind_and_assemble()
+
+    def clone(self, bind=True, stream=None):
+        """A handle over the same plan with a buffer of its own, filled from
+        this (assembled) handle device to device when `bind` is true."""
+        c = HLU.__new__(HLU)
+        h = C.c_void_p()
+        _check(lib.hlu_clone(self.h, C.byref(h)))
+        c.h, c.n, c.params, c.device, c.buf = h, self.n, self.params, self.device, None
+        if bind:
+            c.bind()
+            _check(lib.hlu_assemble_from(c.h, self.h, _stream(stream)))
+        return c
+
+    def assemble_from(self, src, stream=None):
+        _check(lib.hlu_assemble_from(self.h, src.h, _stream(stream)))
+
+    def set_workers(self, workers):
+        """Dataflow workgroups per launch (0: one per compute unit)."""
+        _check(lib.hlu_set_workers(self.h, int(workers)))
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/hlu.h"
@@ -23,6 +24,8 @@ extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, dou
 extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
                                         int n, int nrhs, double* out, hipStream_t s);
 extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s);
+extern "C" hipError_t hlu_launch_axpy_masked(const double* d, double* x, int ld, int n, int nrhs,
+                                             const int32_t* active, hipStream_t s);
 extern "C" hipError_t hlu_launch_wave(const void* ops, int count, size_t lds, hipStream_t s);
 extern "C" size_t hlu_lds_bytes(int type);
 extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* starts,
@@ -221,7 +224,11 @@ static DfArrays df_solve(const hlu::Plan& p) {
 }
 
 struct hlu_handle_s {
-  hlu::Plan plan;
+  // The plan (schedules, layout, host images of the assembled data) is
+  // immutable once built and shared by the clones of a handle.
+  std::shared_ptr<hlu::Plan> shared;
+  hlu::Plan& plan;
+  explicit hlu_handle_s(std::shared_ptr<hlu::Plan> p) : shared(std::move(p)), plan(*shared) {}
   char* base = nullptr;
   size_t bytes = 0;
   bool assembled = false;
@@ -234,6 +241,7 @@ struct hlu_handle_s {
   hlu_params params;
   bool use_graph = true;
   int executor = 0;                   // 0: waves, 1: dataflow
+  int workers = 0;                    // dataflow workgroups (0: one per compute unit)
   hipGraphExec_t graph_f = nullptr;   // factor schedule (with status reset)
   hipGraphExec_t graph_s = nullptr;   // solve schedule
   hipGraphExec_t graph_df = nullptr;  // factor by the dataflow executor
@@ -284,8 +292,12 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
     return fail(HLU_ERR_ARG, "unknown precision");
   if (p->refine_max_iter < 0 || p->refine_max_iter > 15)
     return fail(HLU_ERR_ARG, "refine_max_iter must be in [0, 15]");
-  hlu_handle h = new (std::nothrow) hlu_handle_s;
-  if (!h) return fail(HLU_ERR_NOMEM, "host allocation failed");
+  hlu_handle h = nullptr;
+  try {
+    h = new hlu_handle_s(std::make_shared<hlu::Plan>());
+  } catch (const std::bad_alloc&) {
+    return fail(HLU_ERR_NOMEM, "host allocation failed");
+  }
   h->params = *p;
   hlu::Params prm;
   prm.kernel = p->kernel;
@@ -311,6 +323,23 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
     delete h;
     return fail(HLU_ERR_NOMEM, "host allocation failed while planning");
   }
+  *out = h;
+  return HLU_OK;
+}
+
+hlu_status hlu_clone(hlu_handle src, hlu_handle* out) {
+  if (!src || !out) return fail(HLU_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  hlu_handle h = nullptr;
+  try {
+    h = new hlu_handle_s(src->shared);
+  } catch (const std::bad_alloc&) {
+    return fail(HLU_ERR_NOMEM, "host allocation failed");
+  }
+  h->params = src->params;
+  h->use_graph = src->use_graph;
+  h->executor = src->executor;
+  h->workers = src->workers;
   *out = h;
   return HLU_OK;
 }
@@ -522,6 +551,36 @@ hlu_status hlu_assemble(hlu_handle h, void* stream) {
   return HLU_OK;
 }
 
+hlu_status hlu_assemble_from(hlu_handle h, hlu_handle src, void* stream) {
+  if (!h || !src) return fail(HLU_ERR_ARG, "NULL handle");
+  if (h->shared != src->shared) return fail(HLU_ERR_ARG, "handles do not share one plan");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  if (!src->assembled) return fail(HLU_ERR_STATE, "source not assembled");
+  hipStream_t s = (hipStream_t)stream;
+  const hlu::Plan& p = h->plan;
+  char* b = h->base;
+  HIPCHK(hipMemcpyAsync(b + p.off_work, src->base + p.off_pristine, p.size_work,
+                        hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(b + p.off_pristine, src->base + p.off_pristine, p.size_work,
+                        hipMemcpyDeviceToDevice, s));
+  if (p.size_mv)
+    HIPCHK(hipMemcpyAsync(b + p.off_mv, src->base + p.off_mv, p.size_mv, hipMemcpyDeviceToDevice,
+                          s));
+  HIPCHK(hlu_launch_set_int((int32_t*)(b + p.off_status), 0, s));
+  h->anorm = src->anorm;
+  h->assembled = true;
+  h->factored = false;
+  return HLU_OK;
+}
+
+hlu_status hlu_set_workers(hlu_handle h, int workers) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (workers < 0 || workers > 65536) return fail(HLU_ERR_ARG, "workers must be in [0, 65536]");
+  if (workers != h->workers) h->drop_graphs();
+  h->workers = workers;
+  return HLU_OK;
+}
+
 hlu_status hlu_reset(hlu_handle h, void* stream) {
   if (!h) return fail(HLU_ERR_ARG, "NULL handle");
   if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
@@ -603,6 +662,7 @@ static hlu_status run_dataflow(hlu_handle h, const DfArrays& da, hipStream_t s,
   hlu_status st = device_facts(&cus, &tps);
   if (st != HLU_OK) return st;
   const long long timeout = 20 * tps;   // no single wait may exceed 20 s
+  if (h->workers > 0) cus = h->workers;
   const bool factor = da.sc == &p.fsched;
   int32_t* status = factor ? (int32_t*)(b + p.off_status) : nullptr;
   int* queue = (int*)(b + da.queue);
@@ -847,9 +907,13 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
   h->eta_final = 0.0;
   const double tol = p.prm.refine_tol;
   if (tol > 0.0) {
+    // Each column is refined until its own backward error meets the
+    // tolerance and is left alone afterwards, so a column's result does not
+    // depend on the other columns solved with it.
     double* out = (double*)(b + p.off_eta);
+    int32_t* active_dev = (int32_t*)(out + 3 * p.prm.max_nrhs);
     std::vector<double> mx(3 * nrhs);
-    double best = INFINITY;
+    std::vector<int32_t> active(nrhs);
     for (int it = 0;; ++it) {
       st = run_mv(h, X, B, 1.0, -1.0, Y, nrhs, s);                       // Y = B - A X
       if (st != HLU_OK) return st;
@@ -861,16 +925,22 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
         double den = h->anorm * mx[3 * j + 1] + mx[3 * j + 2];
         double e = den > 0 ? mx[3 * j] / den : (mx[3 * j] > 0 ? INFINITY : 0.0);
         if (!(e <= INFINITY)) e = INFINITY;  // NaN
+        // a column stays converged once it was (its X no longer changes)
+        if (it > 0 && !active[j]) e = std::min(e, tol);
+        active[j] = e > tol;
         eta = std::max(eta, e);
       }
       if (it < 16) h->eta_hist[it] = eta;
       h->eta_final = eta;
-      best = std::min(best, eta);
       if (eta <= tol) break;
       if (it >= p.prm.refine_max_iter) { h->not_converged = true; break; }
+      HIPCHK(hipMemcpyAsync(active_dev, active.data(), sizeof(int32_t) * nrhs,
+                            hipMemcpyHostToDevice, s));
       st = run_solve(h, s);                                              // Y = A_H^{-1} Y
       if (st != HLU_OK) return st;
-      HIPCHK(hlu_launch_vec(2, Y, n, X, n, nullptr, n, nrhs, s));        // X += Y
+      // X += Y (active columns); `active` is next written after the stream
+      // synchronisation of the following iteration, which follows this copy
+      HIPCHK(hlu_launch_axpy_masked(Y, X, n, n, nrhs, active_dev, s));
       h->iters = it + 1;
     }
   }

@@ -1531,6 +1531,16 @@ __global__ void k_axpy(double* X, const double* D, int ld, int n, int nrhs, doub
   X[p + (size_t)j * ld] = (a == 0.0 ? 0.0 : X[p + (size_t)j * ld]) + D[p + (size_t)j * ld];
 }
 
+// X[:, j] += D[:, j] for the columns with active[j] != 0 (refinement keeps
+// converged columns as they are)
+__global__ void k_axpy_masked(double* X, const double* D, int ld, int n, int nrhs,
+                              const int32_t* active) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nrhs) return;
+  int p = (int)(e % n), j = (int)(e / n);
+  if (active[j]) X[p + (size_t)j * ld] += D[p + (size_t)j * ld];
+}
+
 // per column j: out[3j] = max|R_j|, out[3j+1] = max|X_j|, out[3j+2] = max|B_j|
 __global__ void __launch_bounds__(NT) k_colmax(const double* R, const double* X, const double* B,
                                                int ld, int n, double* out) {
@@ -1777,14 +1787,11 @@ static size_t lds_bytes(int type) {
 
 static hipError_t launch_wave(const Op* ops, int count, size_t lds, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_wave),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)LDS_TRUNC);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // set once per process (thread-safe initialisation of a local static)
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_wave),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)LDS_TRUNC);
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_wave, dim3(count), dim3(NT), lds, s, ops);
   return hipGetLastError();
 }
@@ -1812,12 +1819,12 @@ static const void* df_kernel(int kind) {
                    : reinterpret_cast<const void*>(&hlu::k_df_solve);
 }
 static hipError_t df_attr(int kind) {
-  static bool done[2] = {false, false};
-  if (done[kind]) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(df_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)df_lds(kind));
-  if (e == hipSuccess) done[kind] = true;
-  return e;
+  // set once per process and kernel (thread-safe initialisation of local statics)
+  static const hipError_t e0 = hipFuncSetAttribute(
+      df_kernel(0), hipFuncAttributeMaxDynamicSharedMemorySize, (int)df_lds(0));
+  static const hipError_t e1 = hipFuncSetAttribute(
+      df_kernel(1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)df_lds(1));
+  return kind == 0 ? e0 : e1;
 }
 
 // Runs the union of np schedule parts (n ops in all) with `workers`
@@ -1974,6 +1981,15 @@ extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, dou
     hipLaunchKernelGGL(hlu::k_scatter, g, b, 0, s, a, ldy, y, lda, perm, n, nrhs);
   else if (what == 2) hipLaunchKernelGGL(hlu::k_axpy, g, b, 0, s, y, a, ldy, n, nrhs, 1.0);
   else if (what == 3) hipLaunchKernelGGL(hlu::k_axpy, g, b, 0, s, y, a, ldy, n, nrhs, 0.0);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hlu_launch_axpy_masked(const double* d, double* x, int ld, int n, int nrhs,
+                                             const int32_t* active, hipStream_t s) {
+  int64_t tot = (int64_t)n * nrhs;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(hlu::k_axpy_masked, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, d,
+                     ld, n, nrhs, active);
   return hipGetLastError();
 }
 
