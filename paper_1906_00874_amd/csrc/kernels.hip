@@ -54,7 +54,7 @@ __device__ __forceinline__ double dpp_d(double x) {
 // clock, written by thread 0)
 __device__ __forceinline__ void put_cost(const Op& op, double flops, double bytes,
                                          double cap_hit = 0.0, double rank = 0.0,
-                                         double width = 0.0) {
+                                         double width = 0.0, double detail = 0.0) {
   if (op.cost && threadIdx.x == 0) {
     double* c = reinterpret_cast<double*>(op.cost);
     c[0] = flops;
@@ -63,6 +63,7 @@ __device__ __forceinline__ void put_cost(const Op& op, double flops, double byte
     c[3] = rank;
     c[5] = (double)wall_clock64();
     c[6] = width;
+    c[7] = detail;
   }
 }
 
@@ -817,8 +818,10 @@ __device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K
 // step s), piv[0..r) are the pivots in order, piv[r..K) the remaining
 // columns, and r is the numerical rank.  lv (64 doubles, 16-byte aligned)
 // carries each step's row of R to every lane.
+template <bool TRACE_STOP = false>
 __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv, int* piv, int K,
-                                                 int* r_out) {
+                                                 int* r_out, double trace_stop = 0.0,
+                                                 double* trace_out = nullptr) {
   const int lane = threadIdx.x & 63;
   const bool in = lane < K;
   double g[KM];
@@ -830,7 +833,15 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
   wave_argmax(dmax0, dummy);
   bool alive = in;
   int r = 0;
+  double trace = 0.0;
   for (int s = 0; s < K; ++s) {
+    if constexpr (TRACE_STOP) {
+      // stop once the residual diagonal (the squared distances of the
+      // remaining rows from the span of the chosen ones) sums to at most
+      // trace_stop
+      trace = group_sum(alive ? fmax(d, 0.0) : 0.0, 64);
+      if (!(trace > trace_stop)) break;
+    }
     double v = alive ? d : -1.0;
     int p = lane;
     wave_argmax(v, p);
@@ -858,6 +869,10 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
   const unsigned long long mask = __ballot(alive);
   if (alive) piv[r + __popcll(mask & ((1ull << lane) - 1ull))] = lane;
   if (lane == 0) *r_out = r;
+  if constexpr (TRACE_STOP) {
+    trace = group_sum(alive ? fmax(d, 0.0) : 0.0, 64);
+    if (lane == 0) *trace_out = trace;
+  }
 }
 
 // Tx = D Pi_x R11^{-1} W_k into m (rows = stacked columns), W_k in z and
@@ -957,9 +972,11 @@ __device__ __forceinline__ int jphys(int p) { return ((p & 7) << 3) | (p >> 3); 
 // registers.  Squared column norms (by position) are recomputed at every
 // sweep and carried through the rotations in between, so a round reduces
 // one inner product.  Returns the buffer holding the result (0: m, 1: gy).
-__device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, double ms) {
+__device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, double ms,
+                                            int& sweeps) {
   const int tid = threadIdx.x;
   const int ncol = ry + (ry & 1);
+  sweeps = 0;
   if (ncol < 2 || rx <= 0 || !(ms > 0.0)) return 0;
   const int npair = ncol / 2, nm1 = ncol - 1;
   int grp = 64;
@@ -1034,6 +1051,7 @@ __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, dou
       __syncthreads();
       cur ^= 1;
     }
+    ++sweeps;
     // stop once no pair had a cosine above 1e-12
     if (!(block_max(sh, mu) > 1e-24)) break;
   }
@@ -1055,7 +1073,7 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
   const int tid = threadIdx.x, wid = tid >> 6;
   double flops = 0.0, bytes = 0.0;
   const double es = U.dt == DT_F64 ? 8.0 : 4.0;
-  int capped_any = 0, Kmax = 0;
+  int capped_any = 0, Kmax = 0, passes = 0, sweeps_all = 0, rxmax = 0, rymax = 0;
   if (tid == 0) sh.te = 0;
   __syncthreads();
   while (sh.te < nterms) {
@@ -1135,11 +1153,65 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
         }
     }
     const double ms = block_sum(sh, msq);
-    double (*MF)[KM + 1] = trunc_jacobi(sh, rx, ry, ms) ? sh.gy : sh.m;
+    // 4b. for a tolerance-driven truncation, shrink the SVD to the part of M
+    // that can matter: a pivoted Cholesky of G = M M^T, stopped once the
+    // discarded rows of M (orthogonal to the kept ones) hold at most
+    // (eps/4)^2 |M|_F^2, leaves L (rx x jc) with L L^T = M P M^T for an
+    // orthogonal projector P.  The left singular vectors of L are those of
+    // M P, and the discarded part is Frobenius-orthogonal to every
+    // projection of M P, so its squared norm simply opens the tail of the
+    // rank rule.  Squaring M is harmless at eps >= 1e-6 (FP64 Gram).
+    int jc = ry;
+    double tail0 = 0.0;
+    if (fixed == 0 && eps >= 1e-6 && rx > 8 && ry > 8) {
+      {
+        const int ti = tid % 16, tj = tid / 16;
+        double acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int j = 0; j < ry; ++j) {
+          const int fj = jphys(j);
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[u] = sh.m[ti + 16 * u][fj];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bv[v] = sh.m[tj + 16 * v][fj];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sh.gy[ti + 16 * u][tj + 16 * v] = acc[u][v];
+      }
+      __syncthreads();
+      if (wid == 0)
+        trunc_pchol_wave<true>(sh.gy, sh.lv[0], sh.py, rx, &sh.k, eps * eps * ms / 16.0,
+                               &sh.mnorm);
+      __syncthreads();
+      jc = __builtin_amdgcn_readfirstlane(sh.k);
+      tail0 = sh.mnorm;
+      // L into the Jacobi buffer: column s of L is row s of the factored G
+      for (int e = tid; e < rx * KM; e += NT) {
+        const int i = e % rx, c = e / rx;
+        sh.m[i][jphys(c)] = c < jc ? sh.gy[c][i] : 0.0;
+      }
+      __syncthreads();
+    }
+    int sweeps;
+    double (*MF)[KM + 1] = trunc_jacobi(sh, rx, jc, ms, sweeps) ? sh.gy : sh.m;
+    passes += 1;
+    sweeps_all += sweeps;
+    rxmax = max(rxmax, rx);
+    rymax = max(rymax, jc);
     // 5. singular values (column norms, by position; an odd ry has one zero
     // column more), descending order (stable), rank choice
-    const int nr = rx > 0 ? ry : 0;
-    const int npos = rx > 0 ? ry + (ry & 1) : 0;
+    const int nr = rx > 0 ? jc : 0;
+    const int npos = rx > 0 ? jc + (jc & 1) : 0;
     {
       const int j = tid >> 2, part = tid & 3;
       double s = 0.0;
@@ -1168,10 +1240,10 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
       if (fixed > 0) {
         k = min(fixed, lim);
       } else {
-        double tot = 0.0;
+        double tot = tail0;
         for (int j = 0; j < npos; ++j) tot += sh.sig[j] * sh.sig[j];
         const double thr = eps * eps * tot;
-        double tail = 0.0;
+        double tail = tail0;
         k = nr;
         for (int j = nr; j >= 0; --j) {
           if (tail <= thr) k = j;
@@ -1240,7 +1312,9 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
              21.0 * K * K * K + 2.0 * (m + n) * K * k;
     bytes += es * (double)(m + n) * (K + k);
   }
-  put_cost(op, flops, bytes, (double)capped_any, (double)sh.k, (double)Kmax);
+  // detail: passes, Jacobi sweeps, largest Cholesky ranks of the two sides
+  put_cost(op, flops, bytes, (double)capped_any, (double)sh.k, (double)Kmax,
+           passes * 1e9 + sweeps_all * 1e6 + rxmax * 1e3 + rymax);
 }
 
 // ---------------------------------------------------------------- solve updates

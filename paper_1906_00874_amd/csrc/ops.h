@@ -51,7 +51,9 @@ enum OpType : int32_t {
 
 // Bytes of the per-op record a kernel writes at Op::cost: doubles {model
 // flops, algorithmic bytes, rank-capacity hit, rank, start tick, end tick,
-// stack width, unused}.
+// stack width, detail}; a truncation's detail packs passes * 1e9 + Jacobi
+// sweeps * 1e6 + largest Cholesky rank of the left stack * 1e3 + largest
+// column count of the SVD core.
 constexpr int kCostRecBytes = 64;
 constexpr int kCostRecDoubles = kCostRecBytes / 8;
 
