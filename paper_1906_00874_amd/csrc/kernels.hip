@@ -1802,28 +1802,49 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     const int idx = g - pt.base;
     if (!run_op_masked<MASK>(reinterpret_cast<const Op*>(pt.ops)[idx]) && tid == 0)
       __hip_atomic_store(&ctrl[2], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // one release fence (first wavefront, after the barrier that completed
+    // every wavefront's stores) publishes the op's writes; then all threads
+    // decrement the successors' in-degrees at once (relaxed), so an op with
+    // many successors pays one atomic round trip, not one per successor.
+    // A thread that brings a successor to zero acquires (its decrement read
+    // the others' through the chain of read-modify-writes, so their fences
+    // synchronise with it) and pushes the successor with a release store;
+    // each wavefront reserves the queue slots of its pushes with one atomic.
     __syncthreads();
-    if (tid == 0) {
-      // one release fence publishes the op's writes; the in-degree
-      // decrements are relaxed.  The predecessor that brings a successor to
-      // zero acquires (its decrement read the others' through the chain of
-      // read-modify-writes, so their fences synchronise with it) and then
-      // pushes the successor with a release store.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    {
       const int* succ_off = reinterpret_cast<const int*>(pt.succ_off);
       const int* succ = reinterpret_cast<const int*>(pt.succ);
       int* indeg = reinterpret_cast<int*>(pt.indeg);
-      for (int e = succ_off[idx]; e < succ_off[idx + 1]; ++e) {
-        const int t = succ[e];
-        if (__hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+      const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
+      const int lane = tid & 63;
+      for (int eb = e0; eb < e1; eb += NT) {
+        const int e = eb + tid;
+        int t = -1;
+        bool ready = false;
+        if (e < e1) {
+          t = succ[e];
+          ready = __hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) == 1;
+        }
+        const unsigned long long mask = __ballot(ready);
+        if (mask) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          const int slot =
-              __hip_atomic_fetch_add(&ctrl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (slot < n)
-            __hip_atomic_store(&queue[slot], pt.base + t, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-          else
-            __hip_atomic_store(&ctrl[2], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int leader = __ffsll((long long)mask) - 1;
+          int slot0 = 0;
+          if (lane == leader)
+            slot0 = __hip_atomic_fetch_add(&ctrl[1], __popcll(mask), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+          slot0 = __shfl(slot0, leader);
+          if (ready) {
+            const int slot = slot0 + __popcll(mask & ((1ull << lane) - 1ull));
+            if (slot < n)
+              __hip_atomic_store(&queue[slot], pt.base + t, __ATOMIC_RELEASE,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+            else
+              __hip_atomic_store(&ctrl[2], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
       }
     }
