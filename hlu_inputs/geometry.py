@@ -1,7 +1,7 @@
 """Boundary meshes of the kind the paper's 3D Laplace BEM problems live on.
 
 The paper's experiments discretise integral equations on surfaces with the
-d=3 Laplace kernel (Sec. 5.1, "Mathematical problems") but do not publish the
+d=3 Laplace kernel (Sec. 6.1, "Mathematical problems") but do not publish the
 geometries.  The stand-in used here is the unit sphere triangulated by
 repeated midpoint subdivision of an icosahedron, one degree of freedom per
 flat triangle (its centroid, with the flat triangle's area as quadrature

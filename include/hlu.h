@@ -2,7 +2,7 @@
  * hlu.h -- C-ABI of the MI355X (gfx950) hierarchical-matrix LU library.
  *
  * The library builds an H-matrix for the d=3 Laplace kernel of the paper's
- * BEM problems (Sec. 5.1) from surface points, an admissibility parameter
+ * BEM problems (Sec. 6.1) from surface points, an admissibility parameter
  * eta and a leaf size (cluster tree: Algorithm 1; block tree: Algorithm 2),
  * factors it with the recursive H-LU (the O1.1-O5.5 sequence of Sec. 3.1,
  * with low-rank arithmetic of Sec. 3.1 "Low-rank blocks"), and solves with
@@ -48,7 +48,7 @@ typedef enum {
 } hlu_status;
 
 /* Entries of the collocation matrix for the d=3 Laplace kernel
- * g(x,y) = 1/(4 pi |x-y|) (Sec. 5.1) between panel centroids x_i:
+ * g(x,y) = 1/(4 pi |x-y|) (Sec. 6.1) between panel centroids x_i:
  *   WEIGHTED: A_ij = area_j / (4 pi |x_i - x_j|)   (one-point quadrature)
  *   POINT:    A_ij = 1 / (4 pi |x_i - x_j|)
  * and in both A_ii = 2 sqrt(area_i/pi)/(4 pi) sqrt(pi) + 1. */
@@ -160,7 +160,7 @@ hlu_status hlu_set_graph(hlu_handle h, int enable);
  * static schedule.  1: one persistent launch that runs each op as soon as
  * its own predecessors in the dependency graph have finished (a device-side
  * dataflow executor: the analogue of nested tasks with weak dependencies and
- * early release, Sec. 4.3).  Both give bitwise identical factors.  A wait in
+ * early release, Sec. 5.2).  Both give bitwise identical factors.  A wait in
  * the dataflow executor that exceeds 20 s raises an error flag that makes
  * every workgroup exit; hlu_sync then returns HLU_ERR_DEVICE. */
 hlu_status hlu_set_executor(hlu_handle h, int mode);

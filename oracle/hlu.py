@@ -10,7 +10,7 @@ what the method states:
 * storage types: dense, low-rank X = A B^* (Sec. 3.1, "Low-rank blocks"),
   and 2x2 partitioned blocks (Sec. 2, hmatrix structure);
 * H-LU: the sequence O1.1-O5.5 of Sec. 3.1 applied recursively, with the
-  partitioned triangular solve O2.1-O2.6 of Sec. 4.3;
+  partitioned triangular solve O2.1-O2.6 of Sec. 5.2;
 * low-rank arithmetic: matrix-vector and matrix-matrix products, triangular
   solves on the k columns of the factors, and addition followed by an SVD
   that discards small singular values (Sec. 3.1, "Low-rank blocks").
@@ -54,7 +54,7 @@ def _count(f):
 
 
 # ---------------------------------------------------------------------------
-# kernel entries (Sec. 5.1, d = 3 Laplace kernel g(x,y) = 1/(4 pi |x-y|))
+# kernel entries (Sec. 6.1, d = 3 Laplace kernel g(x,y) = 1/(4 pi |x-y|))
 # ---------------------------------------------------------------------------
 def kernel_entries(xyz, area, rows, cols, reading=READING_WEIGHTED):
     """Dense block A[rows, cols] of the collocation matrix.

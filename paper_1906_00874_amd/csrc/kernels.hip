@@ -1680,7 +1680,7 @@ __global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
 
 // ---------------------------------------------------------------- dataflow
 // Persistent executor of a whole schedule (factor or solve): the device analogue of
-// running nested tasks with weak dependencies and early release (Sec. 4.3)
+// running nested tasks with weak dependencies and early release (Sec. 5.2)
 // -- an op starts as soon as its own predecessors have finished, across
 // recursion levels, instead of waiting for a whole wave.
 //   ctrl[0]: next queue slot to take, ctrl[1]: next slot to fill,

@@ -1,7 +1,7 @@
 // Device-visible descriptors of the static H-LU schedule.
 //
 // The host planner walks the recursive H-LU (the O1.1-O5.5 sequence of the
-// paper's Sec. 3.1, with the partitioned solves of Sec. 4.3) once, emits one
+// paper's Sec. 3.1, with the partitioned solves of Sec. 5.2) once, emits one
 // descriptor per primitive operation on dense leaf blocks and on the factor
 // panels of low-rank blocks, and groups independent operations of the same
 // type into waves.  Every kernel processes one descriptor per workgroup.

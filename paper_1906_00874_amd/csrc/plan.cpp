@@ -6,14 +6,14 @@
 //  * block tree (Algorithm 2) with min(diam t, diam s) <= eta * dist(t, s);
 //  * host assembly: near-field blocks exactly, far-field blocks by adaptive
 //    cross approximation followed by Householder QR of both factors and a
-//    Jacobi SVD of the small core (the "SVD recompression" of Sec. 5.1),
+//    Jacobi SVD of the small core (the "SVD recompression" of Sec. 6.1),
 //    truncated once for the factor copy and once for the refinement copy;
 //  * a static schedule: the recursive H-LU (Sec. 3.1 sequence O1.1-O5.5 and
-//    the partitioned solves O2.1-O2.6 of Sec. 4.3) is walked once and every
+//    the partitioned solves O2.1-O2.6 of Sec. 5.2) is walked once and every
 //    primitive operation becomes a descriptor; a descriptor's wave is one
 //    more than the latest wave it conflicts with (read/write sets tracked per
 //    leaf cluster of every panel), the device analogue of the paper's
-//    skeleton array of representants (Sec. 4.2).
+//    skeleton array of representants (Secs. 4.1 and 5.1).
 #include "plan.hpp"
 
 #include <algorithm>
