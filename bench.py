@@ -450,9 +450,10 @@ def main():
         # per-type work of the same executor from the per-op records
         # (start/end ticks of the constant 100 MHz clock)
         r, info = h.factor_records()
-        names = ["getrf", "trsm_l", "trsm_ut", "trsm_u", "pgemm", "trunc", "addd", "zero"]
+        names = ["getrf", "trsm_l", "trsm_ut", "trsm_u", "pgemm", "trunc", "addd", "zero",
+                 "mvt", "mvrow", "trinv", "invapply"]
         dur = (r[:, 5] - r[:, 4]) / 1e5   # ms
-        for k in range(8):
+        for k in range(len(names)):
             mk = info[:, 0] == k
             if mk.any():
                 breakdown[names[k]] = dict(ops=int(mk.sum()), wg_ms=round(float(dur[mk].sum()), 1),

@@ -37,6 +37,12 @@ extern "C" {
 
 typedef struct hlu_handle_s* hlu_handle;
 
+/* Number of op types of the schedules (length of the per-type arrays of the
+ * diagnostic calls): 0 leaf LU, 1-3 leaf solves (L, U^T, U), 4 panel
+ * product, 5 truncation, 6 dense update, 7 zeroing, 8 V^T X, 9 row update,
+ * 10 leaf inverses, 11 inverse application. */
+#define HLU_OP_TYPES 12
+
 typedef enum {
     HLU_OK = 0,
     HLU_ERR_ARG = 1,            /* invalid argument (NULL, n<1, NaN input, ...) */
@@ -167,7 +173,8 @@ hlu_status hlu_set_executor(hlu_handle h, int mode);
 
 /* hlu_factor with a HIP event pair around every launch on `stream`;
  * returns the summed launch durations (ms) and launch counts per op type
- * (arrays of 8).  Synchronises the stream; used for roofline figures. */
+ * (arrays of HLU_OP_TYPES).  Synchronises the stream; used for roofline
+ * figures. */
 hlu_status hlu_factor_profile(hlu_handle h, void* stream, double* ms_per_type,
                               int64_t* launches_per_type);
 
@@ -224,18 +231,21 @@ hlu_status hlu_validate(hlu_handle h);
 /* Plan statistics. */
 hlu_status hlu_get_stats(hlu_handle h, hlu_plan_stats* out);
 
-/* Per-op-type totals of the last factorisation (arrays of 8, indexed by op
- * type: 0 getrf, 1-3 leaf solves, 4 panel products, 5 truncations, 6 dense
- * updates, 7 zero fills): model flops, algorithmic bytes and op counts,
- * summed from the records each kernel writes.  Synchronous. */
+/* Per-op-type totals of the last factorisation (arrays of HLU_OP_TYPES,
+ * indexed by op type as listed at HLU_OP_TYPES): model flops, algorithmic
+ * bytes and op counts, summed from the records each kernel writes.
+ * Synchronous. */
 hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* counts);
 
-/* Number of kernel launches per op type in the factor schedule (8 int64). */
+/* Number of kernel launches per op type in the factor schedule
+ * (HLU_OP_TYPES int64). */
 hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches);
 
 /* Diagnostics: the per-op records of the last factorisation in schedule
  * order (8 doubles per op: model flops, algorithmic bytes, rank-capacity hit,
- * rank, start and end tick of the device wall clock, stack width, unused)
+ * rank, start and end tick of the device wall clock, stack width, detail;
+ * a truncation's detail packs passes * 1e9 + Jacobi sweeps * 1e6 + largest
+ * left Cholesky rank * 1e3 + largest SVD core width)
  * and static op information (4 int32 per op: type, wave, rows of the first
  * and second operand).  recs: ops_factor*8, info: ops_factor*4.  Synchronous. */
 hlu_status hlu_factor_records(hlu_handle h, double* recs, int32_t* info);

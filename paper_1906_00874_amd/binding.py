@@ -50,6 +50,8 @@ class PlanStats(C.Structure):
                 ("bytes_scratch", C.c_int64), ("bytes_total", C.c_int64)]
 
 
+OP_TYPES = 12   # HLU_OP_TYPES of the C header
+
 # Host views of the schedule descriptors (struct PRef / Op / Term of the
 # kernels' header), as returned by HLU.schedule_ops.
 PREF_DTYPE = np.dtype([("ptr", "<u8"), ("rankp", "<u8"), ("ld", "<i4"), ("rows", "<i4"),
@@ -198,7 +200,7 @@ class HLU:
         _check(lib.hlu_validate(self.h))
 
     def batches(self):
-        b = np.zeros(8, dtype=np.int64)
+        b = np.zeros(OP_TYPES, dtype=np.int64)
         _check(lib.hlu_factor_batches(self.h, b.ctypes.data_as(_P)))
         return b
 
@@ -230,8 +232,8 @@ class HLU:
 
     def factor_profile(self, stream=None):
         """Factor with per-launch events; returns (ms per op type, launches)."""
-        ms = np.zeros(8)
-        ln = np.zeros(8, dtype=np.int64)
+        ms = np.zeros(OP_TYPES)
+        ln = np.zeros(OP_TYPES, dtype=np.int64)
         _check(lib.hlu_factor_profile(self.h, _stream(stream), ms.ctypes.data_as(_P),
                                       ln.ctypes.data_as(_P)))
         return ms, ln
@@ -273,9 +275,9 @@ class HLU:
         return y[:, 0] if one else y
 
     def factor_cost(self):
-        f = np.zeros(8)
-        b = np.zeros(8)
-        c = np.zeros(8, dtype=np.int64)
+        f = np.zeros(OP_TYPES)
+        b = np.zeros(OP_TYPES)
+        c = np.zeros(OP_TYPES, dtype=np.int64)
         _check(lib.hlu_factor_cost(self.h, f.ctypes.data_as(_P), b.ctypes.data_as(_P),
                                    c.ctypes.data_as(_P)))
         return f, b, c

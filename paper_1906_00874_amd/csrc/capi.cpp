@@ -171,6 +171,28 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
       case hlu::OP_ZERO:
         if (!panel_ok(o.p[0], T, why) || o.p[0].rankp) return bad(why.c_str());
         break;
+      case hlu::OP_TRINV: {
+        const hlu::PRef &A = o.p[0], &W = o.p[2], &Ui = o.p[3];
+        for (int q : {0, 2, 3})
+          if (!panel_ok(o.p[q], T, why)) return bad(why.c_str());
+        const int b = A.rows;
+        if (A.cols != b || b < 1 || b > 64 || A.dt != hlu::DT_F64 || A.trans) return bad("leaf");
+        for (const hlu::PRef* q : {&W, &Ui})
+          if (q->rows != b || q->cols != b || q->ld != b || q->dt != hlu::DT_F64 || q->trans ||
+              q->rankp)
+            return bad("leaf inverse target");
+        if (o.p[1].ptr < 512 || o.p[1].ptr + 4 * b > T) return bad("pivots");
+        break;
+      }
+      case hlu::OP_INVAPPLY: {
+        const hlu::PRef &W = o.p[0], &Y = o.p[1];
+        if (!panel_ok(W, T, why) || !panel_ok(Y, T, why)) return bad(why.c_str());
+        if (W.rows != W.cols || W.rows > 64 || W.dt != hlu::DT_F64 || W.trans || W.rankp)
+          return bad("leaf inverse");
+        if (Y.rows != W.rows || Y.dt != hlu::DT_F64 || Y.trans || Y.cols > 64)
+          return bad("leaf inverse operand");
+        break;
+      }
       case hlu::OP_MVT: {
         const hlu::PRef &V = o.p[0], &X = o.p[2], &Tt = o.p[3];
         if (!panel_ok(V, T, why) || !panel_ok(X, T, why) || !panel_ok(Tt, T, why))
@@ -209,6 +231,8 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
 
 // Device offsets of one schedule's dataflow arrays.
 // (the schedule's DfPart descriptor lives at ctrl + 64)
+static_assert(HLU_OP_TYPES == hlu::OP_NTYPES, "op type count of the C-ABI");
+
 struct DfArrays {
   const hlu::Schedule* sc;
   uint64_t ops, succ_off, succ, indeg0, indeg, queue, ready0, ctrl;
@@ -364,9 +388,8 @@ hlu_status hlu_validate(hlu_handle h) {
         scp == &p.fsched
             ? (1u << hlu::OP_GETRF) | (1u << hlu::OP_TRSM_L) | (1u << hlu::OP_TRSM_UT) |
                   (1u << hlu::OP_TRSM_U) | (1u << hlu::OP_PGEMM) | (1u << hlu::OP_TRUNC) |
-                  (1u << hlu::OP_ADDD) | (1u << hlu::OP_ZERO)
-            : (1u << hlu::OP_TRSM_L) | (1u << hlu::OP_TRSM_UT) | (1u << hlu::OP_TRSM_U) |
-                  (1u << hlu::OP_MVT) | (1u << hlu::OP_MVROW);
+                  (1u << hlu::OP_ADDD) | (1u << hlu::OP_ZERO) | (1u << hlu::OP_TRINV)
+            : (1u << hlu::OP_MVT) | (1u << hlu::OP_MVROW) | (1u << hlu::OP_INVAPPLY);
     for (const auto& op : sc.ops)
       if (!((allowed >> op.type) & 1))
         return fail(HLU_ERR_ARG, "op type " + std::to_string(op.type) + " outside the " +
@@ -738,7 +761,7 @@ hlu_status hlu_factor_profile(hlu_handle h, void* stream, double* ms_per_type,
     if (err == hipSuccess) err = hipEventRecord(ev[2 * i + 1], s);
   }
   if (err == hipSuccess) err = hipStreamSynchronize(s);
-  for (int t = 0; t < 8; ++t) { ms_per_type[t] = 0.0; launches_per_type[t] = 0; }
+  for (int t = 0; t < HLU_OP_TYPES; ++t) { ms_per_type[t] = 0.0; launches_per_type[t] = 0; }
   for (size_t i = 0; i < sc.batches.size() && err == hipSuccess; ++i) {
     float ms = 0.f;
     err = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
@@ -1022,7 +1045,7 @@ hlu_status hlu_factor_cost(hlu_handle h, double* flops, double* bytes, int64_t* 
   if (no)
     HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * hlu::kCostRecBytes,
                      hipMemcpyDeviceToHost));
-  for (int t = 0; t < 8; ++t) { flops[t] = 0; bytes[t] = 0; counts[t] = 0; }
+  for (int t = 0; t < HLU_OP_TYPES; ++t) { flops[t] = 0; bytes[t] = 0; counts[t] = 0; }
   for (size_t i = 0; i < no; ++i) {
     int t = h->plan.fsched.ops[i].type;
     flops[t] += c[R * i];
@@ -1097,10 +1120,10 @@ hlu_status hlu_schedule_graph(hlu_handle h, int which, int32_t* succ_off, int32_
   return HLU_OK;
 }
 
-// Number of launches per op type in the factor schedule (array of 8).
+// Number of launches per op type in the factor schedule (HLU_OP_TYPES).
 hlu_status hlu_factor_batches(hlu_handle h, int64_t* launches) {
   if (!h || !launches) return fail(HLU_ERR_ARG, "NULL argument");
-  for (int t = 0; t < 8; ++t) launches[t] = 0;
+  for (int t = 0; t < HLU_OP_TYPES; ++t) launches[t] = 0;
   for (const auto& b : h->plan.fsched.batches) launches[b.type]++;
   return HLU_OK;
 }

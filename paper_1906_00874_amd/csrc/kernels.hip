@@ -1644,6 +1644,145 @@ __global__ void k_set_int(int32_t* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// ---------------------------------------------------------------- leaf inverses
+// From the factored leaf (b x b, L unit lower and U in place) and its
+// interchanges: W = L^{-1} P (so that W y = L^{-1} P y) and U^{-1}, both
+// b x b FP64 with leading dimension b.  Column k of L^{-1} is the forward
+// substitution of e_k (one thread per column, threads 0-63), column k of
+// U^{-1} the backward substitution of e_k (threads 64-127).  The solve then
+// applies each leaf step as one small dense product.
+#define LDS_TRINV (3 * 64 * 65 * 8 + 64 * 4)
+static_assert(LDS_TRINV <= sizeof(TruncShared), "the factor executor's LDS holds the inverses");
+__device__ void d_trinv(const Op& op) {
+  char* const smem = hlu_lds;
+  const PRef A = op.p[0], W = op.p[2], Ui = op.p[3];
+  const int b = A.rows;
+  double (*l)[65] = reinterpret_cast<double (*)[65]>(smem);
+  double (*x)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
+  double (*y)[65] = reinterpret_cast<double (*)[65]>(smem + 2 * 64 * 65 * 8);
+  int* pm = reinterpret_cast<int*>(smem + 3 * 64 * 65 * 8);
+  const int tid = threadIdx.x;
+  {
+    const double* g = reinterpret_cast<const double*>(A.ptr);
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      v[u] = (i < b && j < b) ? g[i + (size_t)j * A.ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      l[i][j] = v[u];
+    }
+  }
+  if (tid < 64) {
+    // row permutation of the interchanges applied in order: lane i holds
+    // the source row of position i
+    const int32_t* piv = reinterpret_cast<const int32_t*>(op.p[1].ptr);
+    const int pk = tid < b ? piv[tid] : tid;
+    int pr = tid;
+    for (int k = 0; k < b; ++k) {
+      const int p = __builtin_amdgcn_readlane(pk, k);
+      const int vk = __builtin_amdgcn_readlane(pr, k), vp = __builtin_amdgcn_readlane(pr, p);
+      pr = tid == k ? vp : (tid == p ? vk : pr);
+    }
+    pm[tid] = pr;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int k = tid;
+    if (k < b) {
+      for (int i = 0; i < b; ++i) {
+        double v = i == k ? 1.0 : 0.0;
+        if (i > k) {
+          double sacc = 0.0;
+          for (int m = k; m < i; ++m) sacc += l[i][m] * x[m][k];
+          v = -sacc;
+        }
+        x[i][k] = v;
+      }
+    }
+  } else if (tid < 128) {
+    const int k = tid - 64;
+    if (k < b) {
+      for (int i = b - 1; i >= 0; --i) {
+        double v = 0.0;
+        if (i <= k) {
+          double sacc = i == k ? 1.0 : 0.0;
+          for (int m = i + 1; m <= k; ++m) sacc -= l[i][m] * y[m][k];
+          v = sacc / l[i][i];
+        }
+        y[i][k] = v;
+      }
+    }
+  }
+  __syncthreads();
+  double* w = reinterpret_cast<double*>(W.ptr);
+  double* u = reinterpret_cast<double*>(Ui.ptr);
+  for (int e = tid; e < b * b; e += NT) {
+    const int i = e % b, k = e / b;
+    w[i + (size_t)pm[k] * b] = x[i][k];
+    u[i + (size_t)k * b] = y[i][k];
+  }
+  put_cost(op, 2.0 * b * b * b / 3.0, 24.0 * b * b);
+}
+
+// p1 := W p1 for a leaf inverse W (b x b) and the b x nrhs panel p1 (FP64):
+// both staged in LDS, 16 x 16 threads with 4 x 4 outputs each.
+#define LDS_INVAPPLY (2 * 64 * 65 * 8)
+__device__ __forceinline__ void invapply_body(const Op& op) {
+  char* const smem = hlu_lds;
+  const PRef Wr = op.p[0], Y = op.p[1];
+  const int b = Wr.rows, nr = pcols(Y);
+  double (*w)[65] = reinterpret_cast<double (*)[65]>(smem);
+  double (*y)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
+  const int tid = threadIdx.x;
+  const double* gw = reinterpret_cast<const double*>(Wr.ptr);
+  double* gy = reinterpret_cast<double*>(Y.ptr);
+  {
+    double v[16], q[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      v[u] = (i < b && j < b) ? gw[i + (size_t)j * Wr.ld] : 0.0;
+      q[u] = (i < b && j < nr) ? gy[i + (size_t)j * Y.ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      w[i][j] = v[u];
+      y[i][j] = q[u];
+    }
+  }
+  __syncthreads();
+  const int ti = tid % 16, tj = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k = 0; k < b; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) av[u] = w[ti + 16 * u][k];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bv[v] = y[k][tj + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + 16 * u, j = tj + 16 * v;
+      if (i < b && j < nr) gy[i + (size_t)j * Y.ld] = acc[u][v];
+    }
+  put_cost(op, 2.0 * b * b * nr, 8.0 * b * b + 16.0 * b * nr);
+}
+
 // Out-of-line entries of the leaf solve and the H-matvec update bodies (the
 // wave kernel and the factor executor call these; the solve executor, which
 // runs only these types, takes the bodies inline and so saves no registers
@@ -1651,6 +1790,7 @@ __global__ void k_set_int(int32_t* p, int v) {
 __device__ __noinline__ void d_trsm(const Op& op) { trsm_body(op); }
 __device__ __noinline__ void d_mvt(const Op& op) { mvt_body(op); }
 __device__ __noinline__ void d_mvrow(const Op& op) { mvrow_body(op); }
+__device__ __noinline__ void d_invapply(const Op& op) { invapply_body(op); }
 
 // ---------------------------------------------------------------- launchers
 // One workgroup per descriptor; the descriptors of a launch may mix op
@@ -1670,6 +1810,8 @@ __device__ __forceinline__ void run_op(const Op& op) {
     case OP_ZERO: d_zero(op); break;
     case OP_MVT: d_mvt(op); break;
     case OP_MVROW: d_mvrow(op); break;
+    case OP_TRINV: d_trinv(op); break;
+    case OP_INVAPPLY: d_invapply(op); break;
     default: break;
   }
 }
@@ -1722,9 +1864,8 @@ __global__ void k_df_reset(const DfPart* parts, int np, int* queue, const int* r
 // outside it raises error 3).
 constexpr unsigned DF_FACTOR_TYPES = (1u << OP_GETRF) | (1u << OP_TRSM_L) | (1u << OP_TRSM_UT) |
                                      (1u << OP_TRSM_U) | (1u << OP_PGEMM) | (1u << OP_TRUNC) |
-                                     (1u << OP_ADDD) | (1u << OP_ZERO);
-constexpr unsigned DF_SOLVE_TYPES = (1u << OP_TRSM_L) | (1u << OP_TRSM_UT) | (1u << OP_TRSM_U) |
-                                    (1u << OP_MVT) | (1u << OP_MVROW);
+                                     (1u << OP_ADDD) | (1u << OP_ZERO) | (1u << OP_TRINV);
+constexpr unsigned DF_SOLVE_TYPES = (1u << OP_MVT) | (1u << OP_MVROW) | (1u << OP_INVAPPLY);
 
 template <unsigned MASK>
 __device__ __forceinline__ bool run_op_masked(const Op& op) {
@@ -1756,6 +1897,14 @@ __device__ __forceinline__ bool run_op_masked(const Op& op) {
       if constexpr ((MASK >> OP_MVROW) & 1) {
         if constexpr (kInlineSolveOps) mvrow_body(op);
         else d_mvrow(op);
+        return true;
+      }
+      break;
+    case OP_TRINV: if constexpr ((MASK >> OP_TRINV) & 1) { d_trinv(op); return true; } break;
+    case OP_INVAPPLY:
+      if constexpr ((MASK >> OP_INVAPPLY) & 1) {
+        if constexpr (kInlineSolveOps) invapply_body(op);
+        else d_invapply(op);
         return true;
       }
       break;
@@ -1876,6 +2025,8 @@ static size_t lds_bytes(int type) {
     case OP_ADDD: return LDS_ADDD;
     case OP_MVT: return LDS_MVT;
     case OP_MVROW: return LDS_MVROW;
+    case OP_TRINV: return LDS_TRINV;
+    case OP_INVAPPLY: return LDS_INVAPPLY;
     default: return 0;
   }
 }
@@ -1906,7 +2057,7 @@ extern "C" size_t hlu_lds_bytes(int type) { return hlu::lds_bytes(type); }
 static size_t df_lds(int kind) {
   if (kind == 0) return sizeof(hlu::TruncShared);
   size_t m = 0;
-  for (int t : {hlu::OP_TRSM_L, hlu::OP_MVT, hlu::OP_MVROW}) m = std::max(m, hlu::lds_bytes(t));
+  for (int t : {hlu::OP_INVAPPLY, hlu::OP_MVT, hlu::OP_MVROW}) m = std::max(m, hlu::lds_bytes(t));
   return m;
 }
 static const void* df_kernel(int kind) {

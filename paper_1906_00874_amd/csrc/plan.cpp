@@ -777,6 +777,33 @@ class Builder {
     op.p[1].rankp = P.off_status;
     op.i0 = P.cl[B.t].off;
     emit(op, {whole(B.objF, true)});
+    // the leaf's inverses for the solve (read by no factor op)
+    Op inv = blank(OP_TRINV);
+    inv.p[0] = op.p[0];
+    inv.p[1].ptr = op.p[1].ptr;
+    inv.p[2] = inv_ref(P.off_inv_l, B.t);
+    inv.p[3] = inv_ref(P.off_inv_u, B.t);
+    emit(inv, {whole(B.objF, false)});
+  }
+  PRef inv_ref(uint64_t region, int cl) const {
+    PRef r;
+    std::memset(&r, 0, sizeof(r));
+    const int b = P.cl[cl].size;
+    r.ptr = region + (uint64_t)P.cl[cl].off * 64 * 8;
+    r.ld = b;
+    r.rows = b;
+    r.cols = b;
+    r.dt = DT_F64;
+    r.kind = PK_MAT;
+    return r;
+  }
+  // solve: Y := W Y with the precomputed inverse W of the leaf of nb
+  void inv_apply(uint64_t region, int nb, const PV& Y) {
+    const LBlock& L = P.blk[node(nb).blk];
+    Op op = blank(OP_INVAPPLY);
+    op.p[0] = inv_ref(region, L.t);
+    op.p[1] = ref(Y);
+    emit(op, {acc_of(Y, true), racc(Y)});
   }
   void trsm_leaf(int type, int nb, const PV& Y) {
     const LBlock& L = P.blk[node(nb).blk];
@@ -929,7 +956,11 @@ class Builder {
 
   // Y := L^{-1} P Y over the rows of diagonal node nb
   void fwd(int nb, const PV& Y) {
-    if (node(nb).kind == 'F') { trsm_leaf(OP_TRSM_L, nb, Y); return; }
+    if (node(nb).kind == 'F') {
+      if (solve_mv) inv_apply(P.off_inv_l, nb, Y);
+      else trsm_leaf(OP_TRSM_L, nb, Y);
+      return;
+    }
     const BNode& L = node(nb);
     int t0 = P.cl[L.t].son[0], t1 = P.cl[L.t].son[1];
     PV Y0 = sub(Y, t0), Y1 = sub(Y, t1);
@@ -950,7 +981,11 @@ class Builder {
   }
   // Y := U^{-1} Y
   void bwd(int nb, const PV& Y) {
-    if (node(nb).kind == 'F') { trsm_leaf(OP_TRSM_U, nb, Y); return; }
+    if (node(nb).kind == 'F') {
+      if (solve_mv) inv_apply(P.off_inv_u, nb, Y);
+      else trsm_leaf(OP_TRSM_U, nb, Y);
+      return;
+    }
     const BNode& U = node(nb);
     int t0 = P.cl[U.t].son[0], t1 = P.cl[U.t].son[1];
     PV Y0 = sub(Y, t0), Y1 = sub(Y, t1);
@@ -1288,6 +1323,10 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   cur = align256(cur + w);
   p.off_piv = cur;
   cur = align256(cur + (uint64_t)n * 4);
+  p.off_inv_l = cur;
+  cur = align256(cur + (uint64_t)n * 64 * 8);
+  p.off_inv_u = cur;
+  cur = align256(cur + (uint64_t)n * 64 * 8);
 
   // ---- host assembly
   Entries E{p.xyz.data(), p.area.data(), prm.kernel};

@@ -87,6 +87,10 @@ struct Plan {
   uint64_t off_work = 0, size_work = 0;      // ranks | dense | low-rank
   uint64_t off_pristine = 0;
   uint64_t off_piv = 0;
+  // inverses of the diagonal leaves for the solve: the leaf at rows
+  // [o, o + b) keeps L^{-1} P at off_inv_l + 512 o and U^{-1} at
+  // off_inv_u + 512 o (b x b FP64, leading dimension b)
+  uint64_t off_inv_l = 0, off_inv_u = 0;
   uint64_t off_mv = 0, size_mv = 0;
   uint64_t off_scratch = 0, size_scratch = 0;
   uint64_t off_cost = 0;           // per-op records of the factor schedule

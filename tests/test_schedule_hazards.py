@@ -3,7 +3,8 @@
 Every op of a schedule reads and writes column segments of panels in the
 device buffer (the operand roles of each op type are those of the op table:
 leaf factorisation, leaf solves, panel products, truncations, dense updates,
-zeroing, and the solve's H-matvec updates).  Two ops that touch overlapping
+zeroing, the leaf inverses, and the solve's H-matvec updates and inverse
+applications).  Two ops that touch overlapping
 bytes, one of them writing, must be ordered: for the wave executor they must
 sit in different waves, in the right order; for the dataflow executor a path
 of dependency edges must lead from the earlier to the later one.  The check
@@ -18,7 +19,7 @@ import paper_1906_00874_amd as P
 from hlu_inputs import icosphere
 
 OP_GETRF, OP_TRSM_L, OP_TRSM_UT, OP_TRSM_U, OP_PGEMM, OP_TRUNC, OP_ADDD, OP_ZERO, \
-    OP_MVT, OP_MVROW = range(10)
+    OP_MVT, OP_MVROW, OP_TRINV, OP_INVAPPLY = range(12)
 
 
 def _segs(r, write, out):
@@ -73,6 +74,14 @@ def accesses(o, terms):
         for q in range(int(o["i0"]), int(o["i0"]) + int(o["i1"])):
             _segs(terms[q]["X"], False, a)
             _segs(terms[q]["Y"], False, a)
+    elif t == OP_TRINV:
+        _segs(p[0], False, a)
+        a.append((int(p[1]["ptr"]), int(p[1]["ptr"]) + 4 * int(p[0]["rows"]), False))
+        _segs(p[2], True, a)
+        _segs(p[3], True, a)
+    elif t == OP_INVAPPLY:
+        _segs(p[0], False, a)
+        _segs(p[1], True, a)
     else:
         raise AssertionError(f"unknown op type {t}")
     return a
