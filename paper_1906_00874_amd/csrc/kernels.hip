@@ -20,10 +20,20 @@ namespace hlu {
 // accesses even when a body is compiled out of line.
 extern __shared__ __align__(16) char hlu_lds[];
 
+// Device data reached through descriptor fields (64-bit addresses) is
+// accessed through global-address-space pointers: generic (flat) accesses
+// also count against the LDS wait counter, so every LDS access of an op
+// would wait for the op's outstanding global loads and stores.
+#define HLU_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ HLU_G T* gptr(uint64_t a) {
+  return (HLU_G T*)a;
+}
+
 // live column count: ranks change while a schedule runs, so they are read
 // with a device-scope atomic load (never through a cached scalar load)
 __device__ __forceinline__ int pcols(const PRef& r) {
-  return r.rankp ? __hip_atomic_load(reinterpret_cast<int32_t*>(r.rankp), __ATOMIC_RELAXED,
+  return r.rankp ? __hip_atomic_load(gptr<int32_t>(r.rankp), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT)
                  : r.cols;
 }
@@ -31,14 +41,67 @@ __device__ __forceinline__ int pcols(const PRef& r) {
 __device__ __forceinline__ double pget(const PRef& r, int i, int j) {
   if (r.kind == PK_IDENT) return (j == i + r.ld) ? 1.0 : 0.0;
   size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
-  return r.dt == DT_F64 ? reinterpret_cast<const double*>(r.ptr)[k]
-                        : (double)reinterpret_cast<const float*>(r.ptr)[k];
+  return r.dt == DT_F64 ? gptr<const double>(r.ptr)[k] : (double)gptr<const float>(r.ptr)[k];
 }
 
 __device__ __forceinline__ void pset(const PRef& r, int i, int j, double v) {
   size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
-  if (r.dt == DT_F64) reinterpret_cast<double*>(r.ptr)[k] = v;
-  else reinterpret_cast<float*>(r.ptr)[k] = (float)v;
+  if (r.dt == DT_F64) gptr<double>(r.ptr)[k] = v;
+  else gptr<float>(r.ptr)[k] = (float)v;
+}
+
+// Staging of operand tiles into LDS: every thread issues all its loads
+// before its first store, so one tile costs one memory round trip.
+// dst[i][kk] = get(i, kk) for a 64 x 32 tile (eight values per thread).
+template <class F>
+__device__ __forceinline__ void stage_64x32(double (*dst)[33], F get) {
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = threadIdx.x + NT * u;
+    v[u] = get(e % 64, e / 64);
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = threadIdx.x + NT * u;
+    dst[e % 64][e / 64] = v[u];
+  }
+}
+// dst[kk][j] = get(kk, j) for a 32 x 64 tile
+template <class F>
+__device__ __forceinline__ void stage_32x64(double (*dst)[65], F get) {
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = threadIdx.x + NT * u;
+    v[u] = get(e % 32, e / 32);
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = threadIdx.x + NT * u;
+    dst[e % 32][e / 32] = v[u];
+  }
+}
+// Y[r0 + ti + 16u][c0 + tj + 16v] += s * acc[u][v] within h x w: all loads
+// first, then all stores (a store could alias a later load otherwise, and
+// every element would cost a round trip)
+__device__ __forceinline__ void tile_update(const PRef& Y, int r0, int c0, int h, int w, int ti,
+                                            int tj, double s, const double (&acc)[4][4]) {
+  double old[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + 16 * u, j = tj + 16 * v;
+      old[u][v] = (i < h && j < w) ? pget(Y, r0 + i, c0 + j) : 0.0;
+    }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + 16 * u, j = tj + 16 * v;
+      if (i < h && j < w) pset(Y, r0 + i, c0 + j, old[u][v] + s * acc[u][v]);
+    }
 }
 
 // cross-lane helpers (64-wide wavefronts)
@@ -56,7 +119,7 @@ __device__ __forceinline__ void put_cost(const Op& op, double flops, double byte
                                          double cap_hit = 0.0, double rank = 0.0,
                                          double width = 0.0, double detail = 0.0) {
   if (op.cost && threadIdx.x == 0) {
-    double* c = reinterpret_cast<double*>(op.cost);
+    HLU_G double* c = gptr<double>(op.cost);
     c[0] = flops;
     c[1] = bytes;
     c[2] = cap_hit;
@@ -68,7 +131,7 @@ __device__ __forceinline__ void put_cost(const Op& op, double flops, double byte
 }
 
 __device__ __forceinline__ void start_tick(const Op& op) {
-  if (op.cost && threadIdx.x == 0) reinterpret_cast<double*>(op.cost)[4] = (double)wall_clock64();
+  if (op.cost && threadIdx.x == 0) gptr<double>(op.cost)[4] = (double)wall_clock64();
 }
 
 // ---------------------------------------------------------------- getrf
@@ -86,13 +149,13 @@ __device__ void d_getrf(const Op& op) {
   int& s_piv = reinterpret_cast<int*>(smem + 64 * 65 * 8)[0];
   int& s_info = reinterpret_cast<int*>(smem + 64 * 65 * 8)[1];
   const int tid = threadIdx.x;
-  double* g = reinterpret_cast<double*>(A.ptr);
+  HLU_G double* g = gptr<double>(A.ptr);
   for (int e = tid; e < b * b; e += NT) {
     int i = e % b, j = e / b;
     a[i][j] = g[i + (size_t)j * A.ld];
   }
   if (tid == 0) s_info = 0;
-  int32_t* piv = reinterpret_cast<int32_t*>(op.p[1].ptr);
+  HLU_G int32_t* piv = gptr<int32_t>(op.p[1].ptr);
   __syncthreads();
   for (int k = 0; k < b; ++k) {
     if (tid < 64) {
@@ -207,7 +270,7 @@ __device__ __forceinline__ void trsm_body(const Op& op) {
   int* pm = reinterpret_cast<int*>(smem + 64 * 65 * 8 + 64 * 8);
   const int tid = threadIdx.x;
   {
-    const double* g = reinterpret_cast<const double*>(L.ptr);
+    const HLU_G double* g = gptr<const double>(L.ptr);
     double v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -224,7 +287,7 @@ __device__ __forceinline__ void trsm_body(const Op& op) {
     if (type == OP_TRSM_L) {
       // row permutation of the interchanges applied in order: lane i holds
       // the source row of position i
-      const int32_t* piv = reinterpret_cast<const int32_t*>(op.p[2].ptr);
+      const HLU_G int32_t* piv = gptr<const int32_t>(op.p[2].ptr);
       const int pk = tid < b ? piv[tid] : tid;
       int pr = tid;
       for (int k = 0; k < b; ++k) {
@@ -296,16 +359,13 @@ __device__ void d_pgemm(const Op& op) {
           for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
         for (int k0 = 0; k0 < r; k0 += 32) {
           const int d = min(32, r - k0);
-          for (int e = tid; e < 64 * 32; e += NT) {
-            int i = e % 64, kk = e / 64;
-            double v = 0.0;
-            if (i < h && kk < d) v = tr ? pget(M, k0 + kk, r0 + i) : pget(M, r0 + i, k0 + kk);
-            sa[i][kk] = v;
-          }
-          for (int e = tid; e < 32 * 64; e += NT) {
-            int kk = e % 32, j = e / 32;
-            sb[kk][j] = (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
-          }
+          stage_64x32(sa, [&](int i, int kk) {
+            if (i >= h || kk >= d) return 0.0;
+            return tr ? pget(M, k0 + kk, r0 + i) : pget(M, r0 + i, k0 + kk);
+          });
+          stage_32x64(sb, [&](int kk, int j) {
+            return (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
+          });
           __syncthreads();
           for (int kk = 0; kk < d; ++kk) {
             double av[4], bv[4];
@@ -320,13 +380,7 @@ __device__ void d_pgemm(const Op& op) {
           }
           __syncthreads();
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            int i = ti + 16 * u, j = tj + 16 * v;
-            if (i < h && j < w) pset(Y, r0 + i, c0 + j, pget(Y, r0 + i, c0 + j) + sg * acc[u][v]);
-          }
+        tile_update(Y, r0, c0, h, w, ti, tj, sg, acc);
       }
     }
     put_cost(op, 2.0 * m * r * c, 8.0 * m * r + esx * r * c + 2.0 * esy * m * c);
@@ -350,14 +404,13 @@ __device__ void d_pgemm(const Op& op) {
       for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     for (int k0 = 0; k0 < r; k0 += 32) {
       const int d = min(32, r - k0);
-      for (int e = tid; e < 64 * 32; e += NT) {
-        int i = e % 64, kk = e / 64;   // i: rank index, kk: row of B
-        sa[i][kk] = (i < k && kk < d) ? pget(B, k0 + kk, i) : 0.0;
-      }
-      for (int e = tid; e < 32 * 64; e += NT) {
-        int kk = e % 32, j = e / 32;
-        sb[kk][j] = (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
-      }
+      // i: rank index, kk: row of B
+      stage_64x32(sa, [&](int i, int kk) {
+        return (i < k && kk < d) ? pget(B, k0 + kk, i) : 0.0;
+      });
+      stage_32x64(sb, [&](int kk, int j) {
+        return (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
+      });
       __syncthreads();
       for (int kk = 0; kk < d; ++kk) {
         double av[4], bv[4];
@@ -380,10 +433,9 @@ __device__ void d_pgemm(const Op& op) {
     // Y += sg * A T
     for (int r0 = 0; r0 < m; r0 += 64) {
       const int h = min(64, m - r0);
-      for (int e = tid; e < 64 * 32; e += NT) {
-        int i = e % 64, kk = e / 64;
-        sa[i][kk] = (i < h && kk < k && kk < 32) ? pget(A, r0 + i, kk) : 0.0;
-      }
+      stage_64x32(sa, [&](int i, int kk) {
+        return (i < h && kk < k && kk < 32) ? pget(A, r0 + i, kk) : 0.0;
+      });
       __syncthreads();
       double o[4][4];
 #pragma unroll
@@ -402,10 +454,9 @@ __device__ void d_pgemm(const Op& op) {
       }
       __syncthreads();
       if (k > 32) {
-        for (int e = tid; e < 64 * 32; e += NT) {
-          int i = e % 64, kk = e / 64;
-          sa[i][kk] = (i < h && 32 + kk < k) ? pget(A, r0 + i, 32 + kk) : 0.0;
-        }
+        stage_64x32(sa, [&](int i, int kk) {
+          return (i < h && 32 + kk < k) ? pget(A, r0 + i, 32 + kk) : 0.0;
+        });
         __syncthreads();
         for (int kk = 0; kk < k - 32; ++kk) {
           double av[4];
@@ -418,13 +469,7 @@ __device__ void d_pgemm(const Op& op) {
         }
         __syncthreads();
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int i = ti + 16 * u, j = tj + 16 * v;
-          if (i < h && j < w) pset(Y, r0 + i, c0 + j, pget(Y, r0 + i, c0 + j) + sg * o[u][v]);
-        }
+      tile_update(Y, r0, c0, h, w, ti, tj, sg, o);
     }
     __syncthreads();
   }
@@ -444,7 +489,6 @@ __device__ void d_addd(const Op& op) {
   double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8);
   const int tid = threadIdx.x;
   const int ti = tid % 16, tj = tid / 16;
-  double* g = reinterpret_cast<double*>(C.ptr);
   for (int c0 = 0; c0 < n; c0 += 64) {
     const int w = min(64, n - c0);
     for (int r0 = 0; r0 < m; r0 += 64) {
@@ -456,14 +500,12 @@ __device__ void d_addd(const Op& op) {
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
       for (int k0 = 0; k0 < k; k0 += 32) {
         const int d = min(32, k - k0);
-        for (int e = tid; e < 64 * 32; e += NT) {
-          int i = e % 64, kk = e / 64;
-          sa[i][kk] = (i < h && kk < d) ? pget(X, r0 + i, k0 + kk) : 0.0;
-        }
-        for (int e = tid; e < 32 * 64; e += NT) {
-          int kk = e % 32, j = e / 32;
-          sb[kk][j] = (kk < d && j < w) ? pget(Y, c0 + j, k0 + kk) : 0.0;
-        }
+        stage_64x32(sa, [&](int i, int kk) {
+          return (i < h && kk < d) ? pget(X, r0 + i, k0 + kk) : 0.0;
+        });
+        stage_32x64(sb, [&](int kk, int j) {
+          return (kk < d && j < w) ? pget(Y, c0 + j, k0 + kk) : 0.0;
+        });
         __syncthreads();
         for (int kk = 0; kk < d; ++kk) {
           double av[4], bv[4];
@@ -478,13 +520,7 @@ __device__ void d_addd(const Op& op) {
         }
         __syncthreads();
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int i = ti + 16 * u, j = tj + 16 * v;
-          if (i < h && j < w) g[(r0 + i) + (size_t)(c0 + j) * C.ld] -= acc[u][v];
-        }
+      tile_update(C, r0, c0, h, w, ti, tj, -1.0, acc);
     }
   }
   const double es = X.dt == DT_F64 ? 8.0 : 4.0;
@@ -683,8 +719,8 @@ __device__ __forceinline__ double cd_get(const ColDesc& d, int i) {
   if (ii < 0 || ii >= d.rows) return 0.0;
   double v;
   if (d.ident) v = ii == d.irow ? 1.0 : 0.0;
-  else if (d.dt == DT_F64) v = reinterpret_cast<const double*>(d.base)[(int64_t)ii * d.stride];
-  else v = (double)reinterpret_cast<const float*>(d.base)[(int64_t)ii * d.stride];
+  else if (d.dt == DT_F64) v = gptr<const double>(d.base)[(int64_t)ii * d.stride];
+  else v = (double)gptr<const float>(d.base)[(int64_t)ii * d.stride];
   return d.sign < 0 ? -v : v;
 }
 
@@ -1305,7 +1341,7 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
     __syncthreads();
     // 7. new factors, streamed in place; then the new rank
     trunc_apply2(sh, U, V, m, n, K, k);
-    if (tid == 0) *reinterpret_cast<int32_t*>(U.rankp) = k;
+    if (tid == 0) *gptr<int32_t>(U.rankp) = k;
     __threadfence_block();
     __syncthreads();
     flops += 2.0 * (m + n) * K * K - 4.0 * K * K * K / 3.0 + 2.0 * K * K * K +
@@ -1368,7 +1404,7 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
     }
     __syncthreads();
   }
-  double* t = reinterpret_cast<double*>(T.ptr);
+  HLU_G double* t = gptr<double>(T.ptr);
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -1389,19 +1425,29 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
 // its partial in registers.  The four partials are summed once at the end.
 #define MVR_TMAX 256
 #define MVR_STAGE (4 * (64 * 17 + 16 * 65) * 8)
-#define LDS_MVROW (MVR_STAGE + 2 * MVR_TMAX * 4)
+#define LDS_MVROW (MVR_STAGE + 2 * MVR_TMAX * 4 + MVR_TMAX * 80)
+static_assert(sizeof(Term) == 80, "term records are staged as ten 8-byte words");
 __device__ __forceinline__ void mvrow_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef Y = op.p[3];
-  const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
   const int nt = min(op.i1, MVR_TMAX), rows = Y.rows, nr = pcols(Y);
+  const double d0 = op.d0;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   double (*sa)[17] = reinterpret_cast<double (*)[17]>(smem + w * (64 * 17 + 16 * 65) * 8);
   double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + w * (64 * 17 + 16 * 65) * 8 +
                                                       64 * 17 * 8);
   int* kk = reinterpret_cast<int*>(smem + MVR_STAGE);
   int* first = kk + MVR_TMAX;   // first work item of each term
-  for (int t = tid; t < nt; t += NT) kk[t] = pcols(terms[t].X);
+  // the term records, staged once (every work item reads its term's
+  // pointers and strides from here instead of global memory)
+  Term* st = reinterpret_cast<Term*>(smem + MVR_STAGE + 2 * MVR_TMAX * 4);
+  {
+    const HLU_G uint64_t* src = gptr<const uint64_t>(op.p[2].ptr) + (size_t)op.i0 * 10;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(st);
+    for (int e = tid; e < nt * 10; e += NT) dst[e] = src[e];
+  }
+  __syncthreads();
+  for (int t = tid; t < nt; t += NT) kk[t] = pcols(st[t].X);
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
@@ -1420,39 +1466,47 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   };
   double (*pb2)[33] = reinterpret_cast<double (*)[33]>(smem);   // 2 x 64 rows x 32
   // right-hand sides in groups of 32 (one group when nrhs <= 32)
+  // chunk `item` (16 columns of one term) of the A panel (lane = row) and of
+  // the B panel (lane = right-hand side h0 + lane) into registers
+  auto fetch = [&](int item, int h0, int nh, double (&ra)[16], double (&rb)[16], int& kc) {
+    int t, c0;
+    locate(item, t, c0);
+    const Term& tp = st[t];
+    kc = min(16, kk[t] - c0);
+    const int lda = tp.X.ld, ldb = tp.Y.ld;
+    if (tp.X.dt == DT_F64) {
+      const HLU_G double* pa = gptr<const double>(tp.X.ptr) + lane + (size_t)c0 * lda;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) ra[u] = (lane < rows && u < kc) ? pa[(size_t)u * lda] : 0.0;
+    } else {
+      const HLU_G float* pa = gptr<const float>(tp.X.ptr) + lane + (size_t)c0 * lda;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        ra[u] = (lane < rows && u < kc) ? (double)pa[(size_t)u * lda] : 0.0;
+    }
+    const HLU_G double* pb = gptr<const double>(tp.Y.ptr) + c0 + (size_t)(h0 + lane) * ldb;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) rb[u] = (lane < nh && u < kc) ? pb[u] : 0.0;
+  };
   for (int h0 = 0; h0 < nr; h0 += 32) {
     const int nh = min(32, nr - h0);
     double o[32];
 #pragma unroll
     for (int v = 0; v < 32; ++v) o[v] = 0.0;
+    double ra[16], rb[16];
+    int kc = 0;
+    if (w < nitems) fetch(w, h0, nh, ra, rb, kc);
     for (int item = w; item < nitems; item += 4) {
-      int t, c0;
-      locate(item, t, c0);
-      const Term* tp = terms + t;
-      const int kc = min(16, kk[t] - c0);
-      const int lda = tp->X.ld, ldb = tp->Y.ld;
-      double ra[16], rb[16];
-      // A chunk: lane = row, 16 columns; B chunk: lane = right-hand side (< nh), 16 rows
-      if (tp->X.dt == DT_F64) {
-        const double* pa = reinterpret_cast<const double*>(tp->X.ptr) + lane + (size_t)c0 * lda;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) ra[u] = (lane < rows && u < kc) ? pa[(size_t)u * lda] : 0.0;
-      } else {
-        const float* pa = reinterpret_cast<const float*>(tp->X.ptr) + lane + (size_t)c0 * lda;
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-          ra[u] = (lane < rows && u < kc) ? (double)pa[(size_t)u * lda] : 0.0;
-      }
-      const double* pb = reinterpret_cast<const double*>(tp->Y.ptr) + c0 + (size_t)(h0 + lane) * ldb;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) rb[u] = (lane < nh && u < kc) ? pb[u] : 0.0;
       // the slices were last read by this wavefront's previous chunk (program order)
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         sa[lane][u] = ra[u];
         sb[u][lane] = rb[u];
       }
-      for (int c = 0; c < kc; ++c) {
+      const int kcur = kc;
+      // the next chunk's loads are in flight while this one is multiplied
+      if (item + 4 < nitems) fetch(item + 4, h0, nh, ra, rb, kc);
+      for (int c = 0; c < kcur; ++c) {
         const double a = sa[lane][c];
 #pragma unroll
         for (int v = 0; v < 32; ++v) o[v] += a * sb[c][v];
@@ -1477,17 +1531,20 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     }
     __syncthreads();
     if (w == 0 && lane < rows) {
-      double* y = reinterpret_cast<double*>(Y.ptr) + lane + (size_t)h0 * Y.ld;
+      HLU_G double* y = gptr<double>(Y.ptr) + lane + (size_t)h0 * Y.ld;
+      double yv[32];
+#pragma unroll
+      for (int v = 0; v < 32; ++v) yv[v] = v < nh ? y[(size_t)v * Y.ld] : 0.0;
 #pragma unroll
       for (int v = 0; v < 32; ++v)
-        if (v < nh) y[(size_t)v * Y.ld] += op.d0 * (o[v] + pb2[lane][v]);
+        if (v < nh) y[(size_t)v * Y.ld] = yv[v] + d0 * (o[v] + pb2[lane][v]);
     }
     __syncthreads();
   }
   if (tid == 0 && op.cost) {
     double fl = 0.0, by = 16.0 * rows * nr;
     for (int t = 0; t < nt; ++t) {
-      const PRef A = terms[t].X;
+      const PRef A = st[t].X;
       fl += 2.0 * rows * kk[t] * nr;
       by += (A.dt == DT_F64 ? 8.0 : 4.0) * rows * kk[t] + 8.0 * kk[t] * nr;
     }
@@ -1501,8 +1558,8 @@ __global__ void __launch_bounds__(NT) k_mv_t(const MvLR* __restrict__ lr, const 
                                              int ldx, int nrhs) {
   const MvLR e = lr[blockIdx.x];
   if (e.k == 0) return;
-  const double* V = reinterpret_cast<const double*>(e.V);
-  double* T = reinterpret_cast<double*>(e.T);
+  const HLU_G double* V = gptr<const double>(e.V);
+  HLU_G double* T = gptr<double>(e.T);
   __shared__ double sv[32][65];
   __shared__ double sx[32][65];
   const int tid = threadIdx.x;
@@ -1564,13 +1621,13 @@ __global__ void __launch_bounds__(NT) k_mv_rows(const MvRow* __restrict__ rows,
     const bool act = i < r.rows && j < nrhs;
     for (int q = 0; q < r.nt; ++q) {
       const MvTerm t = terms[r.t0 + q];
-      const double* A = reinterpret_cast<const double*>(t.A);
+      const HLU_G double* A = gptr<const double>(t.A);
       if (!act) continue;
       if (t.T == 0) {
         const double* x = X + (size_t)j * ldx + t.c0;
         for (int c = 0; c < t.ncol; ++c) acc += A[(t.roff + i) + (size_t)c * t.lda] * x[c];
       } else {
-        const double* T = reinterpret_cast<const double*>(t.T) + (size_t)j * t.c0;
+        const HLU_G double* T = gptr<const double>(t.T) + (size_t)j * t.c0;
         for (int c = 0; c < t.ncol; ++c) acc += A[(t.roff + i) + (size_t)c * t.lda] * T[c];
       }
     }
@@ -1663,7 +1720,7 @@ __device__ void d_trinv(const Op& op) {
   int* pm = reinterpret_cast<int*>(smem + 3 * 64 * 65 * 8);
   const int tid = threadIdx.x;
   {
-    const double* g = reinterpret_cast<const double*>(A.ptr);
+    const HLU_G double* g = gptr<const double>(A.ptr);
     double v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -1679,7 +1736,7 @@ __device__ void d_trinv(const Op& op) {
   if (tid < 64) {
     // row permutation of the interchanges applied in order: lane i holds
     // the source row of position i
-    const int32_t* piv = reinterpret_cast<const int32_t*>(op.p[1].ptr);
+    const HLU_G int32_t* piv = gptr<const int32_t>(op.p[1].ptr);
     const int pk = tid < b ? piv[tid] : tid;
     int pr = tid;
     for (int k = 0; k < b; ++k) {
@@ -1718,8 +1775,8 @@ __device__ void d_trinv(const Op& op) {
     }
   }
   __syncthreads();
-  double* w = reinterpret_cast<double*>(W.ptr);
-  double* u = reinterpret_cast<double*>(Ui.ptr);
+  HLU_G double* w = gptr<double>(W.ptr);
+  HLU_G double* u = gptr<double>(Ui.ptr);
   for (int e = tid; e < b * b; e += NT) {
     const int i = e % b, k = e / b;
     w[i + (size_t)pm[k] * b] = x[i][k];
@@ -1738,8 +1795,8 @@ __device__ __forceinline__ void invapply_body(const Op& op) {
   double (*w)[65] = reinterpret_cast<double (*)[65]>(smem);
   double (*y)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
   const int tid = threadIdx.x;
-  const double* gw = reinterpret_cast<const double*>(Wr.ptr);
-  double* gy = reinterpret_cast<double*>(Y.ptr);
+  const HLU_G double* gw = gptr<const double>(Wr.ptr);
+  HLU_G double* gy = gptr<double>(Y.ptr);
   {
     double v[16], q[16];
 #pragma unroll
@@ -1963,9 +2020,9 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     {
-      const int* succ_off = reinterpret_cast<const int*>(pt.succ_off);
-      const int* succ = reinterpret_cast<const int*>(pt.succ);
-      int* indeg = reinterpret_cast<int*>(pt.indeg);
+      const HLU_G int* succ_off = gptr<const int>(pt.succ_off);
+      const HLU_G int* succ = gptr<const int>(pt.succ);
+      HLU_G int* indeg = gptr<int>(pt.indeg);
       const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
       const int lane = tid & 63;
       for (int eb = e0; eb < e1; eb += NT) {
