@@ -976,9 +976,13 @@ __device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, con
 #pragma unroll
       for (int v = 0; v < 16; ++v) o[v] = 0.0;
       for (int c2 = 0; c2 < K; ++c2) {
+        // the row of T first (the reads overlap), then the updates
         const double a = C[i][c2];
+        double tv[16];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) o[v] += a * T[c2][c0 + v];
+        for (int v = 0; v < 16; ++v) tv[v] = T[c2][c0 + v];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) o[v] += a * tv[v];
       }
       if (side) {   // wave-uniform branch
 #pragma unroll
@@ -1493,23 +1497,24 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     double o[32];
 #pragma unroll
     for (int v = 0; v < 32; ++v) o[v] = 0.0;
-    double ra[16], rb[16];
-    int kc = 0;
-    if (w < nitems) fetch(w, h0, nh, ra, rb, kc);
     for (int item = w; item < nitems; item += 4) {
+      double ra[16], rb[16];
+      int kc;
+      fetch(item, h0, nh, ra, rb, kc);
       // the slices were last read by this wavefront's previous chunk (program order)
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         sa[lane][u] = ra[u];
         sb[u][lane] = rb[u];
       }
-      const int kcur = kc;
-      // the next chunk's loads are in flight while this one is multiplied
-      if (item + 4 < nitems) fetch(item + 4, h0, nh, ra, rb, kc);
-      for (int c = 0; c < kcur; ++c) {
+      for (int c = 0; c < kc; ++c) {
+        // the whole row of B first (the reads overlap), then the updates
         const double a = sa[lane][c];
+        double bv[32];
 #pragma unroll
-        for (int v = 0; v < 32; ++v) o[v] += a * sb[c][v];
+        for (int v = 0; v < 32; ++v) bv[v] = sb[c][v];
+#pragma unroll
+        for (int v = 0; v < 32; ++v) o[v] += a * bv[v];
       }
     }
     // sum the four partials pairwise through the (now free) staging area:
