@@ -889,15 +889,17 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
     if (lane == 0) piv[s] = p;
     if (lane == p) alive = false;
     // rank-one update of the trailing columns (same wavefront: the loads
-    // below see the stores above)
+    // below see the stores above).  Straight-line over all 64 entries: lanes
+    // at or beyond K hold l = 0, so their entries stay zero, and without a
+    // branch per entry the reads are issued together.
     const double2* l2 = reinterpret_cast<const double2*>(lv);
+    double2 lr[KM / 2];
+#pragma unroll
+    for (int i = 0; i < KM; i += 2) lr[i >> 1] = l2[i >> 1];
 #pragma unroll
     for (int i = 0; i < KM; i += 2) {
-      if (i < K) {
-        const double2 li = l2[i >> 1];
-        g[i] -= li.x * l;
-        g[i + 1] -= li.y * l;
-      }
+      g[i] -= lr[i >> 1].x * l;
+      g[i + 1] -= lr[i >> 1].y * l;
     }
     d -= l * l;
     ++r;
