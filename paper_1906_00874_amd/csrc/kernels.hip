@@ -714,38 +714,47 @@ __device__ __forceinline__ void trunc_coldesc(TruncShared& sh, const PRef& U, co
   }
 }
 
-__device__ __forceinline__ double cd_get(const ColDesc& d, int i) {
-  const int ii = i - d.r0;
-  if (ii < 0 || ii >= d.rows) return 0.0;
-  double v;
-  if (d.ident) v = ii == d.irow ? 1.0 : 0.0;
-  else if (d.dt == DT_F64) v = gptr<const double>(d.base)[(int64_t)ii * d.stride];
-  else v = (double)gptr<const float>(d.base)[(int64_t)ii * d.stride];
-  return d.sign < 0 ? -v : v;
-}
+// Word that column reads of absent and identity entries load instead of
+// panel memory (so every load of a chunk is issued unconditionally).
+__device__ __align__(16) uint32_t hlu_zero_words[4];
 
 // rows [r0, r0 + 64) of both stacked panels into d0 (X side, m rows) and d1
-// (Y side, n rows); every thread issues all its loads before its stores
+// (Y side, n rows).  Per side every thread resolves its 16 elements
+// (address, dtype, identity hit, sign) from the column descriptors first,
+// then issues all 32 word loads, then converts and stores: one memory round
+// trip per side and chunk.
 __device__ __forceinline__ void trunc_load2(TruncShared& sh, double (*d0)[KM + 1],
                                             double (*d1)[KM + 1], int r0, int m, int n, int K) {
   const int tid = threadIdx.x;
+  const uint64_t zero = (uint64_t)hlu_zero_words;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const int rows = side ? n : m;
     double (*d)[KM + 1] = side ? d1 : d0;
+    uint32_t lo[16], hi[16];
+    int flag[16];   // bit 0: FP64, bit 1: identity one, bit 2: negate
 #pragma unroll
-    for (int u0 = 0; u0 < 16; u0 += 8) {
-      double v[8];
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;   // j is wave-uniform
+      const ColDesc c = sh.cd[side][j < K ? j : 0];
+      const int ii = r0 + i - c.r0;
+      const bool in = j < K && r0 + i < rows && ii >= 0 && ii < c.rows;
+      const bool f64 = c.dt == DT_F64;
+      const bool mem = in && !c.ident;
+      const uint64_t addr =
+          mem ? c.base + (uint64_t)((int64_t)ii * c.stride * (f64 ? 8 : 4)) : zero;
+      lo[u] = *gptr<const uint32_t>(addr);
+      hi[u] = *gptr<const uint32_t>(mem && f64 ? addr + 4 : zero);
+      flag[u] = (f64 ? 1 : 0) | ((in && c.ident && ii == c.irow) ? 2 : 0) | (c.sign < 0 ? 4 : 0);
+    }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = tid + NT * (u0 + u), i = e & 63, j = e >> 6;   // j is wave-uniform
-        v[u] = (j < K && r0 + i < rows) ? cd_get(sh.cd[side][j], r0 + i) : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = tid + NT * (u0 + u), i = e & 63, j = e >> 6;
-        if (j < K) d[i][j] = v[u];
-      }
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      double v = (flag[u] & 1) ? __hiloint2double((int)hi[u], (int)lo[u])
+                               : (double)__int_as_float((int)lo[u]);
+      if (flag[u] & 2) v = 1.0;
+      if (flag[u] & 4) v = -v;
+      if (j < K) d[i][j] = v;
     }
   }
 }
@@ -786,7 +795,40 @@ __device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K
     __syncthreads();
     const int h = min(64, rows_side - r0);
     if (blk0 >= 0) {
-      for (int i = grp; i < h; i += NG) {
+      int i0 = grp;
+      // four rows per step: their LDS reads are issued together
+      for (; i0 + 3 * NG < h; i0 += 4 * NG) {
+        double av[4][4], bv[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            av[r][u] = a0 + u < K ? C[i0 + r * NG][a0 + u] : 0.0;
+            bv[r][u] = b0 + u < K ? C[i0 + r * NG][b0 + u] : 0.0;
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc0[u][v] += av[r][u] * bv[r][v];
+        if (blk1 >= 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              av[r][u] = a1 + u < K ? C[i0 + r * NG][a1 + u] : 0.0;
+              bv[r][u] = b1 + u < K ? C[i0 + r * NG][b1 + u] : 0.0;
+            }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc1[u][v] += av[r][u] * bv[r][v];
+        }
+      }
+      for (int i = i0; i < h; i += NG) {
         double av[4], bv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
