@@ -218,6 +218,13 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
           if (tm.Y.dt != hlu::DT_F64 || tm.Y.trans || tm.Y.rows < tm.X.cols || tm.Y.cols < Y.cols)
             return bad("row term operand");
         }
+        if (o.i2 != 0 && o.i2 != 1) return bad("row update flag");
+        if (o.i2 == 1) {   // fused leaf inverse in p0
+          const hlu::PRef& W = o.p[0];
+          if (!panel_ok(W, T, why)) return bad(why.c_str());
+          if (W.rows != Y.rows || W.cols != Y.rows || W.dt != hlu::DT_F64 || W.trans || W.rankp)
+            return bad("fused leaf inverse");
+        }
         break;
       }
       default:

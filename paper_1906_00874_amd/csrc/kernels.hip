@@ -1473,7 +1473,10 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
 // its partial in registers.  The four partials are summed once at the end.
 #define MVR_TMAX 256
 #define MVR_STAGE (4 * (64 * 17 + 16 * 65) * 8)
-#define LDS_MVROW (MVR_STAGE + 2 * MVR_TMAX * 4 + MVR_TMAX * 80)
+#define MVR_W (MVR_STAGE + 2 * MVR_TMAX * 4 + MVR_TMAX * 80)   // fused leaf inverse
+#define MVR_Y (MVR_W + 64 * 65 * 8)                             // its updated rows
+#define LDS_MVROW (MVR_Y + 64 * 65 * 8)
+static_assert(LDS_MVROW <= 160 * 1024, "row update LDS");
 static_assert(sizeof(Term) == 80, "term records are staged as ten 8-byte words");
 __device__ __forceinline__ void mvrow_body(const Op& op) {
   char* const smem = hlu_lds;
@@ -1489,6 +1492,27 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   // the term records, staged once (every work item reads its term's
   // pointers and strides from here instead of global memory)
   Term* st = reinterpret_cast<Term*>(smem + MVR_STAGE + 2 * MVR_TMAX * 4);
+  // fused leaf inverse (i2 = 1): W staged beside the tables, the updated
+  // rows of every right-hand-side group collected in a region of their own
+  // (the staging area is reused by the next group), then p3 := W p3
+  const bool fused = op.i2 == 1;
+  double (*sw)[65] = reinterpret_cast<double (*)[65]>(smem + MVR_W);
+  double (*sy)[65] = reinterpret_cast<double (*)[65]>(smem + MVR_Y);
+  if (fused) {
+    const PRef W = op.p[0];
+    const HLU_G double* gw = gptr<const double>(W.ptr);
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      v[u] = (i < rows && j < rows) ? gw[i + (size_t)j * W.ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + NT * u, i = e & 63, j = e >> 6;
+      sw[i][j] = v[u];
+    }
+  }
   {
     const HLU_G uint64_t* src = gptr<const uint64_t>(op.p[2].ptr) + (size_t)op.i0 * 10;
     uint64_t* dst = reinterpret_cast<uint64_t*>(st);
@@ -1584,14 +1608,49 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
       double yv[32];
 #pragma unroll
       for (int v = 0; v < 32; ++v) yv[v] = v < nh ? y[(size_t)v * Y.ld] : 0.0;
+      if (fused) {
 #pragma unroll
-      for (int v = 0; v < 32; ++v)
-        if (v < nh) y[(size_t)v * Y.ld] = yv[v] + d0 * (o[v] + pb2[lane][v]);
+        for (int v = 0; v < 32; ++v)
+          if (v < nh) sy[lane][h0 + v] = yv[v] + d0 * (o[v] + pb2[lane][v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 32; ++v)
+          if (v < nh) y[(size_t)v * Y.ld] = yv[v] + d0 * (o[v] + pb2[lane][v]);
+      }
     }
     __syncthreads();
   }
+  if (fused) {
+    // p3 := W (updated rows), 16 x 16 threads with 4 x 4 outputs each
+    const int ti = tid % 16, tj = tid / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int k = 0; k < rows; ++k) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = sw[ti + 16 * u][k];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = sy[k][tj + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    }
+    HLU_G double* gy = gptr<double>(Y.ptr);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ti + 16 * u, j = tj + 16 * v;
+        if (i < rows && j < nr) gy[i + (size_t)j * Y.ld] = acc[u][v];
+      }
+  }
   if (tid == 0 && op.cost) {
-    double fl = 0.0, by = 16.0 * rows * nr;
+    double fl = fused ? 2.0 * rows * rows * nr : 0.0;
+    double by = 16.0 * rows * nr + (fused ? 8.0 * rows * rows : 0.0);
     for (int t = 0; t < nt; ++t) {
       const PRef A = st[t].X;
       fl += 2.0 * rows * kk[t] * nr;
@@ -2137,12 +2196,20 @@ static size_t lds_bytes(int type) {
   }
 }
 
+// the largest dynamic LDS footprint of any op type (the wave kernel's limit)
+static size_t max_lds_bytes() {
+  size_t mx = 0;
+  for (int t = 0; t < OP_NTYPES; ++t) mx = std::max(mx, lds_bytes(t));
+  return mx;
+}
+
 static hipError_t launch_wave(const Op* ops, int count, size_t lds, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  // set once per process (thread-safe initialisation of a local static)
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_wave),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)LDS_TRUNC);
+  // set once per process (thread-safe initialisation of a local static) to
+  // the largest footprint of any op type
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_wave), hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)max_lds_bytes());
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(k_wave, dim3(count), dim3(NT), lds, s, ops);
   return hipGetLastError();
@@ -2261,7 +2328,7 @@ extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* star
   *out = nullptr;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hlu::k_wave),
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sizeof(hlu::TruncShared));
+                                     (int)hlu::max_lds_bytes());
   if (e != hipSuccess) return e;
   hipGraph_t g;
   e = hipGraphCreate(&g, 0);

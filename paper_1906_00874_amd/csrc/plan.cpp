@@ -797,9 +797,23 @@ class Builder {
     r.kind = PK_MAT;
     return r;
   }
-  // solve: Y := W Y with the precomputed inverse W of the leaf of nb
+  // solve: Y := W Y with the precomputed inverse W of the leaf of nb.  When
+  // a row update on exactly these rows was the last op to write them (no op
+  // reads them before the leaf is solved), the product is fused into that
+  // op (i2 = 1, W in p0), one op and one hand-off less on the sweep's chain.
   void inv_apply(uint64_t region, int nb, const PV& Y) {
     const LBlock& L = P.blk[node(nb).blk];
+    if ((int)last_row_op.size() > L.t && last_row_op[L.t] >= 0) {
+      Op& u = ops[last_row_op[L.t]];
+      last_row_op[L.t] = -1;
+      const PRef yr = ref(Y);
+      if (u.type == OP_MVROW && u.p[3].ptr == yr.ptr && u.p[3].rows == yr.rows &&
+          u.p[3].ld == yr.ld) {
+        u.p[0] = inv_ref(region, L.t);
+        u.i2 = 1;
+        return;
+      }
+    }
     Op op = blank(OP_INVAPPLY);
     op.p[0] = inv_ref(region, L.t);
     op.p[1] = ref(Y);
@@ -856,6 +870,9 @@ class Builder {
   // are summed inside one op instead of being chained op after op.
   bool solve_mv = false;
   std::vector<int> Tobj;     // per block: object of its V^T X slot
+  // solve: per leaf cluster, the last emitted row-update op on its rows
+  // (-1: none since the leaf's last inverse application)
+  std::vector<int> last_row_op;
   void block_leaves(int nb, std::vector<int>& out) {
     if (node(nb).kind == 'H') {
       for (int i = 0; i < 4; ++i) block_leaves(P.bn[nb].son[i], out);
@@ -951,6 +968,10 @@ class Builder {
         o2.i1 = std::min(256, tend - t0);
         emit(o2, acc);
       }
+      // the last op writing this leaf row (the leaf's inverse may be fused
+      // into it)
+      if ((int)last_row_op.size() < (int)P.cl.size()) last_row_op.assign(P.cl.size(), -1);
+      last_row_op[r] = (int)ops.size() - 1;
     }
   }
 

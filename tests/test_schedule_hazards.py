@@ -71,6 +71,8 @@ def accesses(o, terms):
         _segs(p[3], True, a)
     elif t == OP_MVROW:
         _segs(p[3], True, a)
+        if o["i2"] == 1:
+            _segs(p[0], False, a)
         for q in range(int(o["i0"]), int(o["i0"]) + int(o["i1"])):
             _segs(terms[q]["X"], False, a)
             _segs(terms[q]["Y"], False, a)
