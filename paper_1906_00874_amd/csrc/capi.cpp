@@ -78,8 +78,15 @@ void relocate(hlu::Op& op, uint64_t base) {
 // kernel may touch (at full capacity) lies inside the buffer, dynamic column
 // counts point at an int inside the buffer, and operand shapes agree with
 // what each kernel assumes.  Offsets are relative to the buffer start.
-bool panel_ok(const hlu::PRef& r, uint64_t total, std::string& why) {
-  if (r.kind == hlu::PK_IDENT) return r.rows >= 0 && r.cols >= 0;
+bool panel_ok(const hlu::PRef& r, uint64_t total, std::string& why, bool allow_ident = false) {
+  if (r.kind == hlu::PK_IDENT) {
+    // identity panels are implicit; only the dense update's operands and the
+    // truncation's stacked terms evaluate them, every other body reads
+    // stored panels only
+    if (!allow_ident) { why = "identity panel outside a truncation term"; return false; }
+    return r.rows >= 0 && r.cols >= 0;
+  }
+  if (r.kind != hlu::PK_MAT) { why = "unknown panel kind"; return false; }
   if (r.rows < 0 || r.cols < 0 || r.ld < 1) { why = "bad panel dims"; return false; }
   if (r.rows == 0 || r.cols == 0) return true;
   uint64_t es = r.dt == hlu::DT_F64 ? 8 : 4;
@@ -151,7 +158,8 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
         if (o.p[2].ptr != p.off_terms_f) return bad("truncation term table");
         for (int t = o.i0; t < o.i0 + o.i1; ++t) {
           const hlu::Term& tm = sc.terms[t];
-          if (!panel_ok(tm.X, T, why) || !panel_ok(tm.Y, T, why)) return bad(why.c_str());
+          if (!panel_ok(tm.X, T, why, true) || !panel_ok(tm.Y, T, why, true))
+            return bad(why.c_str());
           if (tm.xo < 0 || tm.yo < 0 || tm.xo + tm.X.rows > U.rows || tm.yo + tm.Y.rows > V.rows)
             return bad("truncation term placement");
           if (tm.X.cols != tm.Y.cols) return bad("truncation term widths");
@@ -163,7 +171,7 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
       case hlu::OP_ADDD: {
         const hlu::PRef &Cm = o.p[0], &X = o.p[1], &Y = o.p[2];
         for (int q = 0; q < 3; ++q)
-          if (!panel_ok(o.p[q], T, why)) return bad(why.c_str());
+          if (!panel_ok(o.p[q], T, why, q > 0)) return bad(why.c_str());
         if (X.rows != Cm.rows || Y.rows != Cm.cols || X.cols != Y.cols) return bad("dense update shapes");
         if (Cm.dt != hlu::DT_F64 || Cm.trans || Cm.rankp) return bad("dense update target");
         break;

@@ -50,58 +50,133 @@ __device__ __forceinline__ void pset(const PRef& r, int i, int j, double v) {
   else gptr<float>(r.ptr)[k] = (float)v;
 }
 
-// Staging of operand tiles into LDS: every thread issues all its loads
-// before its first store, so one tile costs one memory round trip.
-// dst[i][kk] = get(i, kk) for a 64 x 32 tile (eight values per thread).
+// Batched panel access.  Element (i, j) of a stored panel sits at
+// i * si + j * sj elements from its start (a transposed panel swaps the two
+// strides; `tr` transposes the view once more).  A batch of loads takes one
+// uniform branch on the element type around all of its loads, and every
+// index must lie inside the panel: callers clamp the indices of lanes they
+// do not need and zero those values after the batch.  (Selecting zero per
+// element instead would write a register that a load is still filling, and
+// the compiler then waits for each load before issuing the next.)  An
+// identity panel (element (i, j) is one iff j == i + diag, read only) is
+// evaluated instead of loaded.
+struct GView {
+  uint64_t ptr;
+  int64_t si, sj;
+  bool f64, ident, tr;
+  int diag;
+};
+__device__ __forceinline__ GView gview(const PRef& r, bool tr = false) {
+  const bool t = (r.trans != 0) != tr;
+  GView g;
+  g.ptr = r.ptr;
+  g.si = t ? (int64_t)r.ld : 1;
+  g.sj = t ? 1 : (int64_t)r.ld;
+  g.f64 = r.dt == DT_F64;
+  g.ident = r.kind == PK_IDENT;
+  g.tr = tr;
+  g.diag = r.ld;
+  return g;
+}
+template <int N>
+__device__ __forceinline__ void gload(const GView& g, const int (&i)[N], const int (&j)[N],
+                                      double (&v)[N]) {
+  if (g.ident) {
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      v[u] = (g.tr ? i[u] == j[u] + g.diag : j[u] == i[u] + g.diag) ? 1.0 : 0.0;
+  } else if (g.f64) {
+    const HLU_G double* p = gptr<const double>(g.ptr);
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj];
+  } else {
+    const HLU_G float* p = gptr<const float>(g.ptr);
+    float f[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) f[u] = p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj];
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = (double)f[u];
+  }
+}
+template <int N>
+__device__ __forceinline__ void gstore(const GView& g, const int (&i)[N], const int (&j)[N],
+                                       const bool (&ok)[N], const double (&v)[N]) {
+  if (g.f64) {
+    HLU_G double* p = gptr<double>(g.ptr);
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (ok[u]) p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj] = v[u];
+  } else {
+    HLU_G float* p = gptr<float>(g.ptr);
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (ok[u]) p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj] = (float)v[u];
+  }
+}
+
+// Staging of operand tiles into LDS with one memory round trip per tile.
+// dst[a][b] = view(ri, cj) where map(a, b, ri, cj) returns whether the
+// element is inside the operand (else it is staged as zero and (ri, cj) must
+// still name an element inside the panel).  64 x 32 tiles:
 template <class F>
-__device__ __forceinline__ void stage_64x32(double (*dst)[33], F get) {
+__device__ __forceinline__ void stage_64x32(double (*dst)[33], const GView& g, F map) {
+  int ri[8], cj[8];
+  bool ok[8];
   double v[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int e = threadIdx.x + NT * u;
-    v[u] = get(e % 64, e / 64);
+    ok[u] = map(e % 64, e / 64, ri[u], cj[u]);
   }
+  gload(g, ri, cj, v);
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int e = threadIdx.x + NT * u;
-    dst[e % 64][e / 64] = v[u];
+    dst[e % 64][e / 64] = ok[u] ? v[u] : 0.0;
   }
 }
-// dst[kk][j] = get(kk, j) for a 32 x 64 tile
+// 32 x 64 tiles
 template <class F>
-__device__ __forceinline__ void stage_32x64(double (*dst)[65], F get) {
+__device__ __forceinline__ void stage_32x64(double (*dst)[65], const GView& g, F map) {
+  int ri[8], cj[8];
+  bool ok[8];
   double v[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int e = threadIdx.x + NT * u;
-    v[u] = get(e % 32, e / 32);
+    ok[u] = map(e % 32, e / 32, ri[u], cj[u]);
   }
+  gload(g, ri, cj, v);
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int e = threadIdx.x + NT * u;
-    dst[e % 32][e / 32] = v[u];
+    dst[e % 32][e / 32] = ok[u] ? v[u] : 0.0;
   }
 }
-// Y[r0 + ti + 16u][c0 + tj + 16v] += s * acc[u][v] within h x w: all loads
-// first, then all stores (a store could alias a later load otherwise, and
-// every element would cost a round trip)
+// Y[r0 + ti + 16u][c0 + tj + 16v] += s * acc[u][v] within h x w (h, w >= 1):
+// all loads first, then all stores (a store could alias a later load
+// otherwise, and every element would cost a round trip)
 __device__ __forceinline__ void tile_update(const PRef& Y, int r0, int c0, int h, int w, int ti,
                                             int tj, double s, const double (&acc)[4][4]) {
-  double old[4][4];
+  const GView g = gview(Y);
+  int ri[16], cj[16];
+  bool ok[16];
+  double v[16];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = ti + 16 * u, j = tj + 16 * v;
-      old[u][v] = (i < h && j < w) ? pget(Y, r0 + i, c0 + j) : 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int i = ti + 16 * u, j = tj + 16 * q;
+      ok[4 * u + q] = i < h && j < w;
+      ri[4 * u + q] = r0 + min(i, h - 1);
+      cj[4 * u + q] = c0 + min(j, w - 1);
     }
+  gload(g, ri, cj, v);
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = ti + 16 * u, j = tj + 16 * v;
-      if (i < h && j < w) pset(Y, r0 + i, c0 + j, old[u][v] + s * acc[u][v]);
-    }
+    for (int q = 0; q < 4; ++q) v[4 * u + q] += s * acc[u][q];
+  gstore(g, ri, cj, ok, v);
 }
 
 // cross-lane helpers (64-wide wavefronts)
@@ -302,25 +377,30 @@ __device__ __forceinline__ void trsm_body(const Op& op) {
   if (type != OP_TRSM_L && tid < b) dinv[tid] = 1.0 / l[tid][tid];
   __syncthreads();
   const int col = tid >> 3, ln = tid & 7;
-  for (int c0 = 0; c0 < c; c0 += 32) {
+  const GView gy = gview(Y);
+  for (int c0 = 0; c0 < (b > 0 ? c : 0); c0 += 32) {
     const int j = c0 + col;
     const bool act = j < c;
+    int ri[8], cj[8];
+    bool ok[8];
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = ln + 8 * u;
-      v[u] = (act && i < b) ? pget(Y, type == OP_TRSM_L ? pm[i] : i, j) : 0.0;
+      const int i = min(ln + 8 * u, b - 1);
+      ok[u] = act && ln + 8 * u < b;
+      ri[u] = type == OP_TRSM_L ? pm[i] : i;
+      cj[u] = min(j, c - 1);
+    }
+    gload(gy, ri, cj, v);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[u] = ok[u] ? v[u] : 0.0;
+      ri[u] = min(ln + 8 * u, b - 1);
     }
     if (type == OP_TRSM_L) trsm_subst<OP_TRSM_L>(v, l, dinv, b, ln);
     else if (type == OP_TRSM_UT) trsm_subst<OP_TRSM_UT>(v, l, dinv, b, ln);
     else trsm_subst<OP_TRSM_U>(v, l, dinv, b, ln);
-    if (act) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = ln + 8 * u;
-        if (i < b) pset(Y, i, j, v[u]);
-      }
-    }
+    gstore(gy, ri, cj, ok, v);
   }
   const double es = Y.dt == DT_F64 ? 8.0 : 4.0;
   put_cost(op, (double)b * b * c, 8.0 * b * b / 2 + 2.0 * es * b * c);
@@ -329,24 +409,267 @@ __device__ __forceinline__ void trsm_body(const Op& op) {
 // ---------------------------------------------------------------- panel products
 // p3 += d0 * op(M) p2.  Dense M: tiles of 64 x 64 outputs with 32-deep LDS
 // slabs.  Low-rank M = A B^T: T = B^T X (k x c) in LDS, then Y += d0 A T.
-#define LDS_PGEMM (64 * 33 * 8 + 32 * 65 * 8 + 64 * 65 * 8)
-__device__ void d_pgemm(const Op& op) {
+#define LDS_PGEMM_WIDE (64 * 33 * 8 + 32 * 65 * 8 + 64 * 65 * 8)
+// narrow products: dense (M chunk 64 x 65, X chunk 64 x 17, partials 4 x 64 x 17)
+// and low-rank (B chunk 64 x 33, X chunk 64 x 17, T 32 x 17, A tile 64 x 33,
+// partials 4 x 64 x 17 = 8 x 32 x 17)
+#define PGN_DENSE_DBL (64 * 65 + 64 * 17 + 4 * 64 * 17)
+#define PGN_LR_DBL (64 * 33 + 64 * 17 + 32 * 17 + 64 * 33 + 4 * 64 * 17)
+#define LDS_PGEMM_NARROW ((PGN_DENSE_DBL > PGN_LR_DBL ? PGN_DENSE_DBL : PGN_LR_DBL) * 8)
+#define LDS_PGEMM (LDS_PGEMM_WIDE > LDS_PGEMM_NARROW ? LDS_PGEMM_WIDE : LDS_PGEMM_NARROW)
+
+// R x C tile of a panel view held in registers (R * C / NT values per
+// thread; consecutive lanes take consecutive rows, so column-major panels
+// load coalesced).  load() reads rows a0 .. a0 + h - 1 and columns
+// b0 .. b0 + w - 1 (h, w >= 1; lanes beyond them read a clamped element),
+// put() stores the tile to LDS with zeros outside h x w.
+template <int R, int C>
+struct TileRegs {
+  static constexpr int N = R * C / NT;
+  double v[N];
+  __device__ __forceinline__ void load(const GView& g, int a0, int b0, int h, int w) {
+    int ri[N], cj[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int e = threadIdx.x + NT * u;
+      ri[u] = a0 + min(e % R, h - 1);
+      cj[u] = b0 + min(e / R, w - 1);
+    }
+    gload(g, ri, cj, v);
+  }
+  template <int LD>
+  __device__ __forceinline__ void put(double* dst, int h, int w) const {
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int e = threadIdx.x + NT * u, a = e % R, b = e / R;
+      dst[a * LD + b] = (a < h && b < w) ? v[u] : 0.0;
+    }
+  }
+};
+
+// Sum of the four wavefronts' 64 x 16 partials (red[g][row][col], ld 17)
+// plus the old values, stored to rows r0 .. r0 + h - 1, columns 0 .. w - 1
+// of Y.  Thread t owns row t % 64, columns t / 64 + 4u (the layout of
+// TileRegs<64, 16>).
+__device__ __forceinline__ void narrow_finish(const GView& gy, const double* red, int r0, int h,
+                                              int w, double sg, const double (&old)[4]) {
+  const int a = threadIdx.x & 63;
+  int ri[4], cj[4];
+  bool ok[4];
+  double out[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int b = (threadIdx.x >> 6) + 4 * u;
+    const double s = red[a * 17 + b] + red[(64 + a) * 17 + b] + red[(128 + a) * 17 + b] +
+                     red[(192 + a) * 17 + b];
+    out[u] = old[u] + sg * s;
+    ok[u] = a < h && b < w;
+    ri[u] = r0 + min(a, h - 1);
+    cj[u] = min(b, w - 1);
+  }
+  gstore(gy, ri, cj, ok, out);
+}
+
+// Y += sg * op(M) X for at most 16 columns.  Output tiles of 64 x 16; lane
+// (ti, tj) of wavefront g holds rows ti + 16u, columns tj + 4v, and takes
+// the inner indices 16g .. 16g + 15 of each 64-deep chunk; the four
+// partials meet in LDS.  The old values of the tile and the first chunk
+// are loaded together.
+__device__ __forceinline__ void pgemm_narrow_dense(const Op& op, const PRef& X, const PRef& Y,
+                                                   int m, int c, double sg) {
+  double* const sm = reinterpret_cast<double*>(hlu_lds);
+  double* const sx = sm + 64 * 65;
+  double* const red = sx + 64 * 17;
+  const GView gm = gview(op.p[0], op.i1 != 0), gx = gview(X), gy = gview(Y);
+  const int r = X.rows;
+  const int tid = threadIdx.x, g = tid >> 6, ti = tid & 15, tj = (tid >> 4) & 3;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    const int h = min(64, m - r0);
+    TileRegs<64, 16> yo;
+    yo.load(gy, r0, 0, h, c);
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int k0 = 0; k0 < r; k0 += 64) {
+      const int d = min(64, r - k0);
+      TileRegs<64, 64> mt;
+      TileRegs<64, 16> xt;
+      mt.load(gm, r0, k0, h, d);
+      xt.load(gx, k0, 0, d, c);
+      mt.put<65>(sm, h, d);
+      xt.put<17>(sx, d, c);
+      __syncthreads();
+      const int kb = 16 * g, ke = min(kb + 16, d);
+      for (int kk = kb; kk < ke; ++kk) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = sm[(ti + 16 * u) * 65 + kk];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bv[v] = sx[kk * 17 + tj + 4 * v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(g * 64 + ti + 16 * u) * 17 + tj + 4 * v] = acc[u][v];
+    __syncthreads();
+    narrow_finish(gy, red, r0, h, c, sg, yo.v);
+    __syncthreads();
+  }
+}
+
+// Y += sg * A (B^T X) for at most 16 columns and rank k <= 32 (A: m x k,
+// B: r x k).  T = B^T X: lane (ta, tb) of group q (eight groups of 32
+// lanes) holds T rows ta + 8u, columns tb + 4v over the rows 8q .. 8q + 7
+// of each 64-row chunk, the next chunk loading while the current one is
+// multiplied; the eight partials meet in LDS.  Then Y += sg A T tile by
+// tile as in the dense case (wavefront g takes rank indices 8g .. 8g + 7),
+// the first tile's A rows and old values loading with the first chunk and
+// every later tile's while the previous one is computed.
+__device__ __forceinline__ void pgemm_narrow_lr(const PRef& A, const PRef& B, const PRef& X,
+                                                const PRef& Y, int m, int c, int k, double sg) {
+  double* const sb = reinterpret_cast<double*>(hlu_lds);
+  double* const sx = sb + 64 * 33;
+  double* const st = sx + 64 * 17;
+  double* const sa = st + 32 * 17;
+  double* const red = sa + 64 * 33;
+  const GView ga = gview(A), gb = gview(B), gx = gview(X), gy = gview(Y);
+  const int r = X.rows;
+  const int tid = threadIdx.x;
+  TileRegs<64, 32> at;
+  TileRegs<64, 16> yo;
+  at.load(ga, 0, 0, min(64, m), k);
+  yo.load(gy, 0, 0, min(64, m), c);
+  {
+    const int q = tid >> 5, ta = tid & 7, tb = (tid >> 3) & 3;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    TileRegs<64, 32> bt;
+    TileRegs<64, 16> xt;
+    if (r > 0) {
+      bt.load(gb, 0, 0, min(64, r), k);
+      xt.load(gx, 0, 0, min(64, r), c);
+    }
+    for (int k0 = 0; k0 < r; k0 += 64) {
+      const int d = min(64, r - k0);
+      bt.put<33>(sb, d, k);
+      xt.put<17>(sx, d, c);
+      __syncthreads();
+      if (k0 + 64 < r) {
+        bt.load(gb, k0 + 64, 0, min(64, r - k0 - 64), k);
+        xt.load(gx, k0 + 64, 0, min(64, r - k0 - 64), c);
+      }
+      const int ib = 8 * q, ie = min(ib + 8, d);
+      for (int i = ib; i < ie; ++i) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = sb[i * 33 + ta + 8 * u];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bv[v] = sx[i * 17 + tb + 4 * v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(q * 32 + ta + 8 * u) * 17 + tb + 4 * v] = acc[u][v];
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int e = tid + NT * w, a = e & 31, b = e >> 5;
+      double s = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < 8; ++q2) s += red[(q2 * 32 + a) * 17 + b];
+      st[a * 17 + b] = s;
+    }
+    __syncthreads();
+  }
+  const int g = tid >> 6, ti = tid & 15, tj = (tid >> 4) & 3;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    const int h = min(64, m - r0);
+    at.put<33>(sa, h, k);
+    __syncthreads();
+    double old[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) old[u] = yo.v[u];
+    if (r0 + 64 < m) {
+      at.load(ga, r0 + 64, 0, min(64, m - r0 - 64), k);
+      yo.load(gy, r0 + 64, 0, min(64, m - r0 - 64), c);
+    }
+    double o[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[u][v] = 0.0;
+    const int kb = 8 * g, ke = min(kb + 8, k);
+    for (int kk = kb; kk < ke; ++kk) {
+      double av[4], tv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = sa[(ti + 16 * u) * 33 + kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tv[v] = st[kk * 17 + tj + 4 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[u][v] += av[u] * tv[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(g * 64 + ti + 16 * u) * 17 + tj + 4 * v] = o[u][v];
+    __syncthreads();
+    narrow_finish(gy, red, r0, h, c, sg, old);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void pgemm_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef X = op.p[2];
   const PRef Y = op.p[3];
   const double sg = op.d0;
   const int tid = threadIdx.x;
-  const int c = pcols(Y) < pcols(X) ? pcols(Y) : pcols(X);
+  const int cy = pcols(Y), cx = pcols(X);
+  const int kl = op.i0 == 0 ? 0 : pcols(op.p[0]);
+  const int c = min(cy, cx);
   const int m = Y.rows;
+  const double esx = X.dt == DT_F64 ? 8.0 : 4.0;
+  const double esy = Y.dt == DT_F64 ? 8.0 : 4.0;
+  if (c <= 16 && (op.i0 == 0 || kl <= 32)) {
+    const int r = X.rows;
+    if (op.i0 == 0) {
+      if (c > 0 && m > 0) pgemm_narrow_dense(op, X, Y, m, c, sg);
+      put_cost(op, 2.0 * m * r * c, 8.0 * m * r + esx * r * c + 2.0 * esy * m * c);
+    } else {
+      const bool tr = op.i1 != 0;
+      if (c > 0 && m > 0 && kl > 0)
+        pgemm_narrow_lr(tr ? op.p[1] : op.p[0], tr ? op.p[0] : op.p[1], X, Y, m, c, kl, sg);
+      const double esm = op.p[0].dt == DT_F64 ? 8.0 : 4.0;
+      put_cost(op, 2.0 * (double)kl * c * (r + m),
+               esm * (double)kl * (r + m) + esx * r * c + 2.0 * esy * m * c);
+    }
+    return;
+  }
   double (*sa)[33] = reinterpret_cast<double (*)[33]>(smem);
   double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8);
   double (*st)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8 + 32 * 65 * 8);
   const int ti = tid % 16, tj = tid / 16;   // 16 x 16 threads, 4 x 4 outputs each
-  const double esx = X.dt == DT_F64 ? 8.0 : 4.0;
-  const double esy = Y.dt == DT_F64 ? 8.0 : 4.0;
   if (op.i0 == 0) {
-    PRef M = op.p[0];
-    const bool tr = op.i1 != 0;
+    const GView gm = gview(op.p[0], op.i1 != 0), gx = gview(X);
     const int r = X.rows;   // inner dimension
     for (int c0 = 0; c0 < c; c0 += 64) {
       const int w = min(64, c - c0);
@@ -359,12 +682,15 @@ __device__ void d_pgemm(const Op& op) {
           for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
         for (int k0 = 0; k0 < r; k0 += 32) {
           const int d = min(32, r - k0);
-          stage_64x32(sa, [&](int i, int kk) {
-            if (i >= h || kk >= d) return 0.0;
-            return tr ? pget(M, k0 + kk, r0 + i) : pget(M, r0 + i, k0 + kk);
+          stage_64x32(sa, gm, [&](int i, int kk, int& a, int& b) {
+            a = r0 + min(i, h - 1);
+            b = k0 + min(kk, d - 1);
+            return i < h && kk < d;
           });
-          stage_32x64(sb, [&](int kk, int j) {
-            return (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
+          stage_32x64(sb, gx, [&](int kk, int j, int& a, int& b) {
+            a = k0 + min(kk, d - 1);
+            b = c0 + min(j, w - 1);
+            return kk < d && j < w;
           });
           __syncthreads();
           for (int kk = 0; kk < d; ++kk) {
@@ -391,10 +717,11 @@ __device__ void d_pgemm(const Op& op) {
   const bool tr = op.i1 != 0;
   const PRef A = tr ? V : U;
   const PRef B = tr ? U : V;
-  const int k = pcols(U);
+  const int k = kl;
   const int r = X.rows;
   const double esm = U.dt == DT_F64 ? 8.0 : 4.0;
-  for (int c0 = 0; c0 < c; c0 += 64) {
+  const GView ga = gview(A), gb = gview(B, true), gx = gview(X);
+  for (int c0 = 0; c0 < (k > 0 ? c : 0); c0 += 64) {
     const int w = min(64, c - c0);
     // T = B^T X  (k x w), k <= 64
     double acc[4][4];
@@ -405,11 +732,15 @@ __device__ void d_pgemm(const Op& op) {
     for (int k0 = 0; k0 < r; k0 += 32) {
       const int d = min(32, r - k0);
       // i: rank index, kk: row of B
-      stage_64x32(sa, [&](int i, int kk) {
-        return (i < k && kk < d) ? pget(B, k0 + kk, i) : 0.0;
+      stage_64x32(sa, gb, [&](int i, int kk, int& a, int& b) {
+        a = min(i, k - 1);
+        b = k0 + min(kk, d - 1);
+        return i < k && kk < d;
       });
-      stage_32x64(sb, [&](int kk, int j) {
-        return (kk < d && j < w) ? pget(X, k0 + kk, c0 + j) : 0.0;
+      stage_32x64(sb, gx, [&](int kk, int j, int& a, int& b) {
+        a = k0 + min(kk, d - 1);
+        b = c0 + min(j, w - 1);
+        return kk < d && j < w;
       });
       __syncthreads();
       for (int kk = 0; kk < d; ++kk) {
@@ -433,8 +764,10 @@ __device__ void d_pgemm(const Op& op) {
     // Y += sg * A T
     for (int r0 = 0; r0 < m; r0 += 64) {
       const int h = min(64, m - r0);
-      stage_64x32(sa, [&](int i, int kk) {
-        return (i < h && kk < k && kk < 32) ? pget(A, r0 + i, kk) : 0.0;
+      stage_64x32(sa, ga, [&](int i, int kk, int& a, int& b) {
+        a = r0 + min(i, h - 1);
+        b = min(kk, k - 1);
+        return i < h && kk < k;
       });
       __syncthreads();
       double o[4][4];
@@ -454,8 +787,10 @@ __device__ void d_pgemm(const Op& op) {
       }
       __syncthreads();
       if (k > 32) {
-        stage_64x32(sa, [&](int i, int kk) {
-          return (i < h && 32 + kk < k) ? pget(A, r0 + i, 32 + kk) : 0.0;
+        stage_64x32(sa, ga, [&](int i, int kk, int& a, int& b) {
+          a = r0 + min(i, h - 1);
+          b = min(32 + kk, k - 1);
+          return i < h && 32 + kk < k;
         });
         __syncthreads();
         for (int kk = 0; kk < k - 32; ++kk) {
@@ -480,7 +815,7 @@ __device__ void d_pgemm(const Op& op) {
 // ---------------------------------------------------------------- dense update
 // p0 (FP64 dense, m x n) -= p1 p2^T
 #define LDS_ADDD (64 * 33 * 8 + 32 * 65 * 8)
-__device__ void d_addd(const Op& op) {
+__device__ __forceinline__ void addd_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef C = op.p[0], X = op.p[1], Y = op.p[2];
   const int m = C.rows, n = C.cols;
@@ -489,6 +824,7 @@ __device__ void d_addd(const Op& op) {
   double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8);
   const int tid = threadIdx.x;
   const int ti = tid % 16, tj = tid / 16;
+  const GView gx = gview(X), gy = gview(Y, true);
   for (int c0 = 0; c0 < n; c0 += 64) {
     const int w = min(64, n - c0);
     for (int r0 = 0; r0 < m; r0 += 64) {
@@ -500,11 +836,15 @@ __device__ void d_addd(const Op& op) {
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
       for (int k0 = 0; k0 < k; k0 += 32) {
         const int d = min(32, k - k0);
-        stage_64x32(sa, [&](int i, int kk) {
-          return (i < h && kk < d) ? pget(X, r0 + i, k0 + kk) : 0.0;
+        stage_64x32(sa, gx, [&](int i, int kk, int& a, int& b) {
+          a = r0 + min(i, h - 1);
+          b = k0 + min(kk, d - 1);
+          return i < h && kk < d;
         });
-        stage_32x64(sb, [&](int kk, int j) {
-          return (kk < d && j < w) ? pget(Y, c0 + j, k0 + kk) : 0.0;
+        stage_32x64(sb, gy, [&](int kk, int j, int& a, int& b) {
+          a = k0 + min(kk, d - 1);
+          b = c0 + min(j, w - 1);
+          return kk < d && j < w;
         });
         __syncthreads();
         for (int kk = 0; kk < d; ++kk) {
@@ -528,12 +868,18 @@ __device__ void d_addd(const Op& op) {
 }
 
 // ---------------------------------------------------------------- zero
-__device__ void d_zero(const Op& op) {
+__device__ __forceinline__ void zero_body(const Op& op) {
   const PRef Z = op.p[0];
   const int tot = Z.rows * Z.cols;
-  for (int e = threadIdx.x; e < tot; e += NT) {
-    int i = e % Z.rows, j = e / Z.rows;
-    pset(Z, i, j, 0.0);
+  const GView g = gview(Z);
+  if (g.f64) {
+    HLU_G double* p = gptr<double>(g.ptr);
+    for (int e = threadIdx.x; e < tot; e += NT)
+      p[(int64_t)(e % Z.rows) * g.si + (int64_t)(e / Z.rows) * g.sj] = 0.0;
+  } else {
+    HLU_G float* p = gptr<float>(g.ptr);
+    for (int e = threadIdx.x; e < tot; e += NT)
+      p[(int64_t)(e % Z.rows) * g.si + (int64_t)(e / Z.rows) * g.sj] = 0.0f;
   }
   put_cost(op, 0.0, (Z.dt == DT_F64 ? 8.0 : 4.0) * tot);
 }
@@ -1419,25 +1765,33 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   double pv[8], px[8];
+  const GView gv = gview(V), gx = gview(X);
+  // loads only: lanes outside V or X read a clamped element and are zeroed
+  // when the chunk is stored to LDS, so the prefetch stays in flight
   auto fetch = [&](int r0) {
+    int ri[8], cv[8], cx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = tid + NT * u, i = q & 31, j = q >> 5;
+      ri[u] = min(r0 + i, n - 1);
+      cv[u] = min(j, k - 1);
+      cx[u] = min(j, nr - 1);
+    }
+    gload(gv, ri, cv, pv);
+    gload(gx, ri, cx, px);
+  };
+  const int nn = (k > 0 && nr > 0) ? n : 0;
+  if (nn > 0) fetch(0);
+  for (int r0 = 0; r0 < nn; r0 += 32) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int q = tid + NT * u, i = q & 31, j = q >> 5;
       const bool in = r0 + i < n;
-      pv[u] = (in && j < k) ? pget(V, r0 + i, j) : 0.0;
-      px[u] = (in && j < nr) ? pget(X, r0 + i, j) : 0.0;
-    }
-  };
-  if (n > 0) fetch(0);
-  for (int r0 = 0; r0 < n; r0 += 32) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = tid + NT * u, i = q & 31, j = q >> 5;
-      sv[i][j] = pv[u];
-      sx[i][j] = px[u];
+      sv[i][j] = (in && j < k) ? pv[u] : 0.0;
+      sx[i][j] = (in && j < nr) ? px[u] : 0.0;
     }
     __syncthreads();
-    if (r0 + 32 < n) fetch(r0 + 32);
+    if (r0 + 32 < nn) fetch(r0 + 32);
     const int d = min(32, n - r0);
     for (int i = 0; i < d; ++i) {
       double av[4], bv[4];
@@ -1948,11 +2302,13 @@ __device__ __forceinline__ void invapply_body(const Op& op) {
   put_cost(op, 2.0 * b * b * nr, 8.0 * b * b + 16.0 * b * nr);
 }
 
-// Out-of-line entries of the leaf solve and the H-matvec update bodies (the
-// wave kernel and the factor executor call these; the solve executor, which
-// runs only these types, takes the bodies inline and so saves no registers
-// across a call).
+// Out-of-line entries of the leaf solve, panel product, dense update, zeroing
+// and H-matvec update bodies for the wave kernel.  The dataflow executors
+// take the bodies inline, so no registers are saved across a call.
 __device__ __noinline__ void d_trsm(const Op& op) { trsm_body(op); }
+__device__ __noinline__ void d_pgemm(const Op& op) { pgemm_body(op); }
+__device__ __noinline__ void d_addd(const Op& op) { addd_body(op); }
+__device__ __noinline__ void d_zero(const Op& op) { zero_body(op); }
 __device__ __noinline__ void d_mvt(const Op& op) { mvt_body(op); }
 __device__ __noinline__ void d_mvrow(const Op& op) { mvrow_body(op); }
 __device__ __noinline__ void d_invapply(const Op& op) { invapply_body(op); }
@@ -2034,7 +2390,6 @@ constexpr unsigned DF_SOLVE_TYPES = (1u << OP_MVT) | (1u << OP_MVROW) | (1u << O
 
 template <unsigned MASK>
 __device__ __forceinline__ bool run_op_masked(const Op& op) {
-  constexpr bool kInlineSolveOps = MASK == DF_SOLVE_TYPES;
   start_tick(op);
   switch (op.type) {
     case OP_GETRF: if constexpr ((MASK >> OP_GETRF) & 1) { d_getrf(op); return true; } break;
@@ -2042,34 +2397,30 @@ __device__ __forceinline__ bool run_op_masked(const Op& op) {
     case OP_TRSM_UT:
     case OP_TRSM_U:
       if constexpr (MASK & ((1u << OP_TRSM_L) | (1u << OP_TRSM_UT) | (1u << OP_TRSM_U))) {
-        if constexpr (kInlineSolveOps) trsm_body(op);
-        else d_trsm(op);
+        trsm_body(op);
         return true;
       }
       break;
-    case OP_PGEMM: if constexpr ((MASK >> OP_PGEMM) & 1) { d_pgemm(op); return true; } break;
+    case OP_PGEMM: if constexpr ((MASK >> OP_PGEMM) & 1) { pgemm_body(op); return true; } break;
     case OP_TRUNC: if constexpr ((MASK >> OP_TRUNC) & 1) { d_trunc(op); return true; } break;
-    case OP_ADDD: if constexpr ((MASK >> OP_ADDD) & 1) { d_addd(op); return true; } break;
-    case OP_ZERO: if constexpr ((MASK >> OP_ZERO) & 1) { d_zero(op); return true; } break;
+    case OP_ADDD: if constexpr ((MASK >> OP_ADDD) & 1) { addd_body(op); return true; } break;
+    case OP_ZERO: if constexpr ((MASK >> OP_ZERO) & 1) { zero_body(op); return true; } break;
     case OP_MVT:
       if constexpr ((MASK >> OP_MVT) & 1) {
-        if constexpr (kInlineSolveOps) mvt_body(op);
-        else d_mvt(op);
+        mvt_body(op);
         return true;
       }
       break;
     case OP_MVROW:
       if constexpr ((MASK >> OP_MVROW) & 1) {
-        if constexpr (kInlineSolveOps) mvrow_body(op);
-        else d_mvrow(op);
+        mvrow_body(op);
         return true;
       }
       break;
     case OP_TRINV: if constexpr ((MASK >> OP_TRINV) & 1) { d_trinv(op); return true; } break;
     case OP_INVAPPLY:
       if constexpr ((MASK >> OP_INVAPPLY) & 1) {
-        if constexpr (kInlineSolveOps) invapply_body(op);
-        else d_invapply(op);
+        invapply_body(op);
         return true;
       }
       break;
