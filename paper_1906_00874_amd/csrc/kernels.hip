@@ -187,6 +187,14 @@ __device__ __forceinline__ double dpp_d(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// FP64 matrix-core step D += A B with A 16 x 4 and B 4 x 16 (one wavefront):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and its four
+// results are D[l / 16 + 4r][l % 16], r = 0..3.
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // per-op record {model flops, algorithmic bytes, rank-capacity hit, rank,
 // start tick, end tick, stack width, 0} (ticks of the constant-rate wall
 // clock, written by thread 0)
@@ -1106,134 +1114,61 @@ __device__ __forceinline__ void trunc_load2(TruncShared& sh, double (*d0)[KM + 1
 }
 
 // Gx into gx and Gy into gy: threads 0-127 take the X side (chunks staged in
-// m), threads 128-255 the Y side (chunks staged in gy)
+// m), threads 128-255 the Y side (chunks staged in gy).  The matrix cores
+// form the 16 x 16 tiles on and above the diagonal (at most ten, dealt to
+// the side's two wavefronts), four rows per step; the tiles above the
+// diagonal are mirrored when written.
 __device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K) {
   const int tid = threadIdx.x;
-  const int side = tid >> 7, t = tid & 127;
+  const int side = tid >> 7, w = (tid >> 6) & 1, l = tid & 63;
   const int rows_side = side ? n : m;
   double (*C)[KM + 1] = side ? sh.gy : sh.m;
   double (*G)[KM + 1] = side ? sh.gy : sh.gx;
-  const int B = (K + 3) >> 2, BB = B * B;
-  int NG, grp, blk0, blk1;
-  if (BB == 0) {
-    NG = 1; grp = 0; blk0 = -1; blk1 = -1;
-  } else if (BB <= 128) {
-    NG = min(128 / BB, 16);
-    grp = t / BB;
-    blk0 = grp < NG ? t % BB : -1;
-    blk1 = -1;
-  } else {
-    NG = 1;
-    grp = 0;
-    blk0 = t;
-    blk1 = t + 128 < BB ? t + 128 : -1;
+  const int nb = (K + 15) >> 4, ntile = nb * (nb + 1) / 2;
+  int ta[5], tb[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    int a = 0, b = w + 2 * j;
+    while (a < nb && b >= nb - a) {
+      b -= nb - a;
+      ++a;
+    }
+    ta[j] = 16 * a;
+    tb[j] = 16 * (a + b);
   }
-  const int a0 = blk0 >= 0 ? 4 * (blk0 / B) : 0, b0 = blk0 >= 0 ? 4 * (blk0 % B) : 0;
-  const int a1 = blk1 >= 0 ? 4 * (blk1 / B) : 0, b1 = blk1 >= 0 ? 4 * (blk1 % B) : 0;
-  double acc0[4][4], acc1[4][4];
+  v4d acc[5];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc0[u][v] = acc1[u][v] = 0.0;
+  for (int j = 0; j < 5; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
   const int rows = max(m, n);
   for (int r0 = 0; r0 < rows; r0 += 64) {
     trunc_load2(sh, sh.m, sh.gy, r0, m, n, K);
     __syncthreads();
-    const int h = min(64, rows_side - r0);
-    if (blk0 >= 0) {
-      int i0 = grp;
-      // four rows per step: their LDS reads are issued together
-      for (; i0 + 3 * NG < h; i0 += 4 * NG) {
-        double av[4][4], bv[4][4];
+    const int nq = min(16, (rows_side - r0 + 3) >> 2);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            av[r][u] = a0 + u < K ? C[i0 + r * NG][a0 + u] : 0.0;
-            bv[r][u] = b0 + u < K ? C[i0 + r * NG][b0 + u] : 0.0;
-          }
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc0[u][v] += av[r][u] * bv[r][v];
-        if (blk1 >= 0) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              av[r][u] = a1 + u < K ? C[i0 + r * NG][a1 + u] : 0.0;
-              bv[r][u] = b1 + u < K ? C[i0 + r * NG][b1 + u] : 0.0;
-            }
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc1[u][v] += av[r][u] * bv[r][v];
-        }
-      }
-      for (int i = i0; i < h; i += NG) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          av[u] = a0 + u < K ? C[i][a0 + u] : 0.0;
-          bv[u] = b0 + u < K ? C[i][b0 + u] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc0[u][v] += av[u] * bv[v];
-        if (blk1 >= 0) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            av[u] = a1 + u < K ? C[i][a1 + u] : 0.0;
-            bv[u] = b1 + u < K ? C[i][b1 + u] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc1[u][v] += av[u] * bv[v];
+    for (int j = 0; j < 5; ++j) {
+      if (w + 2 * j < ntile) {
+        for (int q = 0; q < nq; ++q) {
+          const int i = 4 * q + (l >> 4);
+          acc[j] = mfma16x16x4(C[i][ta[j] + (l & 15)], C[i][tb[j] + (l & 15)], acc[j]);
         }
       }
     }
     __syncthreads();
   }
-  if (NG == 1) {
-    if (blk0 >= 0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+  for (int j = 0; j < 5; ++j) {
+    if (w + 2 * j < ntile) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (a0 + u < K && b0 + v < K) G[a0 + u][b0 + v] = acc0[u][v];
+      for (int r = 0; r < 4; ++r) {
+        const int a = ta[j] + (l >> 4) + 4 * r, b = tb[j] + (l & 15);
+        if (a < K && b < K) {
+          G[a][b] = acc[j][r];
+          if (ta[j] != tb[j]) G[b][a] = acc[j][r];
+        }
+      }
     }
-    if (blk1 >= 0) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (a1 + u < K && b1 + v < K) G[a1 + u][b1 + v] = acc1[u][v];
-    }
-    __syncthreads();
-  } else {
-    double* part = &sh.z[0][0] + side * 2048;
-    if (blk0 >= 0) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) part[(grp * BB + blk0) * 16 + u * 4 + v] = acc0[u][v];
-    }
-    __syncthreads();
-    for (int e = t; e < K * K; e += 128) {
-      const int a = e % K, b = e / K;
-      const int q = ((a >> 2) * B + (b >> 2)) * 16 + (a & 3) * 4 + (b & 3);
-      double s = 0.0;
-      for (int g = 0; g < NG; ++g) s += part[g * BB * 16 + q];
-      G[a][b] = s;
-    }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Pivoted Cholesky of the K x K matrix G by one wavefront; lane j keeps
@@ -1351,38 +1286,44 @@ __device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int 
 // chunks staged in gx / z
 __device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, const PRef& V, int m,
                                              int n, int K, int k) {
+  // per side and row chunk: out (64 x k) = C (64 x K) T (K x k), taken
+  // transposed on the matrix cores (out^T = T^T C^T) so that the sixteen
+  // lanes of a result register hold consecutive rows; the side's two
+  // wavefronts share the 16 x 16 tiles
   const int tid = threadIdx.x;
-  const int side = tid >> 7, t = tid & 127;
-  const int i = t & 63, c0 = (t >> 6) * 16;
+  const int side = tid >> 7, w = (tid >> 6) & 1, l = tid & 63;
   const int rows_side = side ? n : m;
   double (*C)[KM + 1] = side ? sh.z : sh.gx;
   double (*T)[KM + 1] = side ? sh.gy : sh.m;
+  const GView g = gview(side ? V : U);
   const int rows = max(m, n);
+  const int ntile = 4 * ((k + 15) >> 4), nq = (K + 3) >> 2;
   for (int r0 = 0; r0 < rows; r0 += 64) {
     trunc_load2(sh, sh.gx, sh.z, r0, m, n, K);
     __syncthreads();
-    if (r0 + i < rows_side && c0 < k) {
-      double o[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) o[v] = 0.0;
-      for (int c2 = 0; c2 < K; ++c2) {
-        // the row of T first (the reads overlap), then the updates
-        const double a = C[i][c2];
-        double tv[16];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) tv[v] = T[c2][c0 + v];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) o[v] += a * tv[v];
+    const int h = rows_side - r0;
+    for (int tt = w; tt < ntile; tt += 2) {
+      const int i0 = 16 * (tt & 3), c0 = 16 * (tt >> 2);
+      if (i0 >= h) continue;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < nq; ++q) {
+        const int kk = 4 * q + (l >> 4);
+        const double a = kk < K ? T[kk][c0 + (l & 15)] : 0.0;
+        const double b = kk < K ? C[i0 + (l & 15)][kk] : 0.0;
+        acc = mfma16x16x4(a, b, acc);
       }
-      if (side) {   // wave-uniform branch
+      int ri[4], cj[4];
+      bool ok[4];
+      double o[4];
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          if (c0 + v < k) pset(V, r0 + i, c0 + v, o[v]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < 16; ++v)
-          if (c0 + v < k) pset(U, r0 + i, c0 + v, o[v]);
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + (l & 15), col = c0 + (l >> 4) + 4 * r;
+        ok[r] = row < h && col < k;
+        ri[r] = r0 + min(row, h - 1);
+        cj[r] = min(col, k - 1);
+        o[r] = acc[r];
       }
+      gstore(g, ri, cj, ok, o);
     }
     __syncthreads();
   }
