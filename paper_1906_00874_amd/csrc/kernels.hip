@@ -921,13 +921,16 @@ __device__ __forceinline__ void zero_body(const Op& op) {
 // Stacked column j of one side: element i is sign * base[(i - r0) * stride]
 // for r0 <= i < r0 + rows and zero elsewhere; an identity column (ident)
 // holds a single one at row r0 + irow.
-struct ColDesc {
-  uint64_t base;
-  int32_t stride, r0, rows, irow;
-  uint8_t dt, ident;
-  int8_t sign;
-  uint8_t pad[5];
+// Stacked column j of one side, resolved once per pass: element i (a row of
+// the stacked panel) lies at base0 + i * sbytes for lo <= i < hi and is zero
+// elsewhere; an identity column holds a single one at row irow.  flags: bit
+// 0 FP64 storage, bit 1 identity, bit 2 negated.  Read as two 16-byte words.
+struct __align__(16) ColDesc {
+  uint64_t base0;
+  int32_t sbytes, lo, hi, irow;
+  uint32_t flags, pad;
 };
+static_assert(sizeof(ColDesc) == 32, "column descriptors are read as two 16-byte words");
 
 struct TruncShared {
   double lv[2][KM];         // pivot rows broadcast by the two Cholesky waves (16-byte aligned)
@@ -1056,14 +1059,16 @@ __device__ __forceinline__ void trunc_coldesc(TruncShared& sh, const PRef& U, co
     }
     ColDesc d;
     const int64_t es = dt == DT_F64 ? 8 : 4;
-    d.base = ptr + (uint64_t)((trans ? (int64_t)cj : (int64_t)cj * ld) * es);
-    d.stride = trans ? ld : 1;
-    d.r0 = r0;
-    d.rows = rows;
-    d.irow = cj - ld;   // identity: (ii, cj) is one iff cj == ii + ld
-    d.dt = dt;
-    d.ident = kind == PK_IDENT;
-    d.sign = (int8_t)sg;
+    const int64_t sb = (trans ? (int64_t)ld : 1) * es;
+    // the panel's row ii is stacked row r0 + ii
+    d.base0 = ptr + (uint64_t)((trans ? (int64_t)cj : (int64_t)cj * ld) * es) -
+              (uint64_t)((int64_t)r0 * sb);
+    d.sbytes = (int32_t)sb;
+    d.lo = r0;
+    d.hi = r0 + rows;
+    d.irow = r0 + cj - ld;   // identity: (ii, cj) is one iff cj == ii + ld
+    d.flags = (dt == DT_F64 ? 1u : 0u) | (kind == PK_IDENT ? 2u : 0u) | (sg < 0 ? 4u : 0u);
+    d.pad = 0;
     sh.cd[side][j] = d;
   }
 }
@@ -1072,44 +1077,100 @@ __device__ __forceinline__ void trunc_coldesc(TruncShared& sh, const PRef& U, co
 // panel memory (so every load of a chunk is issued unconditionally).
 __device__ __align__(16) uint32_t hlu_zero_words[4];
 
-// rows [r0, r0 + 64) of both stacked panels into d0 (X side, m rows) and d1
-// (Y side, n rows).  Per side every thread resolves its 16 elements
-// (address, dtype, identity hit, sign) from the column descriptors first,
-// then issues all 32 word loads, then converts and stores: one memory round
-// trip per side and chunk.
+// rows [r0, r0 + 64) of both stacked panels into d0 (X side) and d1 (Y
+// side).  Lane i of wavefront w takes row r0 + i of the stacked columns
+// w + 4u (u = 0..15) of each side.  The descriptors are read four columns at
+// a time, addresses are formed with selects (absent and identity entries
+// read a zero word), and all 32 word loads of a side are in flight before
+// the first is converted: one memory round trip per side and chunk.
 __device__ __forceinline__ void trunc_load2(TruncShared& sh, double (*d0)[KM + 1],
                                             double (*d1)[KM + 1], int r0, int m, int n, int K) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, i = tid & 63, w = tid >> 6;
+  const int row = r0 + i;
   const uint64_t zero = (uint64_t)hlu_zero_words;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    const int rows = side ? n : m;
     double (*d)[KM + 1] = side ? d1 : d0;
-    uint32_t lo[16], hi[16];
-    int flag[16];   // bit 0: FP64, bit 1: identity one, bit 2: negate
+    const uint4* cd = reinterpret_cast<const uint4*>(&sh.cd[side][0]);
+    uint32_t lo[16], hi[16], fl[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = tid + NT * u, i = e & 63, j = e >> 6;   // j is wave-uniform
-      const ColDesc c = sh.cd[side][j < K ? j : 0];
-      const int ii = r0 + i - c.r0;
-      const bool in = j < K && r0 + i < rows && ii >= 0 && ii < c.rows;
-      const bool f64 = c.dt == DT_F64;
-      const bool mem = in && !c.ident;
-      const uint64_t addr =
-          mem ? c.base + (uint64_t)((int64_t)ii * c.stride * (f64 ? 8 : 4)) : zero;
-      lo[u] = *gptr<const uint32_t>(addr);
-      hi[u] = *gptr<const uint32_t>(mem && f64 ? addr + 4 : zero);
-      flag[u] = (f64 ? 1 : 0) | ((in && c.ident && ii == c.irow) ? 2 : 0) | (c.sign < 0 ? 4 : 0);
+    for (int g = 0; g < 4; ++g) {
+      uint4 a[4], b[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = w + 4 * (4 * g + v);
+        const int jj = j < K ? j : 0;
+        a[v] = cd[2 * jj];
+        b[v] = cd[2 * jj + 1];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int u = 4 * g + v, j = w + 4 * u;
+        const uint64_t base0 = (uint64_t)a[v].x | ((uint64_t)a[v].y << 32);
+        const int sb = (int)a[v].z, clo = (int)a[v].w, chi = (int)b[v].x, irow = (int)b[v].y;
+        const uint32_t f = b[v].z;
+        const bool in = j < K && row >= clo && row < chi;
+        const bool mem = in && !(f & 2u);
+        const uint64_t addr = base0 + (uint64_t)((int64_t)row * sb);
+        const uint64_t pl = mem ? addr : zero;
+        const uint64_t ph = (mem && (f & 1u)) ? addr + 4 : zero;
+        lo[u] = *gptr<const uint32_t>(pl);
+        hi[u] = *gptr<const uint32_t>(ph);
+        fl[u] = (f & 5u) | ((in && (f & 2u) && row == irow) ? 2u : 0u) | (j < K ? 8u : 0u);
+      }
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = tid + NT * u, i = e & 63, j = e >> 6;
-      double v = (flag[u] & 1) ? __hiloint2double((int)hi[u], (int)lo[u])
-                               : (double)__int_as_float((int)lo[u]);
-      if (flag[u] & 2) v = 1.0;
-      if (flag[u] & 4) v = -v;
-      if (j < K) d[i][j] = v;
+      double v = (fl[u] & 1u) ? __hiloint2double((int)hi[u], (int)lo[u])
+                              : (double)__int_as_float((int)lo[u]);
+      if (fl[u] & 2u) v = 1.0;
+      if (fl[u] & 4u) v = -v;
+      if (fl[u] & 8u) d[i][w + 4 * u] = v;
     }
+  }
+  (void)m;
+  (void)n;
+}
+
+// Gram tiles of one wavefront: tile t = W, W + 2, ... of the NB (NB + 1) / 2
+// 16 x 16 tiles on and above the diagonal, numbered row by row.  Each step
+// of four rows reads the NB column blocks once and feeds the independent
+// tiles back to back.
+constexpr int gram_tile_row(int nb, int t) {
+  int a = 0;
+  while (t >= nb - a) {
+    t -= nb - a;
+    ++a;
+  }
+  return a;
+}
+constexpr int gram_tile_col(int nb, int t) {
+  int a = 0;
+  while (t >= nb - a) {
+    t -= nb - a;
+    ++a;
+  }
+  return a + t;
+}
+template <int NB, int W, int J>
+__device__ __forceinline__ void gram_step(const double (&cv)[NB], v4d (&acc)[5]) {
+  if constexpr (J < 5 && W + 2 * J < NB * (NB + 1) / 2) {
+    constexpr int t = W + 2 * J;
+    constexpr int a = gram_tile_row(NB, t), b = gram_tile_col(NB, t);
+    acc[J] = mfma16x16x4(cv[a], cv[b], acc[J]);
+    gram_step<NB, W, J + 1>(cv, acc);
+  }
+}
+template <int NB, int W>
+__device__ __forceinline__ void gram_tiles(double (*C)[KM + 1], int nq, v4d (&acc)[5]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll 2
+  for (int q = 0; q < nq; ++q) {
+    const int i = 4 * q + (l >> 4);
+    double cv[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) cv[c] = C[i][16 * c + (l & 15)];
+    gram_step<NB, W, 0>(cv, acc);
   }
 }
 
@@ -1125,17 +1186,6 @@ __device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K
   double (*C)[KM + 1] = side ? sh.gy : sh.m;
   double (*G)[KM + 1] = side ? sh.gy : sh.gx;
   const int nb = (K + 15) >> 4, ntile = nb * (nb + 1) / 2;
-  int ta[5], tb[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    int a = 0, b = w + 2 * j;
-    while (a < nb && b >= nb - a) {
-      b -= nb - a;
-      ++a;
-    }
-    ta[j] = 16 * a;
-    tb[j] = 16 * (a + b);
-  }
   v4d acc[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -1144,26 +1194,30 @@ __device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K
     trunc_load2(sh, sh.m, sh.gy, r0, m, n, K);
     __syncthreads();
     const int nq = min(16, (rows_side - r0 + 3) >> 2);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      if (w + 2 * j < ntile) {
-        for (int q = 0; q < nq; ++q) {
-          const int i = 4 * q + (l >> 4);
-          acc[j] = mfma16x16x4(C[i][ta[j] + (l & 15)], C[i][tb[j] + (l & 15)], acc[j]);
-        }
-      }
+    switch (nb * 2 + w) {
+      case 2: gram_tiles<1, 0>(C, nq, acc); break;
+      case 3: gram_tiles<1, 1>(C, nq, acc); break;
+      case 4: gram_tiles<2, 0>(C, nq, acc); break;
+      case 5: gram_tiles<2, 1>(C, nq, acc); break;
+      case 6: gram_tiles<3, 0>(C, nq, acc); break;
+      case 7: gram_tiles<3, 1>(C, nq, acc); break;
+      case 8: gram_tiles<4, 0>(C, nq, acc); break;
+      case 9: gram_tiles<4, 1>(C, nq, acc); break;
+      default: break;
     }
     __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    if (w + 2 * j < ntile) {
+    const int t = w + 2 * j;
+    if (t < ntile) {
+      const int ta = 16 * gram_tile_row(nb, t), tb = 16 * gram_tile_col(nb, t);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = ta[j] + (l >> 4) + 4 * r, b = tb[j] + (l & 15);
+        const int a = ta + (l >> 4) + 4 * r, b = tb + (l & 15);
         if (a < K && b < K) {
           G[a][b] = acc[j][r];
-          if (ta[j] != tb[j]) G[b][a] = acc[j][r];
+          if (ta != tb) G[b][a] = acc[j][r];
         }
       }
     }
@@ -1284,12 +1338,36 @@ __device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int 
 
 // new rows of U (threads 0-127, Tx in m) and V (threads 128-255, Ty in gy),
 // chunks staged in gx / z
+// out^T tiles of one wavefront in the factor update: row blocks W and W + 2
+// of the chunk, NCT column blocks; each step of four stacked columns reads
+// the two row blocks of C and the NCT column blocks of T once.
+template <int NCT>
+__device__ __forceinline__ void apply_tiles(double (*C)[KM + 1], double (*T)[KM + 1], int K,
+                                            int w, v4d (&acc)[2][2]) {
+  const int l = threadIdx.x & 63;
+  const int nq = (K + 3) >> 2;
+#pragma unroll 2
+  for (int q = 0; q < nq; ++q) {
+    const int kk = 4 * q + (l >> 4);
+    const bool in = kk < K;
+    double cv[2], tv[NCT];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) cv[u] = in ? C[16 * (w + 2 * u) + (l & 15)][kk] : 0.0;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) tv[c] = in ? T[kk][16 * c + (l & 15)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) acc[u][c] = mfma16x16x4(tv[c], cv[u], acc[u][c]);
+  }
+}
+
 __device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, const PRef& V, int m,
                                              int n, int K, int k) {
   // per side and row chunk: out (64 x k) = C (64 x K) T (K x k), taken
   // transposed on the matrix cores (out^T = T^T C^T) so that the sixteen
   // lanes of a result register hold consecutive rows; the side's two
-  // wavefronts share the 16 x 16 tiles
+  // wavefronts take alternate 16-row blocks
   const int tid = threadIdx.x;
   const int side = tid >> 7, w = (tid >> 6) & 1, l = tid & 63;
   const int rows_side = side ? n : m;
@@ -1297,33 +1375,36 @@ __device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, con
   double (*T)[KM + 1] = side ? sh.gy : sh.m;
   const GView g = gview(side ? V : U);
   const int rows = max(m, n);
-  const int ntile = 4 * ((k + 15) >> 4), nq = (K + 3) >> 2;
+  const int nct = (k + 15) >> 4;
   for (int r0 = 0; r0 < rows; r0 += 64) {
     trunc_load2(sh, sh.gx, sh.z, r0, m, n, K);
     __syncthreads();
     const int h = rows_side - r0;
-    for (int tt = w; tt < ntile; tt += 2) {
-      const int i0 = 16 * (tt & 3), c0 = 16 * (tt >> 2);
-      if (i0 >= h) continue;
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-      for (int q = 0; q < nq; ++q) {
-        const int kk = 4 * q + (l >> 4);
-        const double a = kk < K ? T[kk][c0 + (l & 15)] : 0.0;
-        const double b = kk < K ? C[i0 + (l & 15)][kk] : 0.0;
-        acc = mfma16x16x4(a, b, acc);
-      }
-      int ri[4], cj[4];
-      bool ok[4];
-      double o[4];
+    if (h > 0 && nct > 0) {
+      v4d acc[2][2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = i0 + (l & 15), col = c0 + (l >> 4) + 4 * r;
-        ok[r] = row < h && col < k;
-        ri[r] = r0 + min(row, h - 1);
-        cj[r] = min(col, k - 1);
-        o[r] = acc[r];
-      }
-      gstore(g, ri, cj, ok, o);
+      for (int u = 0; u < 2; ++u) acc[u][0] = acc[u][1] = (v4d){0.0, 0.0, 0.0, 0.0};
+      if (nct == 1) apply_tiles<1>(C, T, K, w, acc);
+      else apply_tiles<2>(C, T, K, w, acc);
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (c < nct && 16 * (w + 2 * u) < h) {
+            int ri[4], cj[4];
+            bool ok[4];
+            double o[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * (w + 2 * u) + (l & 15), col = 16 * c + (l >> 4) + 4 * r;
+              ok[r] = row < h && col < k;
+              ri[r] = r0 + min(row, h - 1);
+              cj[r] = min(col, k - 1);
+              o[r] = acc[u][c][r];
+            }
+            gstore(g, ri, cj, ok, o);
+          }
+        }
     }
     __syncthreads();
   }
