@@ -1576,33 +1576,35 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
     __syncthreads();
     const int rx = __builtin_amdgcn_readfirstlane(sh.rx);
     const int ry = __builtin_amdgcn_readfirstlane(sh.ry);
-    // 4. M = R S^T (rows and columns in pivot order), |M|_F^2
+    // 4. M = R S^T (rows and columns in pivot order), |M|_F^2: 16 x 16 tiles
+    // covering rx x ry on the matrix cores (wavefront w takes tiles w, w + 4,
+    // ...), zeros everywhere else in the 64 x 64 buffer
     double msq = 0.0;
     {
-      const int ti = tid % 16, tj = tid / 16;
-      double acc[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-      for (int c = 0; c < K; ++c) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) av[u] = ti + 16 * u < rx ? sh.gx[ti + 16 * u][c] : 0.0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) bv[v] = tj + 16 * v < ry ? sh.gy[tj + 16 * v][c] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      const int l = tid & 63;
+      const int nbx = (rx + 15) >> 4, nby = (ry + 15) >> 4, nq = (K + 3) >> 2;
+      for (int e = tid; e < KM * KM; e += NT) {
+        const int i = e & 63, p = e >> 6;
+        if (i >= 16 * nbx || p >= 16 * nby) sh.m[i][jphys(p)] = 0.0;
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          sh.m[ti + 16 * u][jphys(tj + 16 * v)] = acc[u][v];
-          msq += acc[u][v] * acc[u][v];
+      for (int t = wid; t < nbx * nby; t += 4) {
+        const int i0 = 16 * (t % nbx), j0 = 16 * (t / nbx);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < nq; ++q) {
+          const int c = 4 * q + (l >> 4);
+          const bool in = c < K;
+          const double a = in ? sh.gx[i0 + (l & 15)][c] : 0.0;
+          const double b = in ? sh.gy[j0 + (l & 15)][c] : 0.0;
+          acc = mfma16x16x4(a, b, acc);
         }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + (l >> 4) + 4 * r, j = j0 + (l & 15);
+          const double v = (i < rx && j < ry) ? acc[r] : 0.0;
+          sh.m[i][jphys(j)] = v;
+          msq += v * v;
+        }
+      }
     }
     const double ms = block_sum(sh, msq);
     // 4b. for a tolerance-driven truncation, shrink the SVD to the part of M
@@ -1617,28 +1619,29 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
     double tail0 = 0.0;
     if (fixed == 0 && eps >= 1e-6 && rx > 8 && ry > 8) {
       {
-        const int ti = tid % 16, tj = tid / 16;
-        double acc[4][4];
+        // G = M M^T (rx x rx): tiles on and above the diagonal, mirrored
+        const int l = tid & 63;
+        const int nb = (rx + 15) >> 4, ntl = nb * (nb + 1) / 2, nq = (ry + 3) >> 2;
+        for (int t = wid; t < ntl; t += 4) {
+          const int a0 = 16 * gram_tile_row(nb, t), b0 = 16 * gram_tile_col(nb, t);
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+          for (int q = 0; q < nq; ++q) {
+            const int j = 4 * q + (l >> 4);
+            const bool in = j < ry;
+            const int fj = jphys(min(j, KM - 1));
+            const double a = in ? sh.m[a0 + (l & 15)][fj] : 0.0;
+            const double b = in ? sh.m[b0 + (l & 15)][fj] : 0.0;
+            acc = mfma16x16x4(a, b, acc);
+          }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-        for (int j = 0; j < ry; ++j) {
-          const int fj = jphys(j);
-          double av[4], bv[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) av[u] = sh.m[ti + 16 * u][fj];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) bv[v] = sh.m[tj + 16 * v][fj];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+          for (int r = 0; r < 4; ++r) {
+            const int a = a0 + (l >> 4) + 4 * r, b = b0 + (l & 15);
+            if (a < rx && b < rx) {
+              sh.gy[a][b] = acc[r];
+              if (a0 != b0) sh.gy[b][a] = acc[r];
+            }
+          }
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) sh.gy[ti + 16 * u][tj + 16 * v] = acc[u][v];
       }
       __syncthreads();
       if (wid == 0)
