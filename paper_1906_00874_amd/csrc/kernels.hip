@@ -1306,11 +1306,17 @@ __device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int 
   }
   for (int i = rx - 1; i >= 0; --i) {
     const int pi = sh.px[i];
+    const double ri = sh.rinv[i];
+    // the column of R this step needs, read before the broadcast (straight
+    // line: a branch per entry would serialise the reads)
+    double gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) gv[u] = sh.gx[l + 8 * u][pi];
     const int lo = i & 7, uo = i >> 3;
     double own = 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) own = u == uo ? v[u] : own;
-    own = l == lo ? own * sh.rinv[i] : 0.0;
+    own = l == lo ? own * ri : 0.0;
     // broadcast the owner's value within the eight lanes (a sum of zeros
     // and one value is exact)
     double xi = own;
@@ -1320,8 +1326,7 @@ __device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = l + 8 * u;
-      if (t == i) v[u] = xi;
-      else if (t < i) v[u] -= sh.gx[t][pi] * xi;
+      v[u] = t == i ? xi : (t < i ? v[u] - gv[u] * xi : v[u]);
     }
   }
   if (act) {
@@ -1423,9 +1428,10 @@ __device__ __forceinline__ int jphys(int p) { return ((p & 7) << 3) | (p >> 3); 
 // lanes handles one pair, each lane at most 8 rows of both columns in
 // registers.  Squared column norms (by position) are recomputed at every
 // sweep and carried through the rotations in between, so a round reduces
-// one inner product.  Returns the buffer holding the result (0: m, 1: gy).
+// one inner product.  Sweeps stop once no pair had a squared cosine above
+// stop.  Returns the buffer holding the result (0: m, 1: gy).
 __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, double ms,
-                                            int& sweeps) {
+                                            double stop, int& sweeps) {
   const int tid = threadIdx.x;
   const int ncol = ry + (ry & 1);
   sweeps = 0;
@@ -1504,8 +1510,7 @@ __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, dou
       cur ^= 1;
     }
     ++sweeps;
-    // stop once no pair had a cosine above 1e-12
-    if (!(block_max(sh, mu) > 1e-24)) break;
+    if (!(block_max(sh, mu) > stop)) break;
   }
   return cur;
 }
@@ -1657,8 +1662,12 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
       }
       __syncthreads();
     }
+    // rotations stop at a cosine of 1e-3 eps (at most 1e-12): the singular
+    // values then carry relative errors of order (1e-3 eps)^2, far below the
+    // tolerance the rank rule resolves
     int sweeps;
-    double (*MF)[KM + 1] = trunc_jacobi(sh, rx, jc, ms, sweeps) ? sh.gy : sh.m;
+    const double jstop = fixed == 0 ? fmax(1e-24, 1e-6 * eps * eps) : 1e-24;
+    double (*MF)[KM + 1] = trunc_jacobi(sh, rx, jc, ms, jstop, sweeps) ? sh.gy : sh.m;
     passes += 1;
     sweeps_all += sweeps;
     rxmax = max(rxmax, rx);

@@ -864,10 +864,12 @@ class Builder {
 
   // ---- solve updates as an H-matvec: Y[rows of M] -= M X for a block node M
   // off the diagonal.  First T_b := V_b^T X[cols of b] for every low-rank leaf
-  // block b of M (one op each, all independent); then one op per leaf
-  // cluster r of M's rows subtracting every contribution U_b[r] T_b and
-  // F_b[r] X[cols of b] in a fixed order.  Contributions to one row cluster
-  // are summed inside one op instead of being chained op after op.
+  // block b of M (one op each, all independent); then, per leaf cluster r of
+  // M's rows, the contributions U_b[r] T_b and F_b[r] X[cols of b] summed in
+  // a fixed order by two ops: the first takes the blocks whose columns avoid
+  // the column leaf the sweep solves last (ready before it, off the sweep's
+  // chain), the second the blocks that touch it (usually one small block
+  // next to the diagonal).
   bool solve_mv = false;
   std::vector<int> Tobj;     // per block: object of its V^T X slot
   // solve: per leaf cluster, the last emitted row-update op on its rows
@@ -899,7 +901,7 @@ class Builder {
     v.dt = DT_F64;
     return v;
   }
-  void hupd(const PV& Y, int nb, const PV& X) {
+  void hupd(const PV& Y, int nb, const PV& X, bool backward) {
     if ((int)Tobj.size() < (int)P.blk.size()) Tobj.assign(P.blk.size(), -1);
     std::vector<int> lv;
     block_leaves(nb, lv);
@@ -919,59 +921,68 @@ class Builder {
     }
     std::vector<int> rows;
     cluster_leaves(node(nb).t, rows);
+    // the column leaf this sweep solves last among M's columns
+    const Cluster& cc = P.cl[node(nb).s];
+    const int last_leaf = backward ? cc.first_leaf : cc.first_leaf + cc.nleaves - 1;
     for (int r : rows) {
       const Cluster& rc = P.cl[r];
-      Op op = blank(OP_MVROW);
       PV Yr = sub(Y, r);
-      op.p[3] = ref(Yr);
-      op.d0 = -1.0;
-      op.i0 = (int)S.terms.size();
-      std::vector<Acc> acc = {acc_of(Yr, true), racc(Yr)};
-      for (int bn : lv) {
-        const BNode& M = node(bn);
-        const Cluster& tc = P.cl[M.t];
-        if (rc.first_leaf < tc.first_leaf || rc.first_leaf >= tc.first_leaf + tc.nleaves) continue;
-        const LBlock& B = P.blk[M.blk];
-        Term t;
-        std::memset(&t, 0, sizeof(t));
-        if (M.kind == 'R') {
-          t.X = ref(sub(u_panel(M.blk), r));
-          t.Y = ref(tslot(M.blk, X.cols));
-          acc.push_back(whole(B.objU, false));
-          acc.push_back(whole(B.objRank, false));
-          acc.push_back(whole(Tobj[M.blk], false));
-          S.terms.push_back(t);
-        } else {
-          // a dense leaf may be wider than 64 (a leaf cluster against a
-          // larger one): one term per window of at most 64 columns
-          PV Xs = sub(X, M.s);
-          PV Fr = sub(dense_panel(M.blk), r);
-          for (int c0 = 0; c0 < B.n; c0 += 64) {
-            const int w = std::min(64, B.n - c0);
-            PV xw = Xs;
-            xw.off = Xs.off + (uint64_t)c0 * 8;   // rows c0.. of the FP64 vector panel
-            xw.rows = w;
-            t.X = ref(colwin(Fr, c0, w));
-            t.Y = ref(xw);
+      for (int late = 0; late < 2; ++late) {
+        Op op = blank(OP_MVROW);
+        op.p[3] = ref(Yr);
+        op.d0 = -1.0;
+        op.i0 = (int)S.terms.size();
+        std::vector<Acc> acc = {acc_of(Yr, true), racc(Yr)};
+        for (int bn : lv) {
+          const BNode& M = node(bn);
+          const Cluster& tc = P.cl[M.t];
+          if (rc.first_leaf < tc.first_leaf || rc.first_leaf >= tc.first_leaf + tc.nleaves)
+            continue;
+          const Cluster& sc = P.cl[M.s];
+          const bool touches = last_leaf >= sc.first_leaf && last_leaf < sc.first_leaf + sc.nleaves;
+          if (touches != (late == 1)) continue;
+          const LBlock& B = P.blk[M.blk];
+          Term t;
+          std::memset(&t, 0, sizeof(t));
+          if (M.kind == 'R') {
+            t.X = ref(sub(u_panel(M.blk), r));
+            t.Y = ref(tslot(M.blk, X.cols));
+            acc.push_back(whole(B.objU, false));
+            acc.push_back(whole(B.objRank, false));
+            acc.push_back(whole(Tobj[M.blk], false));
             S.terms.push_back(t);
+          } else {
+            // a dense leaf may be wider than 64 (a leaf cluster against a
+            // larger one): one term per window of at most 64 columns
+            PV Xs = sub(X, M.s);
+            PV Fr = sub(dense_panel(M.blk), r);
+            for (int c0 = 0; c0 < B.n; c0 += 64) {
+              const int w = std::min(64, B.n - c0);
+              PV xw = Xs;
+              xw.off = Xs.off + (uint64_t)c0 * 8;   // rows c0.. of the FP64 vector panel
+              xw.rows = w;
+              t.X = ref(colwin(Fr, c0, w));
+              t.Y = ref(xw);
+              S.terms.push_back(t);
+            }
+            acc.push_back(whole(B.objF, false));
+            acc.push_back(acc_of(Xs, false));
           }
-          acc.push_back(whole(B.objF, false));
-          acc.push_back(acc_of(Xs, false));
+        }
+        // at most 256 terms per op (the row kernel's table); longer lists
+        // become several ops on the same rows, ordered by their writes
+        const int tend = (int)S.terms.size();
+        for (int t0 = op.i0; t0 < tend; t0 += 256) {
+          Op o2 = op;
+          o2.i0 = t0;
+          o2.i1 = std::min(256, tend - t0);
+          emit(o2, acc);
+          // the last op writing this leaf row (the leaf's inverse may be
+          // fused into it)
+          if ((int)last_row_op.size() < (int)P.cl.size()) last_row_op.assign(P.cl.size(), -1);
+          last_row_op[r] = (int)ops.size() - 1;
         }
       }
-      // at most 256 terms per op (the row kernel's table); longer lists
-      // become several ops on the same rows, ordered by their writes
-      const int tend = (int)S.terms.size();
-      for (int t0 = op.i0; t0 < tend; t0 += 256) {
-        Op o2 = op;
-        o2.i0 = t0;
-        o2.i1 = std::min(256, tend - t0);
-        emit(o2, acc);
-      }
-      // the last op writing this leaf row (the leaf's inverse may be fused
-      // into it)
-      if ((int)last_row_op.size() < (int)P.cl.size()) last_row_op.assign(P.cl.size(), -1);
-      last_row_op[r] = (int)ops.size() - 1;
     }
   }
 
@@ -986,7 +997,7 @@ class Builder {
     int t0 = P.cl[L.t].son[0], t1 = P.cl[L.t].son[1];
     PV Y0 = sub(Y, t0), Y1 = sub(Y, t1);
     fwd(son(nb, 0, 0), Y0);
-    if (solve_mv) hupd(Y1, son(nb, 1, 0), Y0);
+    if (solve_mv) hupd(Y1, son(nb, 1, 0), Y0, false);
     else pmul(Y1, son(nb, 1, 0), Y0, -1.0, false);
     fwd(son(nb, 1, 1), Y1);
   }
@@ -1011,7 +1022,7 @@ class Builder {
     int t0 = P.cl[U.t].son[0], t1 = P.cl[U.t].son[1];
     PV Y0 = sub(Y, t0), Y1 = sub(Y, t1);
     bwd(son(nb, 1, 1), Y1);
-    if (solve_mv) hupd(Y0, son(nb, 0, 1), Y1);
+    if (solve_mv) hupd(Y0, son(nb, 0, 1), Y1, true);
     else pmul(Y0, son(nb, 0, 1), Y1, -1.0, false);
     bwd(son(nb, 0, 0), Y0);
   }
