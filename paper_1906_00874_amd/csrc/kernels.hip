@@ -1928,25 +1928,25 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   // right-hand sides in groups of 32 (one group when nrhs <= 32)
   // chunk `item` (16 columns of one term) of the A panel (lane = row) and of
   // the B panel (lane = right-hand side h0 + lane) into registers
+  // Lanes beyond the rows or right-hand sides and columns beyond kc read a
+  // clamped element: their products land only in outputs that are never
+  // stored, so nothing is zeroed and all 32 loads are issued together.
   auto fetch = [&](int item, int h0, int nh, double (&ra)[16], double (&rb)[16], int& kc) {
     int t, c0;
     locate(item, t, c0);
     const Term& tp = st[t];
     kc = min(16, kk[t] - c0);
-    const int lda = tp.X.ld, ldb = tp.Y.ld;
-    if (tp.X.dt == DT_F64) {
-      const HLU_G double* pa = gptr<const double>(tp.X.ptr) + lane + (size_t)c0 * lda;
+    int ri[16], cj[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) ra[u] = (lane < rows && u < kc) ? pa[(size_t)u * lda] : 0.0;
-    } else {
-      const HLU_G float* pa = gptr<const float>(tp.X.ptr) + lane + (size_t)c0 * lda;
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        ra[u] = (lane < rows && u < kc) ? (double)pa[(size_t)u * lda] : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      ri[u] = min(lane, rows - 1);
+      cj[u] = c0 + min(u, kc - 1);
     }
-    const HLU_G double* pb = gptr<const double>(tp.Y.ptr) + c0 + (size_t)(h0 + lane) * ldb;
+    gload(gview(tp.X), ri, cj, ra);
+    const HLU_G double* pb =
+        gptr<const double>(tp.Y.ptr) + (size_t)(h0 + min(lane, nh - 1)) * tp.Y.ld;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) rb[u] = (lane < nh && u < kc) ? pb[u] : 0.0;
+    for (int u = 0; u < 16; ++u) rb[u] = pb[cj[u]];
   };
   for (int h0 = 0; h0 < nr; h0 += 32) {
     const int nh = min(32, nr - h0);
@@ -2009,32 +2009,27 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     __syncthreads();
   }
   if (fused) {
-    // p3 := W (updated rows), 16 x 16 threads with 4 x 4 outputs each
-    const int ti = tid % 16, tj = tid / 16;
-    double acc[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    for (int k = 0; k < rows; ++k) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = sw[ti + 16 * u][k];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = sy[k][tj + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-    }
+    // p3 := W (updated rows) on the matrix cores, taken transposed
+    // ((W S)^T = S^T W^T) so that the sixteen lanes of a result register
+    // hold consecutive rows; 16 x 16 tiles dealt to the four wavefronts
+    const int ntj = (nr + 15) >> 4, nq = (rows + 3) >> 2;
     HLU_G double* gy = gptr<double>(Y.ptr);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = ti + 16 * u, j = tj + 16 * v;
-        if (i < rows && j < nr) gy[i + (size_t)j * Y.ld] = acc[u][v];
+    for (int t = w; t < 4 * ntj; t += 4) {
+      const int i0 = 16 * (t & 3), j0 = 16 * (t >> 2);
+      if (i0 >= rows) continue;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < nq; ++q) {
+        const int k = 4 * q + (lane >> 4);
+        const double a = k < rows ? sy[k][j0 + (lane & 15)] : 0.0;
+        const double b = sw[i0 + (lane & 15)][k];
+        acc = mfma16x16x4(a, b, acc);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + (lane & 15), j = j0 + (lane >> 4) + 4 * r;
+        if (i < rows && j < nr) gy[i + (size_t)j * Y.ld] = acc[r];
+      }
+    }
   }
   if (tid == 0 && op.cost) {
     double fl = fused ? 2.0 * rows * rows * nr : 0.0;
