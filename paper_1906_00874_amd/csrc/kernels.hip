@@ -1792,12 +1792,14 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
   const int n = V.rows, k = pcols(V), nr = pcols(X);
   double (*sv)[65] = reinterpret_cast<double (*)[65]>(smem);
   double (*sx)[65] = reinterpret_cast<double (*)[65]>(smem + 32 * 65 * 8);
-  const int tid = threadIdx.x, ti = tid % 16, tj = tid / 16;
-  double acc[4][4];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  // T^T = X^T V on the matrix cores (the sixteen lanes of a result register
+  // then hold consecutive rows of T): 16 x 16 tiles over (nrhs, k), tile
+  // w + 4j to wavefront w
+  const int nta = (k + 15) >> 4, ntile = nta * ((nr + 15) >> 4);
+  v4d acc[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int j = 0; j < 4; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
   double pv[8], px[8];
   const GView gv = gview(V), gx = gview(X);
   // loads only: lanes outside V or X read a clamped element and are zeroed
@@ -1826,28 +1828,33 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
     }
     __syncthreads();
     if (r0 + 32 < nn) fetch(r0 + 32);
-    const int d = min(32, n - r0);
-    for (int i = 0; i < d; ++i) {
-      double av[4], bv[4];
+    const int nq = (min(32, n - r0) + 3) >> 2;   // rows beyond n are zero
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = sv[i][ti + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = sx[i][tj + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+    for (int j = 0; j < 4; ++j) {
+      const int tt = w + 4 * j;
+      if (tt < ntile) {
+        const int a0 = 16 * (tt % nta), b0 = 16 * (tt / nta);
+        for (int q = 0; q < nq; ++q) {
+          const int i = 4 * q + (l >> 4);
+          acc[j] = mfma16x16x4(sx[i][b0 + (l & 15)], sv[i][a0 + (l & 15)], acc[j]);
+        }
+      }
     }
     __syncthreads();
   }
   HLU_G double* t = gptr<double>(T.ptr);
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int j = 0; j < 4; ++j) {
+    const int tt = w + 4 * j;
+    if (tt < ntile) {
+      const int a0 = 16 * (tt % nta), b0 = 16 * (tt / nta);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = ti + 16 * u, b = tj + 16 * v;
-      if (a < k && b < nr) t[a + (size_t)b * T.ld] = acc[u][v];
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + (l & 15), b = b0 + (l >> 4) + 4 * r;
+        if (a < k && b < nr) t[a + (size_t)b * T.ld] = acc[j][r];
+      }
     }
+  }
   const double es = V.dt == DT_F64 ? 8.0 : 4.0;
   put_cost(op, 2.0 * n * k * nr, es * n * k + 8.0 * n * nr + 8.0 * k * nr);
 }
@@ -1950,6 +1957,14 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   };
   for (int h0 = 0; h0 < nr; h0 += 32) {
     const int nh = min(32, nr - h0);
+    // the old values of the rows (wavefront 0), in flight while the terms
+    // are multiplied; lanes beyond the rows read a clamped element
+    double yv[32];
+    if (w == 0) {
+      const HLU_G double* y = gptr<const double>(Y.ptr) + min(lane, rows - 1) + (size_t)h0 * Y.ld;
+#pragma unroll
+      for (int v = 0; v < 32; ++v) yv[v] = y[(size_t)min(v, nh - 1) * Y.ld];
+    }
     double o[32];
 #pragma unroll
     for (int v = 0; v < 32; ++v) o[v] = 0.0;
@@ -1993,9 +2008,6 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     __syncthreads();
     if (w == 0 && lane < rows) {
       HLU_G double* y = gptr<double>(Y.ptr) + lane + (size_t)h0 * Y.ld;
-      double yv[32];
-#pragma unroll
-      for (int v = 0; v < 32; ++v) yv[v] = v < nh ? y[(size_t)v * Y.ld] : 0.0;
       if (fused) {
 #pragma unroll
         for (int v = 0; v < 32; ++v)
