@@ -2109,35 +2109,97 @@ __global__ void __launch_bounds__(NT) k_mv_t(const MvLR* __restrict__ lr, const 
 }
 
 // y[rows of leaf] = beta * b + alpha * sum over the leaf row's blocks (F X or
-// U T): (0, 1) gives y = A X, (1, -1) the residual b - A X.
+// U T): (0, 1) gives y = A X, (1, -1) the residual b - A X.  Lane i holds row
+// i for 32 right-hand sides at a time and the four wavefronts take alternate
+// columns of every block, so each matrix entry is read once; the slices of X
+// (or T) for 64 columns at a time are staged in LDS and read as broadcasts,
+// and the four partial sums meet in LDS at the end.
 __global__ void __launch_bounds__(NT) k_mv_rows(const MvRow* __restrict__ rows,
                                                 const MvTerm* __restrict__ terms,
                                                 const double* X, int ldx, const double* B,
                                                 double beta, double alpha, double* Yo,
                                                 int nrhs) {
   const MvRow r = rows[blockIdx.x];
-  const int tid = threadIdx.x;
-  for (int c0 = 0; c0 < nrhs; c0 += 4) {
-    // each thread: row i = tid % 64, column c0 + tid / 64
-    const int i = tid % 64, j = c0 + tid / 64;
-    double acc = 0.0;
-    const bool act = i < r.rows && j < nrhs;
+  __shared__ __align__(16) double sx[64][34];
+  __shared__ double red[2][64][33];
+  const int tid = threadIdx.x, i = tid & 63, g = tid >> 6;
+  if (r.rows <= 0) return;
+  const int ir = min(i, r.rows - 1);
+  const HLU_G double* gx = gptr<const double>((uint64_t)X);
+  for (int h0 = 0; h0 < nrhs; h0 += 32) {
+    const int nh = min(32, nrhs - h0);
+    double acc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
     for (int q = 0; q < r.nt; ++q) {
       const MvTerm t = terms[r.t0 + q];
-      const HLU_G double* A = gptr<const double>(t.A);
-      if (!act) continue;
-      if (t.T == 0) {
-        const double* x = X + (size_t)j * ldx + t.c0;
-        for (int c = 0; c < t.ncol; ++c) acc += A[(t.roff + i) + (size_t)c * t.lda] * x[c];
-      } else {
-        const HLU_G double* T = gptr<const double>(t.T) + (size_t)j * t.c0;
-        for (int c = 0; c < t.ncol; ++c) acc += A[(t.roff + i) + (size_t)c * t.lda] * T[c];
+      const HLU_G double* A = gptr<const double>(t.A) + t.roff + ir;
+      for (int cc = 0; cc < t.ncol; cc += 64) {
+        const int nc = min(64, t.ncol - cc);
+        {
+          // sx[c][j] = X[c0 + cc + c][h0 + j] (dense) or T[cc + c][h0 + j]
+          // (low rank); lanes beyond nc or nh read a clamped element that no
+          // product uses
+          const int cl = cc + min(i, nc - 1);
+          double v[8];
+          if (t.T == 0) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              v[u] = gx[(size_t)(t.c0 + cl) + (size_t)(h0 + min(g + 4 * u, nh - 1)) * ldx];
+          } else {
+            const HLU_G double* T = gptr<const double>(t.T);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              v[u] = T[(size_t)cl + (size_t)(h0 + min(g + 4 * u, nh - 1)) * t.c0];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sx[i][g + 4 * u] = v[u];
+        }
+        __syncthreads();
+        for (int c = g; c < nc; c += 16) {
+          double a[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[u] = A[(size_t)(cc + min(c + 4 * u, nc - 1)) * t.lda];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (c + 4 * u < nc) {
+              const double* xr = &sx[c + 4 * u][0];
+              double xv[32];
+#pragma unroll
+              for (int j = 0; j < 32; ++j) xv[j] = xr[j];
+#pragma unroll
+              for (int j = 0; j < 32; ++j) acc[j] += a[u] * xv[j];
+            }
+          }
+        }
+        __syncthreads();
       }
     }
-    if (act) {
-      size_t o = (size_t)(r.r0 + i) + (size_t)j * ldx;
-      Yo[o] = beta * (B ? B[o] : 0.0) + alpha * acc;
+    if (g >= 2) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) red[g - 2][i][j] = acc[j];
     }
+    __syncthreads();
+    if (g < 2) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) acc[j] += red[g][i][j];
+    }
+    __syncthreads();
+    if (g == 1) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) red[0][i][j] = acc[j];
+    }
+    __syncthreads();
+    if (g == 0 && i < r.rows) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        if (j < nh) {
+          const size_t o = (size_t)(r.r0 + i) + (size_t)(h0 + j) * ldx;
+          Yo[o] = beta * (B ? B[o] : 0.0) + alpha * (acc[j] + red[0][i][j]);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
