@@ -2056,54 +2056,75 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
 }
 
 // ---------------------------------------------------------------- matvec
-// T_b = V_b^T X[c0:c0+n, :] for every low-rank block b of the matvec copy.
+// T_b = V_b^T X[c0:c0+n, :] for every low-rank block b of the matvec copy:
+// rows in chunks of 32, the next chunk loading while the current one is
+// multiplied; T^T = X^T V on the matrix cores (16 x 16 tiles over the
+// right-hand sides and the rank, tile w + 4j to wavefront w).
 __global__ void __launch_bounds__(NT) k_mv_t(const MvLR* __restrict__ lr, const double* X,
                                              int ldx, int nrhs) {
   const MvLR e = lr[blockIdx.x];
-  if (e.k == 0) return;
+  if (e.k == 0 || e.n <= 0) return;
   const HLU_G double* V = gptr<const double>(e.V);
+  const HLU_G double* gx = gptr<const double>((uint64_t)X);
   HLU_G double* T = gptr<double>(e.T);
   __shared__ double sv[32][65];
   __shared__ double sx[32][65];
-  const int tid = threadIdx.x;
-  const int ti = tid % 16, tj = tid / 16;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   for (int k0 = 0; k0 < e.k; k0 += 64) {
     const int kk = min(64, e.k - k0);
     for (int c0 = 0; c0 < nrhs; c0 += 64) {
-      const int w = min(64, nrhs - c0);
-      double acc[4][4];
+      const int wc = min(64, nrhs - c0);
+      const int nta = (kk + 15) >> 4, ntile = nta * ((wc + 15) >> 4);
+      v4d acc[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int j = 0; j < 4; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
+      double pv[8], px[8];
+      auto fetch = [&](int r0) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int u = 0; u < 8; ++u) {
+          const int q = tid + NT * u, i = q & 31, j = q >> 5;
+          const int row = min(r0 + i, e.n - 1);
+          pv[u] = V[(size_t)row + (size_t)(k0 + min(j, kk - 1)) * e.n];
+          px[u] = gx[(size_t)(e.c0 + row) + (size_t)(c0 + min(j, wc - 1)) * ldx];
+        }
+      };
+      fetch(0);
       for (int r0 = 0; r0 < e.n; r0 += 32) {
-        const int d = min(32, e.n - r0);
-        for (int q = tid; q < 32 * 64; q += NT) {
-          int i = q % 32, j = q / 32;
-          sv[i][j] = (i < d && j < kk) ? V[(r0 + i) + (size_t)(k0 + j) * e.n] : 0.0;
-          sx[i][j] = (i < d && j < w) ? X[(e.c0 + r0 + i) + (size_t)(c0 + j) * ldx] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int q = tid + NT * u, i = q & 31, j = q >> 5;
+          const bool in = r0 + i < e.n;
+          sv[i][j] = (in && j < kk) ? pv[u] : 0.0;
+          sx[i][j] = (in && j < wc) ? px[u] : 0.0;
         }
         __syncthreads();
-        for (int i = 0; i < d; ++i) {
-          double av[4], bv[4];
+        if (r0 + 32 < e.n) fetch(r0 + 32);
+        const int nq = (min(32, e.n - r0) + 3) >> 2;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) av[u] = sv[i][ti + 16 * u];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) bv[v] = sx[i][tj + 16 * v];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        for (int j = 0; j < 4; ++j) {
+          const int tt = w + 4 * j;
+          if (tt < ntile) {
+            const int a0 = 16 * (tt % nta), b0 = 16 * (tt / nta);
+            for (int q = 0; q < nq; ++q) {
+              const int i = 4 * q + (l >> 4);
+              acc[j] = mfma16x16x4(sx[i][b0 + (l & 15)], sv[i][a0 + (l & 15)], acc[j]);
+            }
+          }
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int j = 0; j < 4; ++j) {
+        const int tt = w + 4 * j;
+        if (tt < ntile) {
+          const int a0 = 16 * (tt % nta), b0 = 16 * (tt / nta);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int a = ti + 16 * u, b = tj + 16 * v;
-          if (a < kk && b < w) T[(k0 + a) + (size_t)(c0 + b) * e.kcap] = acc[u][v];
+          for (int r = 0; r < 4; ++r) {
+            const int a = a0 + (l & 15), b = b0 + (l >> 4) + 4 * r;
+            if (a < kk && b < wc) T[(size_t)(k0 + a) + (size_t)(c0 + b) * e.kcap] = acc[j][r];
+          }
         }
+      }
     }
   }
 }
