@@ -1006,6 +1006,36 @@ __device__ __forceinline__ void wave_argmax(double& v, int& ix) {
   v = __hiloint2double(hi, lo);
 }
 
+// Wave-wide choice of the lane with the largest candidate value v >= 0
+// (scaled by inv_scale into [0, 1]) through one 32-bit key per lane: the
+// float bits of the scaled value with the low six bits replaced by
+// 63 - lane, so each step is a single unsigned max.  Values that agree in
+// their leading 17 mantissa bits count as equal and go to the lowest lane.
+// Returns the lane (wave-uniform), or -1 when no lane is a candidate.
+template <int CTRL, int RM>
+__device__ __forceinline__ uint32_t umax_dpp(uint32_t k) {
+  const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)k, (int)k, CTRL, RM, 0xf, false);
+  return o > k ? o : k;
+}
+__device__ __forceinline__ int wave_argmax_key(double v, bool cand, double inv_scale) {
+  const int lane = threadIdx.x & 63;
+  const float f = (float)(v * inv_scale);
+  uint32_t key = (cand && f > 0.0f) ? ((__float_as_uint(f) & ~63u) | (uint32_t)(63 - lane)) : 0u;
+  key = umax_dpp<0xB1, 0xf>(key);    // quad_perm [1,0,3,2]
+  key = umax_dpp<0x4E, 0xf>(key);    // quad_perm [2,3,0,1]
+  key = umax_dpp<0x141, 0xf>(key);   // row_half_mirror
+  key = umax_dpp<0x140, 0xf>(key);   // row_mirror
+  key = umax_dpp<0x142, 0xa>(key);   // row_bcast:15
+  key = umax_dpp<0x143, 0xc>(key);   // row_bcast:31: lane 63 holds the maximum
+  key = (uint32_t)__builtin_amdgcn_readlane((int)key, 63);
+  return key ? 63 - (int)(key & 63u) : -1;
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double block_sum(TruncShared& sh, double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
@@ -1244,6 +1274,7 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
   double dmax0 = d;
   int dummy = lane;
   wave_argmax(dmax0, dummy);
+  const double inv_dmax0 = dmax0 > 0.0 ? 1.0 / dmax0 : 0.0;
   bool alive = in;
   int r = 0;
   double trace = 0.0;
@@ -1255,11 +1286,14 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
       trace = group_sum(alive ? fmax(d, 0.0) : 0.0, 64);
       if (!(trace > trace_stop)) break;
     }
-    double v = alive ? d : -1.0;
-    int p = lane;
-    wave_argmax(v, p);
+    const int p = wave_argmax_key(d, alive, inv_dmax0);
+    if (p < 0) break;
+    const double v = readlane_d(d, p);
     if (!(v > 1e-14 * dmax0) || !(dmax0 > 0.0)) break;
-    const double rp = sqrt(v), inv = 1.0 / rp;
+    // 1 / sqrt(v) by the hardware estimate and one Newton step, sqrt(v) from it
+    double inv = __builtin_amdgcn_rsq(v);
+    inv = inv * (1.5 - 0.5 * v * inv * inv);
+    const double rp = v * inv;
     const double l = alive ? (lane == p ? rp : pick64(g, p) * inv) : 0.0;
     if (in) G[s][lane] = l;
     lv[lane] = l;
