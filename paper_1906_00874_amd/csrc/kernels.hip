@@ -947,7 +947,7 @@ struct TruncShared {
   Term tm[TMAX];
   int px[KM], py[KM], ord[KM];
   int8_t colt[KM], colj[KM];
-  int rx, ry, k, capped, K, kc, te;
+  int rx, ry, k, capped, K, kc, te, jcur, jsweeps;
   double mnorm;
 };
 
@@ -1471,6 +1471,94 @@ __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, dou
   sweeps = 0;
   if (ncol < 2 || rx <= 0 || !(ms > 0.0)) return 0;
   const int npair = ncol / 2, nm1 = ncol - 1;
+  if (npair <= 8) {
+    // at most 16 columns: every pair on eight lanes of wavefront 0, whose
+    // rounds need no block barrier (the wavefront's LDS accesses complete in
+    // order; the fences keep the compiler from moving them across rounds)
+    if (tid < 64) {
+      const int q = tid >> 3, l = tid & 7;
+      const bool act = q < npair;
+      const int p0 = q, p1 = nm1 - q;
+      const int n0 = q == 0 ? 0 : q + 1, n1 = q == 0 ? 1 : ncol - q;
+      const int f0 = jphys(p0), f1 = jphys(p1), g0 = jphys(n0), g1 = jphys(n1);
+      const double tiny = 1e-30 * ms;
+      int cur = 0;
+      for (int sweep = 0; sweep < 30; ++sweep) {
+        {
+          double (*A)[KM + 1] = cur ? sh.gy : sh.m;
+          const int j = tid >> 2, part = tid & 3;
+          double s2 = 0.0;
+          if (j < ncol) {
+            const int fj = jphys(j);
+            for (int i = part; i < rx; i += 4) s2 += A[i][fj] * A[i][fj];
+          }
+          s2 += dpp_d<0xB1>(s2);
+          s2 += dpp_d<0x4E>(s2);
+          if (part == 0 && j < ncol) sh.nrm[cur][j] = s2;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        double mu = 0.0;
+        for (int round = 0; round < nm1; ++round) {
+          double (*S)[KM + 1] = cur ? sh.gy : sh.m;
+          double (*D)[KM + 1] = cur ? sh.m : sh.gy;
+          double ma[8], mb[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int i = l + 8 * t;
+            ma[t] = (act && i < rx) ? S[i][f0] : 0.0;
+            mb[t] = (act && i < rx) ? S[i][f1] : 0.0;
+          }
+          const double al = act ? sh.nrm[cur][p0] : 0.0, be = act ? sh.nrm[cur][p1] : 0.0;
+          double ga = 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) ga += ma[t] * mb[t];
+          ga = group_sum(ga, 8);
+          double cs = 1.0, sn = 0.0, al2 = al, be2 = be;
+          if (act && al > tiny && be > tiny && ga * ga > 1e-30 * al * be) {
+            mu = fmax(mu, ga * ga / (al * be));
+            const double d = be - al, g2 = 2.0 * ga;
+            const double rr = sqrt(d * d + g2 * g2), ad = fabs(d);
+            const double y = 2.0 * rr * (rr + ad);
+            double qy = __builtin_amdgcn_rsq(y);
+            qy = qy * (1.5 - 0.5 * y * qy * qy);
+            sn = (d >= 0.0 ? g2 : -g2) * qy;
+            cs = (rr + ad) * qy;
+            const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * ga;
+            al2 = c2 * al - cg + s2 * be;
+            be2 = s2 * al + cg + c2 * be;
+          }
+          if (act) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int i = l + 8 * t;
+              if (i < rx) {
+                D[i][g0] = cs * ma[t] - sn * mb[t];
+                D[i][g1] = sn * ma[t] + cs * mb[t];
+              }
+            }
+            if (l == 0) {
+              sh.nrm[cur ^ 1][n0] = al2;
+              sh.nrm[cur ^ 1][n1] = be2;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          cur ^= 1;
+        }
+        ++sweeps;
+        for (int o = 32; o > 0; o >>= 1) mu = fmax(mu, __shfl_xor(mu, o));
+        if (!(mu > stop)) break;
+      }
+      if (tid == 0) {
+        sh.jcur = cur;
+        sh.jsweeps = sweeps;
+      }
+    }
+    __syncthreads();
+    sweeps = sh.jsweeps;
+    return sh.jcur;
+  }
   int grp = 64;
   while (grp > 8 && grp * npair > NT) grp >>= 1;
   const int q = tid / grp, l = tid % grp;
