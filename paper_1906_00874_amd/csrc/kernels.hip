@@ -962,6 +962,26 @@ __device__ __forceinline__ double group_sum(double v, int g) {
   return v;
 }
 
+// sum over the whole wavefront by DPP alone (row sums, then the row
+// broadcasts carry rows 0-2 into row 3); the result is wave-uniform
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_dm(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, RM, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);          // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);          // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);         // row_half_mirror
+  v += dpp_d<0x140>(v);         // row_mirror: every lane holds its row's sum
+  v += dpp_dm<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_dm<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3: lane 63 holds all
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // v[p] for a wave-uniform p (a branch tree, no per-element selects)
 #define HLU_C8(C, b) C(b) C(b + 1) C(b + 2) C(b + 3) C(b + 4) C(b + 5) C(b + 6) C(b + 7)
 #define HLU_C64(C) HLU_C8(C, 0) HLU_C8(C, 8) HLU_C8(C, 16) HLU_C8(C, 24) \
@@ -1283,7 +1303,7 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
       // stop once the residual diagonal (the squared distances of the
       // remaining rows from the span of the chosen ones) sums to at most
       // trace_stop
-      trace = group_sum(alive ? fmax(d, 0.0) : 0.0, 64);
+      trace = wave_sum(alive ? fmax(d, 0.0) : 0.0);
       if (!(trace > trace_stop)) break;
     }
     const int p = wave_argmax_key(d, alive, inv_dmax0);
@@ -1319,7 +1339,7 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
   if (alive) piv[r + __popcll(mask & ((1ull << lane) - 1ull))] = lane;
   if (lane == 0) *r_out = r;
   if constexpr (TRACE_STOP) {
-    trace = group_sum(alive ? fmax(d, 0.0) : 0.0, 64);
+    trace = wave_sum(alive ? fmax(d, 0.0) : 0.0);
     if (lane == 0) *trace_out = trace;
   }
 }
