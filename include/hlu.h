@@ -151,6 +151,23 @@ hlu_status hlu_assemble_from(hlu_handle h, hlu_handle src, void* stream);
  * compute units to launches of other handles on other streams. */
 hlu_status hlu_set_workers(hlu_handle h, int workers);
 
+/* Scheduling of the factorisation by the dataflow executor (the early start
+ * of each operation once its own predecessors are done, Secs. 4-5; the
+ * priorities are this library's refinement of it).  From the op records of
+ * the last factorisation of h (durations, plus a fixed hand-off per
+ * dependency edge), every op's slack against the longest path L is
+ * computed; ops with predecessors and slack <= slack_frac * L are flagged
+ * near-critical and from then on go to a second ready ring that
+ * high_workers workgroups serve exclusively.  high_workers = 0 clears the
+ * flags (one ring).  The flags live in h's device buffer (bit 30 of each
+ * op's initial in-degree); batched launches ignore them.  *n_flagged
+ * (optional) receives the number of flagged ops.  HLU_ERR_STATE if h is
+ * unbound or, with high_workers > 0, not factored since its last reset;
+ * HLU_ERR_ARG for slack_frac outside [0, 1] or high_workers outside
+ * [0, 1024].  Synchronises the device. */
+hlu_status hlu_set_priorities(hlu_handle h, double slack_frac, int high_workers,
+                              int32_t* n_flagged);
+
 /* H-LU of the factor copy in place (Sec. 3.1 sequence, recursive), one
  * launch per kernel type per wave of the static schedule.  Zero pivots are
  * recorded on the device and reported by hlu_sync. */

@@ -74,6 +74,7 @@ _sig = {
     "hlu_clone": (C.c_int, [_P, C.POINTER(_P)]),
     "hlu_assemble_from": (C.c_int, [_P, _P, _P]),
     "hlu_set_workers": (C.c_int, [_P, C.c_int]),
+    "hlu_set_priorities": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int32)]),
     "hlu_factor": (C.c_int, [_P, _P]),
     "hlu_batch_create": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(_P)]),
     "hlu_batch_required_bytes": (C.c_size_t, [_P]),
@@ -174,6 +175,15 @@ class HLU:
     def set_workers(self, workers):
         """Dataflow workgroups per launch (0: one per compute unit)."""
         _check(lib.hlu_set_workers(self.h, int(workers)))
+
+    def set_priorities(self, slack_frac, high_workers):
+        """Flag the factor ops within slack_frac of the longest path (from
+        the last factorisation's records) for the high ring served by
+        high_workers workgroups (0 clears); returns the flagged count."""
+        nf = C.c_int32(0)
+        _check(lib.hlu_set_priorities(self.h, float(slack_frac), int(high_workers),
+                                      C.byref(nf)))
+        return int(nf.value)
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -33,12 +33,12 @@ extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* star
                                            int32_t* status, hipGraphExec_t* out);
 extern "C" hipError_t hlu_launch_dataflow(int kind, const void* parts, int np, int* queue,
                                           const int* ready0, int nready, int* ctrl, int n,
-                                          int workers, long long timeout, int32_t* status,
-                                          hipStream_t s);
+                                          int nhigh, int nhw, int workers, long long timeout,
+                                          int32_t* status, hipStream_t s);
 extern "C" hipError_t hlu_build_df_graph(int kind, const void* parts, int np, int* queue,
                                          const int* ready0, int nready, int* ctrl, int n,
-                                         int workers, long long timeout, int32_t* status,
-                                         hipGraphExec_t* out);
+                                         int nhigh, int nhw, int workers, long long timeout,
+                                         int32_t* status, hipGraphExec_t* out);
 
 namespace {
 
@@ -281,6 +281,8 @@ struct hlu_handle_s {
   bool use_graph = true;
   int executor = 0;                   // 0: waves, 1: dataflow
   int workers = 0;                    // dataflow workgroups (0: one per compute unit)
+  int n_high = 0;                     // factor ops flagged near-critical (high ring)
+  int high_workers = 0;               // workgroups serving the high ring
   hipGraphExec_t graph_f = nullptr;   // factor schedule (with status reset)
   hipGraphExec_t graph_s = nullptr;   // solve schedule
   hipGraphExec_t graph_df = nullptr;  // factor by the dataflow executor
@@ -709,16 +711,17 @@ static hlu_status run_dataflow(hlu_handle h, const DfArrays& da, hipStream_t s,
   const void* part = b + da.part();
   const int n = (int)sc.ops.size(), nready = (int)sc.ready0.size();
   if (n == 0) return HLU_OK;
+  const int nhigh = factor && h->high_workers > 0 && h->high_workers < cus ? h->n_high : 0;
+  const int nhw = nhigh > 0 ? h->high_workers : 0;
   if (h->use_graph) {
     if (!*graph)
-      HIPCHK(hlu_build_df_graph(factor ? 0 : 1, part, 1, queue, ready0, nready, ctrl, n, cus,
-                                timeout, status,
-                                graph));
+      HIPCHK(hlu_build_df_graph(factor ? 0 : 1, part, 1, queue, ready0, nready, ctrl, n, nhigh,
+                                nhw, cus, timeout, status, graph));
     HIPCHK(hipGraphLaunch(*graph, s));
     return HLU_OK;
   }
-  HIPCHK(hlu_launch_dataflow(factor ? 0 : 1, part, 1, queue, ready0, nready, ctrl, n, cus, timeout,
-                             status, s));
+  HIPCHK(hlu_launch_dataflow(factor ? 0 : 1, part, 1, queue, ready0, nready, ctrl, n, nhigh, nhw,
+                             cus, timeout, status, s));
   return HLU_OK;
 }
 
@@ -747,6 +750,70 @@ hlu_status hlu_set_executor(hlu_handle h, int mode) {
   if (!h) return fail(HLU_ERR_ARG, "NULL handle");
   if (mode != 0 && mode != 1) return fail(HLU_ERR_ARG, "executor must be 0 (waves) or 1 (dataflow)");
   h->executor = mode;
+  return HLU_OK;
+}
+
+// Near-critical ops of the factor schedule from the last factorisation's op
+// records: with d the recorded durations and a fixed hand-off time per edge,
+// top(u) is the longest path to u's start and bottom(u) the longest path
+// from u's start to the end; an op whose slack L - top - bottom is at most
+// slack_frac * L (L the longest path) and that has predecessors is flagged
+// (bit 30 of its initial in-degree on the device) and goes to the high
+// ring, served by high_workers workgroups.  high_workers = 0 clears the
+// flags.
+hlu_status hlu_set_priorities(hlu_handle h, double slack_frac, int high_workers,
+                              int32_t* n_flagged) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  if (high_workers < 0 || high_workers > 1024)
+    return fail(HLU_ERR_ARG, "high_workers must be in [0, 1024]");
+  if (!(slack_frac >= 0.0 && slack_frac <= 1.0))
+    return fail(HLU_ERR_ARG, "slack_frac must be in [0, 1]");
+  const hlu::Schedule& sc = h->plan.fsched;
+  const size_t n = sc.ops.size();
+  std::vector<int32_t> deg(sc.indeg0.begin(), sc.indeg0.end());
+  int nh = 0;
+  if (high_workers > 0 && n > 0) {
+    if (!h->factored) return fail(HLU_ERR_STATE, "factor once first (its op records give the durations)");
+    int cus = 0;
+    long long tps = 0;
+    hlu_status st = device_facts(&cus, &tps);
+    if (st != HLU_OK) return st;
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<double> rec(n * (hlu::kCostRecBytes / 8));
+    HIPCHK(hipMemcpy(rec.data(), h->base + h->plan.off_cost, n * hlu::kCostRecBytes,
+                     hipMemcpyDeviceToHost));
+    const size_t w = hlu::kCostRecBytes / 8;
+    const double hop = 8e-6 * (double)tps;   // hand-off of one edge, in ticks
+    std::vector<double> d(n), top(n, 0.0), bot(n, 0.0);
+    for (size_t i = 0; i < n; ++i) d[i] = std::max(0.0, rec[i * w + 5] - rec[i * w + 4]);
+    // the schedule is in topological order (every edge points forward)
+    for (size_t u = 0; u < n; ++u)
+      for (int e = sc.succ_off[u]; e < sc.succ_off[u + 1]; ++e) {
+        const int v = sc.succ[e];
+        top[v] = std::max(top[v], top[u] + d[u] + hop);
+      }
+    double L = 0.0;
+    for (size_t u = n; u-- > 0;) {
+      double b = 0.0;
+      for (int e = sc.succ_off[u]; e < sc.succ_off[u + 1]; ++e)
+        b = std::max(b, hop + bot[sc.succ[e]]);
+      bot[u] = d[u] + b;
+      L = std::max(L, top[u] + bot[u]);
+    }
+    for (size_t u = 0; u < n; ++u)
+      if (deg[u] > 0 && L - top[u] - bot[u] <= slack_frac * L) {
+        deg[u] |= 1 << 30;
+        ++nh;
+      }
+  }
+  const DfArrays da = df_factor(h->plan);
+  if (n > 0)
+    HIPCHK(hipMemcpy(h->base + da.indeg0, deg.data(), n * 4, hipMemcpyHostToDevice));
+  h->n_high = nh;
+  h->high_workers = nh > 0 ? high_workers : 0;
+  h->drop_graphs();
+  if (n_flagged) *n_flagged = nh;
   return HLU_OK;
 }
 
@@ -901,8 +968,8 @@ hlu_status hlu_batch_factor(hlu_batch b, void* stream) {
     HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
   HIPCHK(hlu_launch_dataflow(0, b->dev + b->off_parts, (int)b->hs.size(), (int*)(b->dev + b->off_queue),
                              (const int*)(b->dev + b->off_ready0), (int)b->ready0.size(),
-                             (int*)(b->dev + b->off_ctrl), (int)b->ntot, cus, 20 * tps, nullptr,
-                             s));
+                             (int*)(b->dev + b->off_ctrl), (int)b->ntot, 0, 0, cus, 20 * tps,
+                             nullptr, s));
   for (hlu_handle h : b->hs) h->factored = true;
   return HLU_OK;
 }

@@ -2640,9 +2640,11 @@ __global__ void k_df_reset(const DfPart* parts, int np, int* queue, const int* r
     queue[i] = i < nready ? ready0[i] : -1;
   }
   if (i == 0) {
-    ctrl[0] = 0;
-    ctrl[1] = nready;
-    ctrl[2] = 0;
+    ctrl[0] = 0;        // low ring: next ticket
+    ctrl[1] = nready;   // low ring: next free slot
+    ctrl[2] = 0;        // error flag
+    ctrl[3] = 0;        // high ring: next ticket
+    ctrl[4] = 0;        // high ring: next free slot
   }
 }
 
@@ -2695,21 +2697,34 @@ __device__ __forceinline__ bool run_op_masked(const Op& op) {
   return false;
 }
 
+// The ready ops sit in two FIFO rings of one queue array: the low ring
+// (slots [0, n - nhigh)) and the high ring (slots [n - nhigh, n)) for the ops
+// flagged as near-critical (bit 30 of their initial in-degree).  Workgroups
+// 0 .. nhw - 1 serve the high ring, the others the low ring, each with the
+// same protocol: take a ticket, wait for the op pushed into that slot.
+// The initially ready ops are never flagged, so exactly nhigh ops enter the
+// high ring.  With nhw == 0 the flags are ignored (one ring).
 template <unsigned MASK>
 __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np, int* queue,
-                                       int* ctrl, int n, long long timeout) {
+                                       int* ctrl, int n, int nhigh, int nhw, long long timeout) {
   __shared__ int s_op;
   const int tid = threadIdx.x;
+  if (nhw <= 0) nhigh = 0;
+  const int nlow = n - nhigh;
+  const bool hw = (int)blockIdx.x < nhw;
+  int* const head = hw ? &ctrl[3] : &ctrl[0];
+  int* const ring = hw ? queue + nlow : queue;
+  const int cnt = hw ? nhigh : nlow;
   for (;;) {
     if (tid == 0) {
       int v = -1;
-      const int s = __hip_atomic_fetch_add(&ctrl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (s < n) {
+      const int s = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (s < cnt) {
         const long long t0 = (long long)wall_clock64();
         // spin with relaxed loads: an acquire per iteration would invalidate
         // this chiplet's L2 under the ops running beside it
         for (;;) {
-          v = __hip_atomic_load(&queue[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          v = __hip_atomic_load(&ring[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (v >= 0) {
             // pairs with the release store that pushed v: the op's inputs
             // (every predecessor's writes) are visible from here on
@@ -2739,8 +2754,9 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     // many successors pays one atomic round trip, not one per successor.
     // A thread that brings a successor to zero acquires (its decrement read
     // the others' through the chain of read-modify-writes, so their fences
-    // synchronise with it) and pushes the successor with a release store;
-    // each wavefront reserves the queue slots of its pushes with one atomic.
+    // synchronise with it) and pushes the successor with a release store
+    // into the ring its flag names; each wavefront reserves the slots of its
+    // pushes with one atomic per ring.
     __syncthreads();
     if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -2753,28 +2769,35 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
       for (int eb = e0; eb < e1; eb += NT) {
         const int e = eb + tid;
         int t = -1;
-        bool ready = false;
+        bool ready = false, hi = false;
         if (e < e1) {
           t = succ[e];
-          ready = __hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) == 1;
+          const int old = __hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          ready = (old & 0x3fffffff) == 1;
+          hi = nhigh > 0 && ((old >> 30) & 1);
         }
-        const unsigned long long mask = __ballot(ready);
-        if (mask) {
+        const unsigned long long mlo = __ballot(ready && !hi), mhi = __ballot(ready && hi);
+        if (mlo | mhi) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          const int leader = __ffsll((long long)mask) - 1;
-          int slot0 = 0;
-          if (lane == leader)
-            slot0 = __hip_atomic_fetch_add(&ctrl[1], __popcll(mask), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-          slot0 = __shfl(slot0, leader);
-          if (ready) {
-            const int slot = slot0 + __popcll(mask & ((1ull << lane) - 1ull));
-            if (slot < n)
-              __hip_atomic_store(&queue[slot], pt.base + t, __ATOMIC_RELEASE,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-            else
-              __hip_atomic_store(&ctrl[2], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            const unsigned long long mask = r ? mhi : mlo;
+            if (!mask) continue;
+            const int leader = __ffsll((long long)mask) - 1;
+            int slot0 = 0;
+            if (lane == leader)
+              slot0 = __hip_atomic_fetch_add(r ? &ctrl[4] : &ctrl[1], __popcll(mask),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            slot0 = __shfl(slot0, leader);
+            if ((mask >> lane) & 1ull) {
+              const int slot = slot0 + __popcll(mask & ((1ull << lane) - 1ull));
+              if (slot < (r ? nhigh : nlow))
+                __hip_atomic_store(&queue[(r ? nlow : 0) + slot], pt.base + t, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+              else
+                __hip_atomic_store(&ctrl[2], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
           }
         }
       }
@@ -2783,17 +2806,15 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
   }
 }
 
-// The executor over factor schedules (one or several parts) and over solve
-// schedules.
 __global__ void __launch_bounds__(NT) k_df_factor(const DfPart* __restrict__ parts, int np,
-                                                  int* queue, int* ctrl, int n,
-                                                  long long timeout) {
-  df_run<DF_FACTOR_TYPES>(parts, np, queue, ctrl, n, timeout);
+                                                  int* queue, int* ctrl, int n, int nhigh,
+                                                  int nhw, long long timeout) {
+  df_run<DF_FACTOR_TYPES>(parts, np, queue, ctrl, n, nhigh, nhw, timeout);
 }
 __global__ void __launch_bounds__(NT) k_df_solve(const DfPart* __restrict__ parts, int np,
-                                                 int* queue, int* ctrl, int n,
-                                                 long long timeout) {
-  df_run<DF_SOLVE_TYPES>(parts, np, queue, ctrl, n, timeout);
+                                                 int* queue, int* ctrl, int n, int nhigh,
+                                                 int nhw, long long timeout) {
+  df_run<DF_SOLVE_TYPES>(parts, np, queue, ctrl, n, nhigh, nhw, timeout);
 }
 
 static size_t lds_bytes(int type) {
@@ -2869,9 +2890,11 @@ static hipError_t df_attr(int kind) {
 // `status` is given, it is cleared first.
 extern "C" hipError_t hlu_launch_dataflow(int kind, const void* parts, int np, int* queue,
                                           const int* ready0, int nready, int* ctrl, int n,
-                                          int workers, long long timeout, int32_t* status,
-                                          hipStream_t s) {
+                                          int nhigh, int nhw, int workers, long long timeout,
+                                          int32_t* status, hipStream_t s) {
   if (kind != 0 && kind != 1) return hipErrorInvalidValue;
+  if (nhigh < 0 || nhigh > n - nready || nhw < 0 || (nhigh > 0 && nhw >= workers))
+    return hipErrorInvalidValue;
   hipError_t e = df_attr(kind);
   if (e != hipSuccess) return e;
   if (n <= 0) return hipSuccess;
@@ -2881,20 +2904,22 @@ extern "C" hipError_t hlu_launch_dataflow(int kind, const void* parts, int np, i
                      nready, n, ctrl);
   if (kind == 0)
     hipLaunchKernelGGL(hlu::k_df_factor, dim3(workers), dim3(NT), df_lds(0), s, pp, np, queue,
-                       ctrl, n, timeout);
+                       ctrl, n, nhigh, nhw, timeout);
   else
     hipLaunchKernelGGL(hlu::k_df_solve, dim3(workers), dim3(NT), df_lds(1), s, pp, np, queue,
-                       ctrl, n, timeout);
+                       ctrl, n, nhigh, nhw, timeout);
   return hipGetLastError();
 }
 
 // The same run as a graph (status clear, reset, executor), built explicitly.
 extern "C" hipError_t hlu_build_df_graph(int kind, const void* parts, int np, int* queue,
                                          const int* ready0, int nready, int* ctrl, int n,
-                                         int workers, long long timeout, int32_t* status,
-                                         hipGraphExec_t* out) {
+                                         int nhigh, int nhw, int workers, long long timeout,
+                                         int32_t* status, hipGraphExec_t* out) {
   *out = nullptr;
   if (kind != 0 && kind != 1) return hipErrorInvalidValue;
+  if (nhigh < 0 || nhigh > n - nready || nhw < 0 || (nhigh > 0 && nhw >= workers))
+    return hipErrorInvalidValue;
   hipError_t e = df_attr(kind);
   if (e != hipSuccess) return e;
   hipGraph_t g;
@@ -2922,7 +2947,7 @@ extern "C" hipError_t hlu_build_df_graph(int kind, const void* parts, int np, in
     e = hipGraphAddKernelNode(&n1, g, status ? &n0 : nullptr, status ? 1 : 0, &p);
   }
   if (e == hipSuccess) {
-    void* args[] = {&pp, &np, &queue, &ctrl, &n, &timeout};
+    void* args[] = {&pp, &np, &queue, &ctrl, &n, &nhigh, &nhw, &timeout};
     hipKernelNodeParams p = {};
     p.func = const_cast<void*>(df_kernel(kind));
     p.gridDim = dim3(workers);

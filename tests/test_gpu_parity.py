@@ -318,6 +318,41 @@ def test_dataflow_executor_matches_waves(P, level, prec, graph):
         assert np.array_equal(x, x0), rep
 
 
+@pytest.mark.parametrize("slack,workers,graph", [(0.02, 4, 0), (0.2, 16, 1), (1.0, 2, 0)])
+def test_priority_rings_match_one_ring(P, slack, workers, graph):
+    """Near-critical ops flagged from a factorisation's own records go to a
+    second ready ring served by dedicated workgroups; the ops and their
+    inputs are the same, so the factors are bitwise those of one ring.  The
+    last case flags every op that has predecessors (the high ring carries
+    almost all of the schedule through two workgroups); clearing the flags
+    restores one ring."""
+    xyz, area, h = _hlu(P, 4, 32, eps=1e-6, precision=P.PREC_MIXED, max_nrhs=2)
+    h.set_graph(graph)
+    h.set_executor(1)
+    h.factor()
+    st, _ = h.sync(check=False)
+    assert st == 0
+    L0, U0 = h.export_factors()
+    p0 = h.export_pivots()
+    nf = h.set_priorities(slack, workers)
+    assert nf > 0
+    for rep in range(2):
+        h.reset()
+        h.factor()
+        st, _ = h.sync(check=False)
+        assert st == 0, (rep, P.lib.hlu_last_error())
+        L, U = h.export_factors()
+        assert np.array_equal(h.export_pivots(), p0)
+        assert np.array_equal(L, L0) and np.array_equal(U, U0), rep
+    assert h.set_priorities(slack, 0) == 0
+    h.reset()
+    h.factor()
+    st, _ = h.sync(check=False)
+    assert st == 0
+    L, U = h.export_factors()
+    assert np.array_equal(L, L0) and np.array_equal(U, U0)
+
+
 def test_batched_factor_matches_alone(P):
     """One persistent launch over the union of several matrices' schedules
     (sphere and ellipsoids of different sizes) gives, matrix by matrix, the
