@@ -38,18 +38,6 @@ __device__ __forceinline__ int pcols(const PRef& r) {
                  : r.cols;
 }
 
-__device__ __forceinline__ double pget(const PRef& r, int i, int j) {
-  if (r.kind == PK_IDENT) return (j == i + r.ld) ? 1.0 : 0.0;
-  size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
-  return r.dt == DT_F64 ? gptr<const double>(r.ptr)[k] : (double)gptr<const float>(r.ptr)[k];
-}
-
-__device__ __forceinline__ void pset(const PRef& r, int i, int j, double v) {
-  size_t k = r.trans ? (size_t)j + (size_t)i * r.ld : (size_t)i + (size_t)j * r.ld;
-  if (r.dt == DT_F64) gptr<double>(r.ptr)[k] = v;
-  else gptr<float>(r.ptr)[k] = (float)v;
-}
-
 // Batched panel access.  Element (i, j) of a stored panel sits at
 // i * si + j * sj elements from its start (a transposed panel swaps the two
 // strides; `tr` transposes the view once more).  A batch of loads takes one
@@ -1214,7 +1202,6 @@ __device__ __forceinline__ void gram_step(const double (&cv)[NB], v4d (&acc)[5])
 template <int NB, int W>
 __device__ __forceinline__ void gram_tiles(double (*C)[KM + 1], int nq, v4d (&acc)[5]) {
   const int l = threadIdx.x & 63;
-#pragma unroll 2
   for (int q = 0; q < nq; ++q) {
     const int i = 4 * q + (l >> 4);
     double cv[NB];
@@ -1405,7 +1392,6 @@ __device__ __forceinline__ void apply_tiles(double (*C)[KM + 1], double (*T)[KM 
                                             int w, v4d (&acc)[2][2]) {
   const int l = threadIdx.x & 63;
   const int nq = (K + 3) >> 2;
-#pragma unroll 2
   for (int q = 0; q < nq; ++q) {
     const int kk = 4 * q + (l >> 4);
     const bool in = kk < K;
