@@ -1310,14 +1310,19 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
     // below see the stores above).  Straight-line over all 64 entries: lanes
     // at or beyond K hold l = 0, so their entries stay zero, and without a
     // branch per entry the reads are issued together.
+    // (two halves of 32 rows: all reads of a half are issued together, and
+    // the batch stays within the register budget of the inlined executor)
     const double2* l2 = reinterpret_cast<const double2*>(lv);
-    double2 lr[KM / 2];
 #pragma unroll
-    for (int i = 0; i < KM; i += 2) lr[i >> 1] = l2[i >> 1];
+    for (int h = 0; h < KM; h += KM / 2) {
+      double2 lr[KM / 4];
 #pragma unroll
-    for (int i = 0; i < KM; i += 2) {
-      g[i] -= lr[i >> 1].x * l;
-      g[i + 1] -= lr[i >> 1].y * l;
+      for (int i = 0; i < KM / 2; i += 2) lr[i >> 1] = l2[(h + i) >> 1];
+#pragma unroll
+      for (int i = 0; i < KM / 2; i += 2) {
+        g[h + i] -= lr[i >> 1].x * l;
+        g[h + i + 1] -= lr[i >> 1].y * l;
+      }
     }
     d -= l * l;
     ++r;
