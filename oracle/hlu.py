@@ -15,7 +15,7 @@ what the method states:
   solves on the k columns of the factors, and addition followed by an SVD
   that discards small singular values (Sec. 3.1, "Low-rank blocks").
 
-Readings where the paper is silent (all listed in the design doc as well):
+Readings where the paper is silent:
 * split: longest bbox axis (lowest axis on ties), box midpoint, strict '<'
   to son 0, stable order; median split if a son would be empty;
 * admissible(t,s): eta > 0, dist > 0 and min(diam t, diam s) <= eta*dist,
