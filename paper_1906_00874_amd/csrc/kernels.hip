@@ -205,6 +205,36 @@ __device__ __forceinline__ void start_tick(const Op& op) {
   if (op.cost && threadIdx.x == 0) gptr<double>(op.cost)[4] = (double)wall_clock64();
 }
 
+// one step of a wave argmax (largest value, smallest index among equals)
+// through a DPP lane permutation; lanes outside row_mask keep their own
+template <int CTRL, int RM>
+__device__ __forceinline__ void amax_dpp(double& v, int& ix) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, RM, 0xf,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, RM, 0xf,
+                                             false);
+  const int i2 = __builtin_amdgcn_update_dpp(ix, ix, CTRL, RM, 0xf, false);
+  const double v2 = __hiloint2double(hi, lo);
+  if (v2 > v || (v2 == v && i2 < ix)) {
+    v = v2;
+    ix = i2;
+  }
+}
+
+// wave-wide argmax; the result (read from lane 63) is wave-uniform
+__device__ __forceinline__ void wave_argmax(double& v, int& ix) {
+  amax_dpp<0xB1, 0xf>(v, ix);    // quad_perm [1,0,3,2]
+  amax_dpp<0x4E, 0xf>(v, ix);    // quad_perm [2,3,0,1]
+  amax_dpp<0x141, 0xf>(v, ix);   // row_half_mirror
+  amax_dpp<0x140, 0xf>(v, ix);   // row_mirror: every lane holds its row's result
+  amax_dpp<0x142, 0xa>(v, ix);   // row_bcast:15 into rows 1 and 3
+  amax_dpp<0x143, 0xc>(v, ix);   // row_bcast:31 into rows 2 and 3: lane 63 holds all
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  ix = __builtin_amdgcn_readlane(ix, 63);
+  v = __hiloint2double(hi, lo);
+}
+
 // ---------------------------------------------------------------- getrf
 // Right-looking unblocked LU with partial pivoting of one b x b leaf
 // (b <= 64) held in LDS; pivot = first row of the largest |a_ik|.
@@ -230,13 +260,10 @@ __device__ void d_getrf(const Op& op) {
   __syncthreads();
   for (int k = 0; k < b; ++k) {
     if (tid < 64) {
+      // first row of the largest |a_ik| (DPP argmax, exact compare)
       double v = (tid >= k && tid < b) ? fabs(a[tid][k]) : -1.0;
       int ix = tid;
-      for (int o = 32; o > 0; o >>= 1) {
-        double v2 = __shfl_xor(v, o);
-        int i2 = __shfl_xor(ix, o);
-        if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
-      }
+      wave_argmax(v, ix);
       if (tid == 0) {
         s_piv = ix;
         piv[k] = ix;
@@ -259,11 +286,17 @@ __device__ void d_getrf(const Op& op) {
       for (int i = k + 1 + tid; i < b; i += NT) a[i][k] = a[i][k] / d;
     }
     __syncthreads();
-    const int r = b - k - 1;
-    for (int e = tid; e < r * r; e += NT) {
-      int i = k + 1 + e % r, j = k + 1 + e / r;
-      double prod = a[i][k] * a[k][j];
-      a[i][j] = a[i][j] - prod;
+    {
+      // rank-one update: lane i holds row i, wavefront w the columns
+      // k + 1 + w, k + 5 + w, ... (no index division per element)
+      const int i = tid & 63, w = tid >> 6;
+      if (i > k && i < b) {
+        const double l = a[i][k];
+        for (int j = k + 1 + w; j < b; j += 4) {
+          const double prod = l * a[k][j];
+          a[i][j] = a[i][j] - prod;
+        }
+      }
     }
     __syncthreads();
   }
@@ -984,36 +1017,6 @@ __device__ __forceinline__ double pick64(const double (&v)[KM], int p) {
   }
   return r;
 }
-// one step of a wave argmax (largest value, smallest index among equals)
-// through a DPP lane permutation; lanes outside row_mask keep their own
-template <int CTRL, int RM>
-__device__ __forceinline__ void amax_dpp(double& v, int& ix) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, RM, 0xf,
-                                             false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, RM, 0xf,
-                                             false);
-  const int i2 = __builtin_amdgcn_update_dpp(ix, ix, CTRL, RM, 0xf, false);
-  const double v2 = __hiloint2double(hi, lo);
-  if (v2 > v || (v2 == v && i2 < ix)) {
-    v = v2;
-    ix = i2;
-  }
-}
-
-// wave-wide argmax; the result (read from lane 63) is wave-uniform
-__device__ __forceinline__ void wave_argmax(double& v, int& ix) {
-  amax_dpp<0xB1, 0xf>(v, ix);    // quad_perm [1,0,3,2]
-  amax_dpp<0x4E, 0xf>(v, ix);    // quad_perm [2,3,0,1]
-  amax_dpp<0x141, 0xf>(v, ix);   // row_half_mirror
-  amax_dpp<0x140, 0xf>(v, ix);   // row_mirror: every lane holds its row's result
-  amax_dpp<0x142, 0xa>(v, ix);   // row_bcast:15 into rows 1 and 3
-  amax_dpp<0x143, 0xc>(v, ix);   // row_bcast:31 into rows 2 and 3: lane 63 holds all
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  ix = __builtin_amdgcn_readlane(ix, 63);
-  v = __hiloint2double(hi, lo);
-}
-
 // Wave-wide choice of the lane with the largest candidate value v >= 0
 // (scaled by inv_scale into [0, 1]) through one 32-bit key per lane: the
 // float bits of the scaled value with the low six bits replaced by
