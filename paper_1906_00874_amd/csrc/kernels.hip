@@ -175,6 +175,12 @@ __device__ __forceinline__ double dpp_d(double x) {
   return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 // FP64 matrix-core step D += A B with A 16 x 4 and B 4 x 16 (one wavefront):
 // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and its four
 // results are D[l / 16 + 4r][l % 16], r = 0..3.
@@ -362,6 +368,83 @@ __device__ __forceinline__ void trsm_subst(double (&v)[8], const double (*l)[65]
 // of Y (lane l holds rows l, l + 8, ... in registers) and each solved entry
 // is broadcast within the eight lanes through DPP, so the substitution runs
 // without barriers.  Columns are taken 32 at a time.
+// Columns of the leaf solve with one lane per row: lane i of wavefront w
+// holds row i of columns w + 4(q0 + t), t < NC, and step k takes x_k of
+// every column from lane k (a readlane), then updates the rows below (L,
+// U^T) or above (U) with one multiply-add per column.  The arithmetic per
+// entry is that of the eight-lane substitution.
+template <int TYPE, int NC>
+__device__ __forceinline__ void trsm_cols(const GView& gy, const double (*l)[65],
+                                          const double* dinv, const int* pm, int b, int c,
+                                          int q0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ncw = (c - w + 3) >> 2;
+  const int nq = min(NC, ncw - q0);
+  const int il = min(lane, b - 1);
+  int ri[NC], cj[NC];
+  bool ok[NC];
+  double v[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    ri[t] = TYPE == OP_TRSM_L ? pm[il] : il;
+    cj[t] = w + 4 * (q0 + min(t, nq - 1));
+  }
+  gload(gy, ri, cj, v);
+  if (TYPE == OP_TRSM_U) {
+    double lk = l[lane][b - 1];
+    for (int k = b - 1; k >= 0; --k) {
+      const double lnext = l[lane][k > 0 ? k - 1 : 0];
+      const double dk = dinv[k];
+#pragma unroll
+      for (int t = 0; t < NC; ++t) {
+        const double xk = readlane_d(v[t], k) * dk;
+        v[t] = lane == k ? xk : (lane < k ? v[t] - lk * xk : v[t]);
+      }
+      lk = lnext;
+    }
+  } else {
+    double lk = TYPE == OP_TRSM_UT ? l[0][lane] : l[lane][0];
+    for (int k = 0; k < b; ++k) {
+      const int kn = k + 1 < b ? k + 1 : k;
+      const double lnext = TYPE == OP_TRSM_UT ? l[kn][lane] : l[lane][kn];
+      if (TYPE == OP_TRSM_L) {
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          const double xk = readlane_d(v[t], k);
+          v[t] = (lane > k && lane < b) ? v[t] - lk * xk : v[t];
+        }
+      } else {
+        const double dk = dinv[k];
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          const double xk = readlane_d(v[t], k) * dk;
+          v[t] = lane == k ? xk : ((lane > k && lane < b) ? v[t] - lk * xk : v[t]);
+        }
+      }
+      lk = lnext;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    ok[t] = lane < b && t < nq;
+    ri[t] = il;
+  }
+  gstore(gy, ri, cj, ok, v);
+}
+template <int TYPE>
+__device__ __forceinline__ void trsm_lanes(const GView& gy, const double (*l)[65],
+                                           const double* dinv, const int* pm, int b, int c) {
+  const int ncw = (c + 3) >> 2;   // columns of wavefront 0 (the most)
+  if (ncw <= 2) {
+    if ((threadIdx.x >> 6) < c) trsm_cols<TYPE, 2>(gy, l, dinv, pm, b, c, 0);
+  } else if (ncw <= 4) {
+    trsm_cols<TYPE, 4>(gy, l, dinv, pm, b, c, 0);
+  } else {
+    const int w = threadIdx.x >> 6, mine = (c - w + 3) >> 2;
+    for (int q0 = 0; q0 < mine; q0 += 8) trsm_cols<TYPE, 8>(gy, l, dinv, pm, b, c, q0);
+  }
+}
+
 __device__ __forceinline__ void trsm_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef L = op.p[0];
@@ -405,31 +488,11 @@ __device__ __forceinline__ void trsm_body(const Op& op) {
   __syncthreads();
   if (type != OP_TRSM_L && tid < b) dinv[tid] = 1.0 / l[tid][tid];
   __syncthreads();
-  const int col = tid >> 3, ln = tid & 7;
   const GView gy = gview(Y);
-  for (int c0 = 0; c0 < (b > 0 ? c : 0); c0 += 32) {
-    const int j = c0 + col;
-    const bool act = j < c;
-    int ri[8], cj[8];
-    bool ok[8];
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = min(ln + 8 * u, b - 1);
-      ok[u] = act && ln + 8 * u < b;
-      ri[u] = type == OP_TRSM_L ? pm[i] : i;
-      cj[u] = min(j, c - 1);
-    }
-    gload(gy, ri, cj, v);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      v[u] = ok[u] ? v[u] : 0.0;
-      ri[u] = min(ln + 8 * u, b - 1);
-    }
-    if (type == OP_TRSM_L) trsm_subst<OP_TRSM_L>(v, l, dinv, b, ln);
-    else if (type == OP_TRSM_UT) trsm_subst<OP_TRSM_UT>(v, l, dinv, b, ln);
-    else trsm_subst<OP_TRSM_U>(v, l, dinv, b, ln);
-    gstore(gy, ri, cj, ok, v);
+  if (b > 0 && c > 0) {
+    if (type == OP_TRSM_L) trsm_lanes<OP_TRSM_L>(gy, l, dinv, pm, b, c);
+    else if (type == OP_TRSM_UT) trsm_lanes<OP_TRSM_UT>(gy, l, dinv, pm, b, c);
+    else trsm_lanes<OP_TRSM_U>(gy, l, dinv, pm, b, c);
   }
   const double es = Y.dt == DT_F64 ? 8.0 : 4.0;
   put_cost(op, (double)b * b * c, 8.0 * b * b / 2 + 2.0 * es * b * c);
@@ -1040,11 +1103,6 @@ __device__ __forceinline__ int wave_argmax_key(double v, bool cand, double inv_s
   key = umax_dpp<0x143, 0xc>(key);   // row_bcast:31: lane 63 holds the maximum
   key = (uint32_t)__builtin_amdgcn_readlane((int)key, 63);
   return key ? 63 - (int)(key & 63u) : -1;
-}
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ double block_sum(TruncShared& sh, double v) {
