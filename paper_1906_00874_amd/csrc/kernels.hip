@@ -319,55 +319,12 @@ __device__ void d_getrf(const Op& op) {
 
 // ---------------------------------------------------------------- leaf solves
 // p1 := L^{-1} P p1 (OP_TRSM_L), U^{-T} p1 (OP_TRSM_UT) or U^{-1} p1
-// (OP_TRSM_U) with the factored b x b leaf p0 (b <= 64); the panel is
-// processed in chunks of 64 columns.
+// (OP_TRSM_U) with the factored b x b leaf p0 (b <= 64).
 #define LDS_TRSM (64 * 65 * 8 + 64 * 8 + 64 * 4)
-// Substitution on the eight-lane column layout: step s solves row k (k = s,
-// or b-1-s for TRSM_U); the leaf entries a step needs are loaded one step
-// ahead, and every update is a select (no branch per row).  Rows >= b of the
-// LDS leaf hold zeros.
-template <int TYPE>
-__device__ __forceinline__ void trsm_subst(double (&v)[8], const double (*l)[65],
-                                           const double* dinv, int b, int ln) {
-  auto operands = [&](int k, double (&lk)[8]) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = ln + 8 * u;
-      lk[u] = TYPE == OP_TRSM_UT ? l[k][i] : l[i][k];
-    }
-  };
-  double lk[8], ln8[8];
-  if (b > 0) operands(TYPE == OP_TRSM_U ? b - 1 : 0, lk);
-  for (int s = 0; s < b; ++s) {
-    const int k = TYPE == OP_TRSM_U ? b - 1 - s : s;
-    const int kn = TYPE == OP_TRSM_U ? (k > 0 ? k - 1 : 0) : (k + 1 < b ? k + 1 : k);
-    operands(kn, ln8);
-    const int lo = k & 7, uo = k >> 3;
-    double own = 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) own = u == uo ? v[u] : own;
-    if (TYPE != OP_TRSM_L) own *= dinv[k];
-    own = ln == lo ? own : 0.0;
-    double xk = own;   // broadcast within the eight lanes (a sum of zeros and one value)
-    xk += dpp_d<0xB1>(xk);
-    xk += dpp_d<0x4E>(xk);
-    xk += dpp_d<0x141>(xk);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = ln + 8 * u;
-      const bool upd = TYPE == OP_TRSM_U ? i < k : (i > k && i < b);
-      const double nv = v[u] - lk[u] * xk;
-      v[u] = i == k ? xk : (upd ? nv : v[u]);
-      lk[u] = ln8[u];
-    }
-  }
-}
 // Leaf solves on the columns of Y (b <= 64 rows): TRSM_L Y := L^{-1} P Y
 // (unit lower, LAPACK-style row interchanges), TRSM_UT Y := U^{-T} Y,
-// TRSM_U Y := U^{-1} Y.  The leaf sits in LDS; eight lanes share one column
-// of Y (lane l holds rows l, l + 8, ... in registers) and each solved entry
-// is broadcast within the eight lanes through DPP, so the substitution runs
-// without barriers.  Columns are taken 32 at a time.
+// TRSM_U Y := U^{-1} Y.  The leaf sits in LDS (rows >= b hold zeros); the
+// columns are solved with one lane per row (trsm_cols), without barriers.
 // Columns of the leaf solve with one lane per row: lane i of wavefront w
 // holds row i of columns w + 4(q0 + t), t < NC, and step k takes x_k of
 // every column from lane k (a readlane), then updates the rows below (L,
