@@ -1355,54 +1355,42 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
 }
 
 // Tx = D Pi_x R11^{-1} W_k into m (rows = stacked columns), W_k in z and
-// R11[i][t] = gx[i][px[t]]: eight lanes per column c < k (k <= 32), lane l
-// holding rows l, l + 8, ... of the column in registers; the solved entry
-// is broadcast within the eight lanes through DPP.
-__device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int k) {
-  const int tid = threadIdx.x;
-  const int c = tid >> 3, l = tid & 7;
-  const bool act = c < k;
-  double v[8];
+// R11[i][t] = gx[i][px[t]] (k <= 32).  One lane per row: lane t of
+// wavefront w holds row t of columns w + 4q, q < NQ; step i takes every
+// column's x_i from lane i by a readlane and updates the rows above it.
+template <int NQ>
+__device__ __forceinline__ void trunc_trsv_cols(TruncShared& sh, int rx, int K, int k) {
+  const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double v[NQ];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int t = l + 8 * u;
-    v[u] = (act && t < rx) ? sh.z[t][c] : 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    const int c = w + 4 * q;
+    v[q] = (t < rx && c < k) ? sh.z[t][c] : 0.0;
   }
   for (int i = rx - 1; i >= 0; --i) {
     const int pi = sh.px[i];
     const double ri = sh.rinv[i];
-    // the column of R this step needs, read before the broadcast (straight
-    // line: a branch per entry would serialise the reads)
-    double gv[8];
+    const double g = sh.gx[t][pi];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) gv[u] = sh.gx[l + 8 * u][pi];
-    const int lo = i & 7, uo = i >> 3;
-    double own = 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) own = u == uo ? v[u] : own;
-    own = l == lo ? own * ri : 0.0;
-    // broadcast the owner's value within the eight lanes (a sum of zeros
-    // and one value is exact)
-    double xi = own;
-    xi += dpp_d<0xB1>(xi);
-    xi += dpp_d<0x4E>(xi);
-    xi += dpp_d<0x141>(xi);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int t = l + 8 * u;
-      v[u] = t == i ? xi : (t < i ? v[u] - gv[u] * xi : v[u]);
+    for (int q = 0; q < NQ; ++q) {
+      const double xi = readlane_d(v[q], i) * ri;
+      v[q] = t == i ? xi : (t < i ? v[q] - g * xi : v[q]);
     }
   }
-  if (act) {
+  if (t < K) {
+    const int row = sh.px[t];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int t = l + 8 * u;
-      if (t < K) {
-        const int row = sh.px[t];
-        sh.m[row][c] = t < rx ? v[u] * sh.dsc[row] : 0.0;
-      }
+    for (int q = 0; q < NQ; ++q) {
+      const int c = w + 4 * q;
+      if (c < k) sh.m[row][c] = t < rx ? v[q] * sh.dsc[row] : 0.0;
     }
   }
+}
+__device__ __forceinline__ void trunc_trsv8(TruncShared& sh, int rx, int K, int k) {
+  const int nq = (k + 3) >> 2;
+  if (nq <= 2) trunc_trsv_cols<2>(sh, rx, K, k);
+  else if (nq <= 4) trunc_trsv_cols<4>(sh, rx, K, k);
+  else trunc_trsv_cols<8>(sh, rx, K, k);
 }
 
 // new rows of U (threads 0-127, Tx in m) and V (threads 128-255, Ty in gy),
