@@ -2,8 +2,9 @@
 
 Each plausible slip (a lost absolute value in the pivot search, a dropped
 column scaling, a missing Sigma in the truncated factors, a sign flip in the
-low-rank update, a permutation applied after the solve instead of before)
-must be caught by the checks the oracle's pins use.  Every check runs on the
+low-rank update, a permutation applied after the solve instead of before,
+the larger box diameter or the distance of the box centres in the
+admissibility condition) must be caught by the checks the oracle's pins use.  Every check runs on the
 unmodified oracle first, so a failure under a mutant is the mutant's doing.
 """
 import math
@@ -37,6 +38,31 @@ def _truncate_ok(fn, m=200, n=150, K=40, eps=1e-6, seed=11):
     U, V = fn(X, Y, OH.Rule(eps=eps, cap=1000))
     err = np.linalg.norm(D - U @ V.T)
     return U.shape[1] == k_ref and abs(err - tails[k_ref]) <= 1e-6 * tails[k_ref] + 1e-13 * nd
+
+
+def _blocktree_ok(level=3, leaf=32, eta=2.0):
+    """Every node of Algorithm 2's block tree against the admissibility
+    condition written out here: low-rank leaves admissible, partitioned
+    nodes and dense leaves not."""
+    from hlu_inputs import icosphere
+    xyz, _ = icosphere(level)
+    root, _, _ = OH.cluster_tree(xyz, leaf)
+
+    def adm(t, s):
+        gap = np.maximum(0.0, np.maximum(s.lo - t.hi, t.lo - s.hi))
+        dist = float(np.sqrt(np.sum(gap * gap)))
+        dmin = min(float(np.sqrt(np.sum((t.hi - t.lo) ** 2))),
+                   float(np.sqrt(np.sum((s.hi - s.lo) ** 2))))
+        return dist > 0 and dmin <= eta * dist
+
+    stack = [OH.block_tree(root, root, eta)]
+    while stack:
+        b = stack.pop()
+        if (b.kind == "R") != adm(b.t, b.s):
+            return False
+        if b.kind == "H":
+            stack.extend(c for row in b.sons for c in row)
+    return True
 
 
 def _hlu_ok():
@@ -101,6 +127,22 @@ def _add_lr_sign(C, X, Y, rule):
                 _add_lr_sign(C.sons[i][j], X[OH._rows(C.t, ti)], Y[OH._rows(C.s, sj)], rule)
 
 
+def _admissible_max_diam(t, s, eta):
+    gap = np.maximum(0.0, np.maximum(s.lo - t.hi, t.lo - s.hi))
+    dist = float(np.linalg.norm(gap))
+    if eta <= 0.0 or dist <= 0.0:
+        return False
+    return max(t.diam(), s.diam()) <= eta * dist     # slip: max instead of min
+
+
+def _admissible_centre_distance(t, s, eta):
+    # slip: distance between the box centres instead of the gap between boxes
+    dist = float(np.linalg.norm(0.5 * (t.lo + t.hi) - 0.5 * (s.lo + s.hi)))
+    if eta <= 0.0 or dist <= 0.0:
+        return False
+    return min(t.diam(), s.diam()) <= eta * dist
+
+
 def _fwd_late_perm(Lb, Y):
     if Lb.kind == "F":
         # slip: the leaf's row interchanges applied after the solve
@@ -135,3 +177,11 @@ def test_hlu_check_catches_update_sign(monkeypatch):
 def test_hlu_check_catches_late_permutation(monkeypatch):
     monkeypatch.setattr(OH, "fwd", _fwd_late_perm)
     assert not _hlu_ok()
+
+
+def test_blocktree_check_catches_admissibility_slips(monkeypatch):
+    assert _blocktree_ok()
+    monkeypatch.setattr(OH, "admissible", _admissible_max_diam)
+    assert not _blocktree_ok()
+    monkeypatch.setattr(OH, "admissible", _admissible_centre_distance)
+    assert not _blocktree_ok()

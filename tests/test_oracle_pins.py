@@ -11,6 +11,7 @@ import pytest
 import scipy.linalg as sla
 
 import oracle as O
+import oracle.hlu as OH
 from hlu_inputs import icosphere, rhs_normal
 
 
@@ -360,3 +361,119 @@ def test_zero_pivot_reported():
             b.F[r1 - b.t.off] = b.F[r0 - b.t.off]
     info = O.factor(H)
     assert lf.off < info <= lf.off + lf.size
+
+
+# ---------------------------------------------------------------- Algorithm 2, both sides
+def _admissible_here(t, s, eta):
+    """The admissibility condition of Sec. 2 (with eta), written out here:
+    the smaller of the two box diameters against eta times the Euclidean
+    gap between the axis-parallel boxes."""
+    gap = [max(0.0, s.lo[d] - t.hi[d], t.lo[d] - s.hi[d]) for d in range(3)]
+    dist = math.sqrt(sum(g * g for g in gap))
+    dt = math.sqrt(sum((t.hi[d] - t.lo[d]) ** 2 for d in range(3)))
+    ds = math.sqrt(sum((s.hi[d] - s.lo[d]) ** 2 for d in range(3)))
+    return eta > 0 and dist > 0 and min(dt, ds) <= eta * dist
+
+
+def _walk(b):
+    yield b
+    if b.kind == "H":
+        for row in b.sons:
+            for c in row:
+                yield from _walk(c)
+
+
+@pytest.mark.parametrize("level,leaf,eta", [(3, 32, 2.0), (4, 32, 2.0), (3, 16, 0.5)])
+def test_block_tree_every_node_against_admissibility(level, leaf, eta):
+    """Algorithm 2 on every node of the block tree: a low-rank leaf is
+    admissible; a partitioned node and a dense leaf are not (a dense leaf
+    also has a leaf cluster on one side)."""
+    xyz, _ = icosphere(level)
+    root, _, _ = O.cluster_tree(xyz, leaf)
+    bt = O.block_tree(root, root, eta)
+    kinds = {"R": 0, "H": 0, "F": 0}
+    for b in _walk(bt):
+        kinds[b.kind] += 1
+        if b.kind == "R":
+            assert _admissible_here(b.t, b.s, eta)
+        else:
+            assert not _admissible_here(b.t, b.s, eta)
+            if b.kind == "H":
+                assert b.t.sons and b.s.sons
+            else:
+                assert not b.t.sons or not b.s.sons
+    assert all(v > 0 for v in kinds.values())
+
+
+# leaves / dense blocks / low-rank blocks of the sphere workloads at eta 2,
+# counted by an independent throwaway implementation of Algorithms 1 and 2
+# (NumPy, written separately from this oracle before it existed)
+SURVEY_COUNTS = [
+    (3, 32, 52, 418, 894),
+    (4, 32, 217, 1845, 3922),
+    (5, 32, 875, 7645, 18096),
+    (5, 64, 437, 4395, 7924),
+]
+
+
+@pytest.mark.parametrize("level,leaf,nleaves,ndense,nlr", SURVEY_COUNTS)
+def test_block_counts_match_independent_count(level, leaf, nleaves, ndense, nlr):
+    xyz, _ = icosphere(level)
+    root, _, leaves = O.cluster_tree(xyz, leaf)
+    bt = O.block_tree(root, root, 2.0)
+    nf = sum(1 for b in O.leaves_of(bt) if b.kind == "F")
+    nr = sum(1 for b in O.leaves_of(bt) if b.kind == "R")
+    assert (len(leaves), nf, nr) == (nleaves, ndense, nlr)
+
+
+# ---------------------------------------------------------------- randomised compression
+@pytest.fixture(scope="module")
+def large_admissible_blocks():
+    """Exact entries of two admissible blocks of the level-5 sphere at leaf
+    64 whose smaller side exceeds the dense-SVD limit (so the oracle's
+    assembly takes its randomised range finder for them)."""
+    xyz, area = icosphere(5)
+    root, perm, _ = O.cluster_tree(xyz, 64)
+    bt = O.block_tree(root, root, 2.0)
+    big = [b for b in O.leaves_of(bt) if b.kind == "R" and min(b.t.size, b.s.size) > 384]
+    big.sort(key=lambda b: b.t.size * b.s.size)
+    pick = [big[0], big[-1]]
+    xp, ap = xyz[perm], area[perm]
+    out = []
+    for b in pick:
+        rows = np.arange(b.t.off, b.t.off + b.t.size)
+        cols = np.arange(b.s.off, b.s.off + b.s.size)
+        out.append(O.kernel_entries(xp, ap, rows, cols))
+    return out
+
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("eps", [1e-5, 1e-6])
+def test_randomised_compression_eckart_young(large_admissible_blocks, which, eps):
+    """The randomised range finder with power iterations (the oracle's
+    assembly of large admissible blocks) against the dense SVD of the same
+    exact block: the rank rule's choice to within one and the error within
+    the tolerance."""
+    A = large_admissible_blocks[which]
+    assert min(A.shape) > 384
+    nA = np.linalg.norm(A)
+    sig = np.linalg.svd(A, compute_uv=False)
+    tails = np.sqrt(np.concatenate([np.cumsum((sig ** 2)[::-1])[::-1], [0.0]]))
+    k_ref = int(np.argmax(tails <= eps * nA))
+    rule = O.Rule(eps=eps, cap=32)
+    U, V = OH._compress_block(A, rule, np.random.default_rng(0))
+    k = U.shape[1]
+    assert abs(k - k_ref) <= 1, (k, k_ref)
+    err = np.linalg.norm(A - U @ V.T)
+    assert err <= eps * nA * (1 + 1e-6)
+    # not much worse than the best approximation of the same rank
+    assert err <= 1.5 * tails[k] + 1e-14 * nA
+
+
+def test_randomised_compression_fixed_rank(large_admissible_blocks):
+    A = large_admissible_blocks[1]
+    sig = np.linalg.svd(A, compute_uv=False)
+    U, V = OH._compress_block(A, O.Rule(fixed=8), np.random.default_rng(1))
+    assert U.shape[1] == 8
+    best = math.sqrt(float(np.sum(sig[8:] ** 2)))
+    assert np.linalg.norm(A - U @ V.T) <= 1.05 * best
