@@ -60,9 +60,10 @@ typedef enum {
  * and in both A_ii = 2 sqrt(area_i/pi)/(4 pi) sqrt(pi) + 1. */
 typedef enum { HLU_KERNEL_LAPLACE3D_WEIGHTED = 0, HLU_KERNEL_LAPLACE3D_POINT = 1 } hlu_kernel;
 
-/* FP64: all factors FP64.  MIXED: low-rank factors stored in FP32 and their
- * triangular solves and products computed in FP32; dense leaves, pivoting,
- * the truncation cores and the refinement residual stay FP64. */
+/* FP64: all factors FP64.  MIXED: the factors of low-rank blocks and the
+ * H-GEMM product panels are stored in FP32 (loaded and converted to FP64
+ * for the arithmetic); dense leaves, pivoting, the dense near field, the
+ * truncation cores and the refinement residual are FP64 throughout. */
 typedef enum { HLU_PREC_FP64 = 0, HLU_PREC_MIXED = 1 } hlu_precision;
 
 typedef struct {
@@ -70,7 +71,8 @@ typedef struct {
     double eta;               /* admissibility: min(diam) <= eta * dist (Sec. 2) */
     int leaf_size;            /* C_lf of Algorithm 1: split while size > C_lf   */
     int fixed_rank;           /* > 0: every truncation keeps this rank          */
-    double eps_factor;        /* truncation tolerance of the factored copy      */
+    double eps_factor;        /* truncation tolerance of the factored copy,
+                                 in [1e-8, 1) unless fixed_rank > 0            */
     int rank_cap_factor;      /* rank capacity of the factored copy (<= 32)     */
     double eps_matvec;        /* tolerance of the refinement operator copy      */
     int rank_cap_matvec;      /* rank capacity of that copy (<= 64); 0: no copy
@@ -110,7 +112,10 @@ typedef struct {
  * recompression to eps_factor and eps_matvec), and build the static op
  * schedule of the factorisation, the solve and the matvec.
  * Returns HLU_ERR_ARG for NULL pointers, n < 1, non-finite input, leaf < 1,
- * eta < 0, caps outside [1,32] / [1,64] or max_nrhs outside [1,64]. */
+ * eta < 0, caps outside [1,32] / [1,64], max_nrhs outside [1,64], or
+ * eps_factor below 1e-8 without fixed_rank (the device truncation forms FP64
+ * Gram matrices of the stacked factors, which resolve singular values only
+ * down to about 1e-8 of the largest). */
 hlu_status hlu_plan(const double* xyz, const double* area, int64_t n,
                     const hlu_params* p, hlu_handle* out);
 
@@ -232,12 +237,22 @@ void hlu_batch_destroy(hlu_batch b);
 hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
                      int64_t ld, void* stream);
 
+/* Refinement settings of this handle's later hlu_solve calls (initially
+ * refine_tol / refine_max_iter of its parameters): refine_tol = 0 gives the
+ * plain solve with the factors.  HLU_ERR_ARG for refine_tol < 0,
+ * refine_max_iter outside [0, 15], or refine_tol > 0 on a handle planned
+ * without the operator copy. */
+hlu_status hlu_set_refinement(hlu_handle h, double refine_tol, int refine_max_iter);
+
 /* y = A_mv x with the matvec copy (original order, n x nrhs). */
 hlu_status hlu_matvec(hlu_handle h, const double* x_dev, double* y_dev, int nrhs,
                       int64_t ld, void* stream);
 
 /* Wait for the stream work of this handle and report device-side status:
- * HLU_ERR_SINGULAR (info set) or HLU_ERR_NOT_CONVERGED from the last solve. */
+ * HLU_ERR_DEVICE if the dataflow executor stopped (time limit or queue
+ * overflow) in the last factorisation or in any solve sweep of the last
+ * hlu_solve, else HLU_ERR_SINGULAR (info set), else HLU_ERR_NOT_CONVERGED
+ * from the last solve. */
 hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out);
 
 /* Host-side check of the schedules and matvec tables (every panel inside

@@ -84,6 +84,7 @@ _sig = {
     "hlu_batch_destroy": (None, [_P]),
     "hlu_factor_profile": (C.c_int, [_P, _P, _P, _P]),
     "hlu_set_graph": (C.c_int, [_P, C.c_int]),
+    "hlu_set_refinement": (C.c_int, [_P, C.c_double, C.c_int]),
     "hlu_set_executor": (C.c_int, [_P, C.c_int]),
     "hlu_factor_records": (C.c_int, [_P, _P, _P]),
     "hlu_factor_graph": (C.c_int, [_P, _P, _P, _P]),
@@ -226,6 +227,10 @@ class HLU:
     def bind_and_assemble(self, stream=None):
         self.bind()
         _check(lib.hlu_assemble(self.h, _stream(stream)))
+
+    def set_refinement(self, tol, max_iter=10):
+        """Refinement target of later solves (0: the plain solve)."""
+        _check(lib.hlu_set_refinement(self.h, float(tol), int(max_iter)))
 
     def set_graph(self, enable):
         _check(lib.hlu_set_graph(self.h, int(bool(enable))))

@@ -24,6 +24,7 @@ extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, dou
 extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
                                         int n, int nrhs, double* out, hipStream_t s);
 extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s);
+extern "C" hipError_t hlu_launch_keep_flag(const int32_t* src, int32_t* dst, hipStream_t s);
 extern "C" hipError_t hlu_launch_axpy_masked(const double* d, double* x, int ld, int n, int nrhs,
                                              const int32_t* active, hipStream_t s);
 extern "C" hipError_t hlu_launch_wave(const void* ops, int count, size_t lds, hipStream_t s);
@@ -277,6 +278,8 @@ struct hlu_handle_s {
   double eta_hist[16] = {0};
   double eta_final = 0.0;
   bool not_converged = false;
+  double refine_tol = 0.0;            // refinement target of hlu_solve (0: none)
+  int refine_max_iter = 0;
   hlu_params params;
   bool use_graph = true;
   int executor = 0;                   // 0: waves, 1: dataflow
@@ -324,6 +327,11 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
     return fail(HLU_ERR_ARG, "fixed_rank must be in [0, rank_cap_factor]");
   if (p->fixed_rank == 0 && !(p->eps_factor > 0 && p->eps_factor < 1))
     return fail(HLU_ERR_ARG, "eps_factor must be in (0, 1)");
+  // the device truncation orthogonalises the stacked factors through FP64
+  // Gram matrices, which resolve singular values only down to about 1e-8 of
+  // the largest: tighter tolerances would be met in name only
+  if (p->fixed_rank == 0 && p->eps_factor < 1e-8)
+    return fail(HLU_ERR_ARG, "eps_factor must be >= 1e-8 (FP64 Gram truncation)");
   if (p->rank_cap_matvec > 0 && !(p->eps_matvec > 0 && p->eps_matvec < 1))
     return fail(HLU_ERR_ARG, "eps_matvec must be in (0, 1)");
   if (p->max_nrhs < 1 || p->max_nrhs > 64) return fail(HLU_ERR_ARG, "max_nrhs must be in [1, 64]");
@@ -340,6 +348,8 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
     return fail(HLU_ERR_NOMEM, "host allocation failed");
   }
   h->params = *p;
+  h->refine_tol = p->refine_tol;
+  h->refine_max_iter = p->refine_max_iter;
   hlu::Params prm;
   prm.kernel = p->kernel;
   prm.eta = p->eta;
@@ -378,6 +388,8 @@ hlu_status hlu_clone(hlu_handle src, hlu_handle* out) {
     return fail(HLU_ERR_NOMEM, "host allocation failed");
   }
   h->params = src->params;
+  h->refine_tol = src->refine_tol;
+  h->refine_max_iter = src->refine_max_iter;
   h->use_graph = src->use_graph;
   h->executor = src->executor;
   h->workers = src->workers;
@@ -725,10 +737,23 @@ static hlu_status run_dataflow(hlu_handle h, const DfArrays& da, hipStream_t s,
   return HLU_OK;
 }
 
+// Word of the status region that keeps the first error flag any solve
+// sweep of the current hlu_solve raised (every dataflow launch clears its
+// own control words, so a later sweep would otherwise hide an earlier one).
+static int32_t* solve_error_word(hlu_handle h) {
+  return (int32_t*)(h->base + h->plan.off_status + 8);
+}
+
 // One forward/backward sweep of the solve schedule (Y := A_H^{-1} Y).
 static hlu_status run_solve(hlu_handle h, hipStream_t s) {
   hlu::Plan& p = h->plan;
-  if (h->executor == 1) return run_dataflow(h, df_solve(p), s, &h->graph_dfs);
+  if (h->executor == 1) {
+    hlu_status st = run_dataflow(h, df_solve(p), s, &h->graph_dfs);
+    if (st != HLU_OK) return st;
+    HIPCHK(hlu_launch_keep_flag((const int32_t*)(h->base + p.off_dfs_ctrl + 8),
+                                solve_error_word(h), s));
+    return HLU_OK;
+  }
   return run_schedule(h, p.ssched, p.off_ops_s, s, nullptr, &h->graph_s);
 }
 
@@ -814,6 +839,19 @@ hlu_status hlu_set_priorities(hlu_handle h, double slack_frac, int high_workers,
   h->high_workers = nh > 0 ? high_workers : 0;
   h->drop_graphs();
   if (n_flagged) *n_flagged = nh;
+  return HLU_OK;
+}
+
+hlu_status hlu_set_refinement(hlu_handle h, double refine_tol, int refine_max_iter) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (!(refine_tol >= 0.0) || !std::isfinite(refine_tol))
+    return fail(HLU_ERR_ARG, "refine_tol must be >= 0");
+  if (refine_max_iter < 0 || refine_max_iter > 15)
+    return fail(HLU_ERR_ARG, "refine_max_iter must be in [0, 15]");
+  if (refine_tol > 0.0 && h->plan.prm.cap_mv == 0)
+    return fail(HLU_ERR_ARG, "refinement needs the operator copy (rank_cap_matvec > 0)");
+  h->refine_tol = refine_tol;
+  h->refine_max_iter = refine_max_iter;
   return HLU_OK;
 }
 
@@ -1002,6 +1040,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
   double* B = (double*)(b + p.off_B);
   const int64_t* perm = (const int64_t*)(b + p.off_perm);
   HIPCHK(hlu_launch_set_int((int32_t*)(b + p.off_nrhs), nrhs, s));
+  HIPCHK(hlu_launch_set_int(solve_error_word(h), 0, s));
   HIPCHK(hlu_launch_vec(0, b_dev, ld, B, n, perm, n, nrhs, s));        // B = P b
   HIPCHK(hlu_launch_vec(3, B, n, Y, n, nullptr, n, nrhs, s));          // Y = B
   hlu_status st = run_solve(h, s);
@@ -1010,7 +1049,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
   h->iters = 0;
   h->not_converged = false;
   h->eta_final = 0.0;
-  const double tol = p.prm.refine_tol;
+  const double tol = h->refine_tol;
   if (tol > 0.0) {
     // Each column is refined until its own backward error meets the
     // tolerance and is left alone afterwards, so a column's result does not
@@ -1019,12 +1058,16 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
     int32_t* active_dev = (int32_t*)(out + 3 * p.prm.max_nrhs);
     std::vector<double> mx(3 * nrhs);
     std::vector<int32_t> active(nrhs);
+    int32_t sweep_err = 0;
     for (int it = 0;; ++it) {
       st = run_mv(h, X, B, 1.0, -1.0, Y, nrhs, s);                       // Y = B - A X
       if (st != HLU_OK) return st;
       HIPCHK(hlu_launch_colmax(Y, X, B, n, n, nrhs, out, s));
       HIPCHK(hipMemcpyAsync(mx.data(), out, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&sweep_err, solve_error_word(h), 4, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      // a failed sweep leaves Y undefined: stop refining (hlu_sync reports it)
+      if (sweep_err) break;
       double eta = 0.0;
       for (int j = 0; j < nrhs; ++j) {
         double den = h->anorm * mx[3 * j + 1] + mx[3 * j + 2];
@@ -1038,7 +1081,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
       if (it < 16) h->eta_hist[it] = eta;
       h->eta_final = eta;
       if (eta <= tol) break;
-      if (it >= p.prm.refine_max_iter) { h->not_converged = true; break; }
+      if (it >= h->refine_max_iter) { h->not_converged = true; break; }
       HIPCHK(hipMemcpyAsync(active_dev, active.data(), sizeof(int32_t) * nrhs,
                             hipMemcpyHostToDevice, s));
       st = run_solve(h, s);                                              // Y = A_H^{-1} Y
@@ -1087,7 +1130,7 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
     if (st > 0) inf.info = h->plan.perm[st - 1] + 1;
     HIPCHK(hipMemcpy(&df_error, h->base + h->plan.off_df_ctrl + 8, 4, hipMemcpyDeviceToHost));
     if (!df_error)
-      HIPCHK(hipMemcpy(&df_error, h->base + h->plan.off_dfs_ctrl + 8, 4, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(&df_error, solve_error_word(h), 4, hipMemcpyDeviceToHost));
   }
   inf.iters = h->iters;
   for (int i = 0; i < 16; ++i) inf.eta_hist[i] = h->eta_hist[i];

@@ -1761,7 +1761,8 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
     // rank rule.  Squaring M is harmless at eps >= 1e-6 (FP64 Gram).
     int jc = ry;
     double tail0 = 0.0;
-    if (fixed == 0 && eps >= 1e-6 && rx > 8 && ry > 8) {
+    const bool reduced = fixed == 0 && eps >= 1e-6 && rx > 8 && ry > 8;
+    if (reduced) {
       {
         // G = M M^T (rx x rx): tiles on and above the diagonal, mirrored
         const int l = tid & 63;
@@ -1911,8 +1912,19 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
     if (tid == 0) *gptr<int32_t>(U.rankp) = k;
     __threadfence_block();
     __syncthreads();
-    flops += 2.0 * (m + n) * K * K - 4.0 * K * K * K / 3.0 + 2.0 * K * K * K +
-             21.0 * K * K * K + 2.0 * (m + n) * K * k;
+    // work of this pass at the sizes it actually ran: the Grams (symmetric
+    // halves) and their pivoted Cholesky, M = R S^T, the optional reduction
+    // (M M^T and its stopped Cholesky), the Jacobi rotations executed (12 rx
+    // flops per column pair and sweep), the small Tx / Ty products and
+    // triangular solve, and the recombination of the new factors
+    {
+      const double dK = K, dm = m + n, drx = rx, dry = ry, djc = jc;
+      double f = dm * dK * (dK + 1.0) + 2.0 * dK * dK * dK / 3.0 + 2.0 * drx * dry * dK;
+      if (reduced) f += drx * (drx + 1.0) * dry + drx * djc * djc;
+      f += 6.0 * drx * djc * (djc - 1.0) * sweeps;
+      f += 2.0 * drx * dK * k + drx * drx * k + 2.0 * dm * dK * k;
+      flops += f;
+    }
     bytes += es * (double)(m + n) * (K + k);
   }
   // detail: passes, Jacobi sweeps, largest Cholesky ranks of the two sides
@@ -2422,6 +2434,9 @@ __global__ void __launch_bounds__(NT) k_colmax(const double* R, const double* X,
   if (tid < 3) out[3 * j + tid] = red[tid][0];
 }
 
+__global__ void k_keep_flag(const int32_t* src, int32_t* dst) {
+  if (threadIdx.x == 0 && *src != 0 && *dst == 0) *dst = *src;
+}
 __global__ void k_set_int(int32_t* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -3054,6 +3069,11 @@ extern "C" hipError_t hlu_launch_axpy_masked(const double* d, double* x, int ld,
 extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
                                         int n, int nrhs, double* out, hipStream_t s) {
   hipLaunchKernelGGL(hlu::k_colmax, dim3(nrhs), dim3(NT), 0, s, R, X, B, ld, n, out);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t hlu_launch_keep_flag(const int32_t* src, int32_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(hlu::k_keep_flag, dim3(1), dim3(64), 0, s, src, dst);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def test_plan_eta_zero_has_no_lowrank_blocks():
 @pytest.mark.parametrize("bad", [
     dict(leaf=0), dict(leaf=65), dict(eta=-1.0), dict(cap=0), dict(cap=33),
     dict(cap_mv=65), dict(eps=0.0), dict(eps=1.5), dict(max_nrhs=0), dict(max_nrhs=65),
-    dict(fixed_rank=40), dict(eps_mv=0.0),
+    dict(fixed_rank=40), dict(eps_mv=0.0), dict(eps=1e-9), dict(eps=1e-10),
 ])
 def test_plan_argument_errors(bad):
     P = _lib()
@@ -135,3 +135,28 @@ def test_schedule_validates(level, leaf, prec, fixed):
     xyz, area = icosphere(level)
     h = P.HLU(xyz, area, assemble=False, leaf=leaf, precision=prec, fixed_rank=fixed)
     h.validate()
+
+
+def test_plan_tight_eps_accepted_with_fixed_rank_and_at_limit():
+    """eps_factor below 1e-8 is refused only for tolerance-driven
+    truncation: a fixed-rank plan ignores it, and 1e-8 itself is accepted."""
+    P = _lib()
+    xyz, area = icosphere(1)
+    P.HLU(xyz, area, assemble=False, eps=1e-8)
+    P.HLU(xyz, area, assemble=False, eps=1e-12, fixed_rank=4)
+
+
+def test_set_refinement_arguments():
+    P = _lib()
+    xyz, area = icosphere(1)
+    h = P.HLU(xyz, area, assemble=False, cap_mv=64, refine_tol=1e-10)
+    h.set_refinement(0.0, 0)
+    h.set_refinement(1e-12, 15)
+    for tol, it in [(-1.0, 3), (1e-10, 16), (1e-10, -1), (float("nan"), 2)]:
+        with pytest.raises(P.HLUError) as e:
+            h.set_refinement(tol, it)
+        assert e.value.status == 1
+    h0 = P.HLU(xyz, area, assemble=False, cap_mv=0, refine_tol=0.0)
+    with pytest.raises(P.HLUError) as e:
+        h0.set_refinement(1e-10, 3)
+    assert e.value.status == 1
