@@ -60,10 +60,15 @@ typedef enum {
  * and in both A_ii = 2 sqrt(area_i/pi)/(4 pi) sqrt(pi) + 1. */
 typedef enum { HLU_KERNEL_LAPLACE3D_WEIGHTED = 0, HLU_KERNEL_LAPLACE3D_POINT = 1 } hlu_kernel;
 
-/* FP64: all factors FP64.  MIXED: the factors of low-rank blocks and the
- * H-GEMM product panels are stored in FP32 (loaded and converted to FP64
- * for the arithmetic); dense leaves, pivoting, the dense near field, the
- * truncation cores and the refinement residual are FP64 throughout. */
+/* FP64: all factors and all arithmetic FP64.  MIXED: the factors of
+ * low-rank blocks and the H-GEMM product panels are stored in FP32, and the
+ * operations that produce them run in FP32: panel products into an FP32
+ * panel on the FP32 matrix cores with FP32 accumulation (FP64 near-field
+ * operands rounded to FP32), leaf triangular solves on FP32 panels in FP32,
+ * and the low-rank part of dense-block updates as an FP32 matrix-core
+ * product subtracted in FP64.  Diagonal-leaf LU and pivoting, the dense
+ * near field, the truncation (FP64 Gram, Cholesky and SVD core from the
+ * FP32 panels) and the refinement residual stay FP64. */
 typedef enum { HLU_PREC_FP64 = 0, HLU_PREC_MIXED = 1 } hlu_precision;
 
 typedef struct {
@@ -150,6 +155,26 @@ hlu_status hlu_clone(hlu_handle src, hlu_handle* out);
  * the two do not share a plan, HLU_ERR_STATE if h is unbound or src is not
  * assembled. */
 hlu_status hlu_assemble_from(hlu_handle h, hlu_handle src, void* stream);
+
+/* Replace the assembled blocks of the factored copy (and of its pristine
+ * copy, so hlu_reset restores them) by the blocks of an H-matrix built
+ * elsewhere on the same cluster and block trees (Algorithms 1 and 2), e.g.
+ * by the CPU oracle, so that two factorisations of one A_H can be compared
+ * (test path).  Synchronous (the null stream); the handle must be bound and
+ * assembled (the refinement operator copy and ||A||_inf stay the handle's
+ * own); afterwards the handle is unfactored.
+ * File (host path, little-endian):
+ *   char magic[8] = "HLUBLK01"; int64 n; int64 nblocks;
+ *   int64 perm[n]              cluster position -> original point index
+ *   nblocks times: int64 r0, c0, m, nc, kind, k
+ *                  (rows r0..r0+m-1 and columns c0..c0+nc-1 in cluster
+ *                  order; kind 0 dense, 1 low-rank of rank k)
+ *     dense:    double F[m*nc] column-major
+ *     low-rank: double U[m*k], double V[nc*k] column-major (block = U V^T)
+ * Returns HLU_ERR_ARG when the file cannot be read, its permutation, block
+ * set, shapes or kinds differ from the handle's trees, or a rank exceeds
+ * rank_cap_factor; HLU_ERR_STATE when unbound or unassembled. */
+hlu_status hlu_import_blocks(hlu_handle h, const char* path);
 
 /* Workgroups of the dataflow executor for this handle's factor and solve
  * launches: 0 (the default) one per compute unit; a smaller count leaves
@@ -330,12 +355,14 @@ hlu_status hlu_getrf_batched(double* a_dev, int32_t* piv_dev, int32_t* info_dev,
                              int b, int count, void* stream);
 
 /* Best low-rank approximation of C - X Y^T (Sec. 3.1, truncated addition):
- * U (m x kc), V (n x kc) hold C = U V^T on entry (kc <= 32); X (m x kx),
- * Y (n x ky=kx) the update, kc + kx <= 64.  On exit U, V (capacity cap
+ * U (m x kc), V (n x kc) hold C = U V^T on entry (kc <= cap <= 32); X
+ * (m x kx), Y (n x kx) the update, kx <= 16 (64 - cap) (the update is taken
+ * in passes whose stacked width stays <= 64).  On exit U, V (capacity cap
  * columns, leading dimensions m and n) hold the truncated result and
  * *rank_dev its rank; fixed_rank > 0 keeps that rank, otherwise the
  * smallest rank whose discarded singular values have Frobenius norm <=
- * eps times the norm of the sum, capped at cap.  All FP64. */
+ * eps times the norm of the sum, capped at cap.  All FP64.  Allocates a
+ * device descriptor buffer and synchronises the stream before returning. */
 hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev,
                             const double* X_dev, const double* Y_dev, int m, int n,
                             int kc, int kx, int cap, double eps, int fixed_rank,

@@ -100,6 +100,7 @@ _sig = {
     "hlu_get_perm": (C.c_int, [_P, _P]),
     "hlu_export_factors": (C.c_int, [_P, _P, _P, _P]),
     "hlu_export_pivots": (C.c_int, [_P, _P, _P]),
+    "hlu_import_blocks": (C.c_int, [_P, C.c_char_p]),
     "hlu_destroy": (None, [_P]),
     "hlu_last_error": (C.c_char_p, []),
     "hlu_getrf_batched": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
@@ -172,6 +173,11 @@ class HLU:
 
     def assemble_from(self, src, stream=None):
         _check(lib.hlu_assemble_from(self.h, src.h, _stream(stream)))
+
+    def import_blocks(self, path):
+        """Replace the factored copy's blocks by those of a block file
+        (format in include/hlu.h), e.g. the oracle's A_H."""
+        _check(lib.hlu_import_blocks(self.h, str(path).encode()))
 
     def set_workers(self, workers):
         """Dataflow workgroups per launch (0: one per compute unit)."""

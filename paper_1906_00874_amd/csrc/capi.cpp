@@ -5,9 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <memory>
 #include <vector>
 
@@ -621,6 +623,87 @@ hlu_status hlu_assemble_from(hlu_handle h, hlu_handle src, void* stream) {
   HIPCHK(hlu_launch_set_int((int32_t*)(b + p.off_status), 0, s));
   h->anorm = src->anorm;
   h->assembled = true;
+  h->factored = false;
+  return HLU_OK;
+}
+
+// Blocks of an H-matrix built elsewhere (the file format is declared in
+// hlu.h): every leaf block of this handle's block tree is replaced, in the
+// factored copy and its pristine copy, by the file's block of the same rows
+// and columns.  The refinement operator copy keeps the handle's own blocks.
+namespace {
+struct ImportFile {
+  FILE* f = nullptr;
+  ~ImportFile() { if (f) std::fclose(f); }
+  bool read(void* dst, size_t bytes) { return std::fread(dst, 1, bytes, f) == bytes; }
+};
+}  // namespace
+
+hlu_status hlu_import_blocks(hlu_handle h, const char* path) {
+  if (!h || !path) return fail(HLU_ERR_ARG, "NULL argument");
+  hlu::Plan& p = h->plan;
+  ImportFile in;
+  in.f = std::fopen(path, "rb");
+  if (!in.f) return fail(HLU_ERR_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  int64_t hdr[2];
+  if (!in.read(magic, 8) || std::memcmp(magic, "HLUBLK01", 8) != 0)
+    return fail(HLU_ERR_ARG, "not an H-matrix block file (magic HLUBLK01)");
+  if (!in.read(hdr, sizeof(hdr))) return fail(HLU_ERR_ARG, "truncated header");
+  if (hdr[0] != p.n) return fail(HLU_ERR_ARG, "block file is for another n");
+  if (hdr[1] != (int64_t)p.blk.size())
+    return fail(HLU_ERR_ARG, "block file has another number of leaf blocks");
+  std::vector<int64_t> perm(p.n);
+  if (!in.read(perm.data(), sizeof(int64_t) * p.n)) return fail(HLU_ERR_ARG, "truncated permutation");
+  if (perm != p.perm) return fail(HLU_ERR_ARG, "block file was built on another cluster tree");
+  std::unordered_map<uint64_t, int> at;
+  for (size_t i = 0; i < p.blk.size(); ++i) {
+    const hlu::LBlock& b = p.blk[i];
+    at[((uint64_t)p.cl[b.t].off << 32) | (uint64_t)p.cl[b.s].off] = (int)i;
+  }
+  std::vector<char> img(p.size_work, 0);
+  std::vector<char> seen(p.blk.size(), 0);
+  std::vector<double> buf;
+  const int cap = p.prm.cap_f;
+  for (size_t q = 0; q < p.blk.size(); ++q) {
+    int64_t d[6];
+    if (!in.read(d, sizeof(d))) return fail(HLU_ERR_ARG, "truncated block header");
+    const int64_t r0 = d[0], c0 = d[1], m = d[2], nc = d[3], kind = d[4], k = d[5];
+    if (r0 < 0 || c0 < 0 || r0 >= p.n || c0 >= p.n)
+      return fail(HLU_ERR_ARG, "block offset out of range");
+    auto it = at.find(((uint64_t)r0 << 32) | (uint64_t)c0);
+    if (it == at.end()) return fail(HLU_ERR_ARG, "block not in this block tree");
+    const hlu::LBlock& b = p.blk[it->second];
+    if (seen[it->second]) return fail(HLU_ERR_ARG, "block given twice");
+    seen[it->second] = 1;
+    if (m != b.m || nc != b.n) return fail(HLU_ERR_ARG, "block shape differs from the block tree");
+    if (kind != (b.kind == 'R' ? 1 : 0)) return fail(HLU_ERR_ARG, "block kind differs (dense/low-rank)");
+    if (kind == 0) {
+      buf.resize((size_t)m * nc);
+      if (!in.read(buf.data(), 8 * buf.size())) return fail(HLU_ERR_ARG, "truncated dense block");
+      std::memcpy(img.data() + (b.offF - p.off_work), buf.data(), 8 * buf.size());
+      continue;
+    }
+    if (k < 0 || k > cap) return fail(HLU_ERR_ARG, "rank above the rank capacity");
+    *(int32_t*)(img.data() + (b.offRank - p.off_work)) = (int32_t)k;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t rows = side ? nc : m;
+      buf.resize((size_t)rows * k);
+      if (!in.read(buf.data(), 8 * buf.size())) return fail(HLU_ERR_ARG, "truncated factor");
+      char* dst = img.data() + ((side ? b.offV : b.offU) - p.off_work);
+      if (p.prm.mixed) {
+        float* f = (float*)dst;
+        for (size_t e = 0; e < buf.size(); ++e) f[e] = (float)buf[e];
+      } else {
+        std::memcpy(dst, buf.data(), 8 * buf.size());
+      }
+    }
+  }
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first (the operator copy)");
+  HIPCHK(hipMemcpy(h->base + p.off_work, img.data(), p.size_work, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->base + p.off_pristine, img.data(), p.size_work, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(h->base + p.off_status, 0, 256));
   h->factored = false;
   return HLU_OK;
 }

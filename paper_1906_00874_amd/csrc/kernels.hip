@@ -189,6 +189,47 @@ __device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// FP32 matrix-core step D += A B with A 16 x 4 and B 4 x 16 (one
+// wavefront): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and
+// its four results are D[4 (l / 16) + r][l % 16], r = 0..3 (the f64 step
+// above interleaves the result rows differently).
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4f mfma16x16x4f(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP32 counterparts of gload / gstore (mixed precision): FP64 storage is
+// rounded to FP32 as it is loaded, an identity panel is evaluated.  The
+// index rules of gload apply (every index inside the panel).
+template <int N>
+__device__ __forceinline__ void gloadf(const GView& g, const int (&i)[N], const int (&j)[N],
+                                       float (&v)[N]) {
+  if (g.ident) {
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      v[u] = (g.tr ? i[u] == j[u] + g.diag : j[u] == i[u] + g.diag) ? 1.0f : 0.0f;
+  } else if (g.f64) {
+    const HLU_G double* p = gptr<const double>(g.ptr);
+    double d[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) d[u] = p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj];
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = (float)d[u];
+  } else {
+    const HLU_G float* p = gptr<const float>(g.ptr);
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj];
+  }
+}
+template <int N>
+__device__ __forceinline__ void gstoref(const GView& g, const int (&i)[N], const int (&j)[N],
+                                        const bool (&ok)[N], const float (&v)[N]) {
+  HLU_G float* p = gptr<float>(g.ptr);
+#pragma unroll
+  for (int u = 0; u < N; ++u)
+    if (ok[u]) p[(int64_t)i[u] * g.si + (int64_t)j[u] * g.sj] = v[u];
+}
+
 // per-op record {model flops, algorithmic bytes, rank-capacity hit, rank,
 // start tick, end tick, stack width, 0} (ticks of the constant-rate wall
 // clock, written by thread 0)
@@ -388,6 +429,81 @@ __device__ __forceinline__ void trsm_cols(const GView& gy, const double (*l)[65]
   }
   gstore(gy, ri, cj, ok, v);
 }
+// The same column solve on an FP32 panel (mixed precision) in FP32
+// arithmetic: the leaf's entries are rounded to FP32 as they are read, and
+// x_k crosses lanes as one 32-bit readlane.
+template <int TYPE, int NC>
+__device__ __forceinline__ void trsm_cols_f32(const GView& gy, const double (*l)[65],
+                                              const double* dinv, const int* pm, int b, int c,
+                                              int q0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ncw = (c - w + 3) >> 2;
+  const int nq = min(NC, ncw - q0);
+  const int il = min(lane, b - 1);
+  int ri[NC], cj[NC];
+  bool ok[NC];
+  float v[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    ri[t] = TYPE == OP_TRSM_L ? pm[il] : il;
+    cj[t] = w + 4 * (q0 + min(t, nq - 1));
+  }
+  gloadf(gy, ri, cj, v);
+  if (TYPE == OP_TRSM_U) {
+    float lk = (float)l[lane][b - 1];
+    for (int k = b - 1; k >= 0; --k) {
+      const float lnext = (float)l[lane][k > 0 ? k - 1 : 0];
+      const float dk = (float)dinv[k];
+#pragma unroll
+      for (int t = 0; t < NC; ++t) {
+        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[t]), k)) * dk;
+        v[t] = lane == k ? xk : (lane < k ? v[t] - lk * xk : v[t]);
+      }
+      lk = lnext;
+    }
+  } else {
+    float lk = (float)(TYPE == OP_TRSM_UT ? l[0][lane] : l[lane][0]);
+    for (int k = 0; k < b; ++k) {
+      const int kn = k + 1 < b ? k + 1 : k;
+      const float lnext = (float)(TYPE == OP_TRSM_UT ? l[kn][lane] : l[lane][kn]);
+      if (TYPE == OP_TRSM_L) {
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[t]), k));
+          v[t] = (lane > k && lane < b) ? v[t] - lk * xk : v[t];
+        }
+      } else {
+        const float dk = (float)dinv[k];
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          const float xk =
+              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[t]), k)) * dk;
+          v[t] = lane == k ? xk : ((lane > k && lane < b) ? v[t] - lk * xk : v[t]);
+        }
+      }
+      lk = lnext;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    ok[t] = lane < b && t < nq;
+    ri[t] = il;
+  }
+  gstoref(gy, ri, cj, ok, v);
+}
+template <int TYPE>
+__device__ __forceinline__ void trsm_lanes_f32(const GView& gy, const double (*l)[65],
+                                               const double* dinv, const int* pm, int b, int c) {
+  const int ncw = (c + 3) >> 2;
+  if (ncw <= 2) {
+    if ((threadIdx.x >> 6) < c) trsm_cols_f32<TYPE, 2>(gy, l, dinv, pm, b, c, 0);
+  } else if (ncw <= 4) {
+    trsm_cols_f32<TYPE, 4>(gy, l, dinv, pm, b, c, 0);
+  } else {
+    const int w = threadIdx.x >> 6, mine = (c - w + 3) >> 2;
+    for (int q0 = 0; q0 < mine; q0 += 8) trsm_cols_f32<TYPE, 8>(gy, l, dinv, pm, b, c, q0);
+  }
+}
 template <int TYPE>
 __device__ __forceinline__ void trsm_lanes(const GView& gy, const double (*l)[65],
                                            const double* dinv, const int* pm, int b, int c) {
@@ -447,9 +563,15 @@ __device__ __forceinline__ void trsm_body(const Op& op) {
   __syncthreads();
   const GView gy = gview(Y);
   if (b > 0 && c > 0) {
-    if (type == OP_TRSM_L) trsm_lanes<OP_TRSM_L>(gy, l, dinv, pm, b, c);
-    else if (type == OP_TRSM_UT) trsm_lanes<OP_TRSM_UT>(gy, l, dinv, pm, b, c);
-    else trsm_lanes<OP_TRSM_U>(gy, l, dinv, pm, b, c);
+    if (Y.dt == DT_F32) {
+      if (type == OP_TRSM_L) trsm_lanes_f32<OP_TRSM_L>(gy, l, dinv, pm, b, c);
+      else if (type == OP_TRSM_UT) trsm_lanes_f32<OP_TRSM_UT>(gy, l, dinv, pm, b, c);
+      else trsm_lanes_f32<OP_TRSM_U>(gy, l, dinv, pm, b, c);
+    } else {
+      if (type == OP_TRSM_L) trsm_lanes<OP_TRSM_L>(gy, l, dinv, pm, b, c);
+      else if (type == OP_TRSM_UT) trsm_lanes<OP_TRSM_UT>(gy, l, dinv, pm, b, c);
+      else trsm_lanes<OP_TRSM_U>(gy, l, dinv, pm, b, c);
+    }
   }
   const double es = Y.dt == DT_F64 ? 8.0 : 4.0;
   put_cost(op, (double)b * b * c, 8.0 * b * b / 2 + 2.0 * es * b * c);
@@ -686,6 +808,178 @@ __device__ __forceinline__ void pgemm_narrow_lr(const PRef& A, const PRef& B, co
   }
 }
 
+// ---- FP32 panel products (mixed precision: the output panel is FP32)
+// Y[:, c0:c0+c) += sg A (B^T X[:, c0:c0+c)) for rank k <= 32 (A: m x k,
+// B: r x k, X: r x ., Y: m x ., c <= 16; FP32 storage, FP64 storage rounded
+// to FP32 on load), on the FP32 matrix cores with FP32 accumulation:
+//  1. T^T = X^T B over the rows in 64-row chunks staged in LDS: wavefront g
+//     takes the rows 16g .. 16g + 15 of each chunk (one or two 16 x 16 tiles
+//     of T^T), the next chunk loads while the current one is multiplied, and
+//     the four partials meet in LDS;
+//  2. Y^T = T^T A^T by 16-row tiles of Y (tile t to wavefront t % 4): A's
+//     rows are read straight from memory in the operand layout (sixteen
+//     consecutive rows of one column per load) and Y is updated in place.
+#define PGF_LR_FLT (64 * 33 + 64 * 17 + 4 * 16 * 33 + 16 * 33)
+__device__ __forceinline__ void pgemm_lr_f32(const PRef& A, const PRef& B, const PRef& X,
+                                             const PRef& Y, int m, int c0, int c, int k,
+                                             float sg) {
+  float* const sb = reinterpret_cast<float*>(hlu_lds);   // [64][33]: B chunk
+  float* const sx = sb + 64 * 33;                        // [64][17]: X chunk
+  float* const red = sx + 64 * 17;                       // [4][16][33]: partials
+  float* const st = red + 4 * 16 * 33;                   // [16][33]: T^T
+  const GView ga = gview(A), gb = gview(B), gx = gview(X), gy = gview(Y);
+  const int r = X.rows;
+  const int tid = threadIdx.x, g = tid >> 6, l = tid & 63, lo = l & 15, hi = l >> 4;
+  {
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    float pb[8], px[4];
+    auto fetch = [&](int r0) {
+      int ri[8], cb[8], rx[4], cx[4];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + NT * u;
+        ri[u] = min(r0 + (e & 63), r - 1);
+        cb[u] = min(e >> 6, k - 1);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + NT * u;
+        rx[u] = min(r0 + (e & 63), r - 1);
+        cx[u] = c0 + min(e >> 6, c - 1);
+      }
+      gloadf(gb, ri, cb, pb);
+      gloadf(gx, rx, cx, px);
+    };
+    if (r > 0) fetch(0);
+    for (int r0 = 0; r0 < r; r0 += 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + NT * u, i = e & 63, j = e >> 6;
+        sb[i * 33 + j] = (r0 + i < r && j < k) ? pb[u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + NT * u, i = e & 63, j = e >> 6;
+        sx[i * 17 + j] = (r0 + i < r && j < c) ? px[u] : 0.f;
+      }
+      __syncthreads();
+      if (r0 + 64 < r) fetch(r0 + 64);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * g + 4 * q + hi;
+        const float a = sx[row * 17 + lo];
+        acc0 = mfma16x16x4f(a, sb[row * 33 + lo], acc0);
+        if (k > 16) acc1 = mfma16x16x4f(a, sb[row * 33 + 16 + lo], acc1);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      red[(g * 16 + 4 * hi + q) * 33 + lo] = acc0[q];
+      red[(g * 16 + 4 * hi + q) * 33 + 16 + lo] = acc1[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + NT * u, i = e >> 5, j = e & 31;
+      st[i * 33 + j] = red[i * 33 + j] + red[(16 + i) * 33 + j] + red[(32 + i) * 33 + j] +
+                       red[(48 + i) * 33 + j];
+    }
+    __syncthreads();
+  }
+  const int nk = (k + 3) >> 2;
+  for (int t = g; 16 * t < m; t += 4) {
+    const int row = 16 * t + lo;
+    int ri[8], cj[8], yr[4], yc[4];
+    bool ok[4];
+    float av[8], yv[4];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      ri[q] = min(row, m - 1);
+      cj[q] = min(4 * q + hi, k - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yr[q] = min(row, m - 1);
+      yc[q] = c0 + min(4 * hi + q, c - 1);
+      ok[q] = row < m && 4 * hi + q < c;
+    }
+    gloadf(ga, ri, cj, av);
+    gloadf(gy, yr, yc, yv);
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nk) {
+        const int kk = 4 * q + hi;
+        acc = mfma16x16x4f(st[lo * 33 + kk], kk < k ? av[q] : 0.f, acc);
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yv[q] += sg * acc[q];
+    gstoref(gy, yr, yc, ok, yv);
+  }
+}
+
+// Y[:, c0:c0+c) += sg op(M) X[:, c0:c0+c) for a dense M (m x r, any
+// storage, rounded to FP32) and an FP32 output panel, c <= 16: per 64-row
+// block of Y and 64-deep chunk of the inner dimension, the X chunk is staged
+// in LDS and wavefront g multiplies the rows 16g .. 16g + 15, reading M's
+// rows straight from memory in the operand layout (Y^T = X^T M^T).
+#define PGF_DENSE_FLT (64 * 17)
+__device__ __forceinline__ void pgemm_dense_f32(const Op& op, const PRef& X, const PRef& Y,
+                                                int m, int c0, int c, float sg) {
+  float* const sx = reinterpret_cast<float*>(hlu_lds);   // [64][17]
+  const GView gm = gview(op.p[0], op.i1 != 0), gx = gview(X), gy = gview(Y);
+  const int r = X.rows;
+  const int tid = threadIdx.x, g = tid >> 6, l = tid & 63, lo = l & 15, hi = l >> 4;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    const int row = r0 + 16 * g + lo;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    int yr[4], yc[4];
+    bool ok[4];
+    float yv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yr[q] = min(row, m - 1);
+      yc[q] = c0 + min(4 * hi + q, c - 1);
+      ok[q] = row < m && 4 * hi + q < c;
+    }
+    gloadf(gy, yr, yc, yv);
+    for (int k0 = 0; k0 < r; k0 += 64) {
+      const int d = min(64, r - k0);
+      float px[4], mv[16];
+      int rx[4], cx[4], mi[16], mj[16];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + NT * u;
+        rx[u] = k0 + min(e & 63, d - 1);
+        cx[u] = c0 + min(e >> 6, c - 1);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        mi[q] = min(row, m - 1);
+        mj[q] = k0 + min(4 * q + hi, d - 1);
+      }
+      gloadf(gx, rx, cx, px);
+      gloadf(gm, mi, mj, mv);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + NT * u, i = e & 63, j = e >> 6;
+        sx[i * 17 + j] = (i < d && j < c) ? px[u] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int kk = 4 * q + hi;
+        acc = mfma16x16x4f(sx[kk * 17 + lo], kk < d ? mv[q] : 0.f, acc);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yv[q] += sg * acc[q];
+    gstoref(gy, yr, yc, ok, yv);
+  }
+}
+
 __device__ __forceinline__ void pgemm_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef X = op.p[2];
@@ -698,6 +992,31 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
   const int m = Y.rows;
   const double esx = X.dt == DT_F64 ? 8.0 : 4.0;
   const double esy = Y.dt == DT_F64 ? 8.0 : 4.0;
+  if (Y.dt == DT_F32 && (op.i0 == 0 || kl <= 32)) {
+    // FP32 output panel (mixed precision): FP32 arithmetic on the matrix
+    // cores, 16 columns at a time
+    const int r = X.rows;
+    const bool tr = op.i1 != 0;
+    if (c > 0 && m > 0 && (op.i0 == 0 || kl > 0)) {
+      for (int c0 = 0; c0 < c; c0 += 16) {
+        const int cw = min(16, c - c0);
+        if (op.i0 == 0)
+          pgemm_dense_f32(op, X, Y, m, c0, cw, (float)sg);
+        else
+          pgemm_lr_f32(tr ? op.p[1] : op.p[0], tr ? op.p[0] : op.p[1], X, Y, m, c0, cw, kl,
+                       (float)sg);
+        __syncthreads();
+      }
+    }
+    if (op.i0 == 0) {
+      put_cost(op, 2.0 * m * r * c, 8.0 * m * r + esx * r * c + 2.0 * esy * m * c);
+    } else {
+      const double esm = op.p[0].dt == DT_F64 ? 8.0 : 4.0;
+      put_cost(op, 2.0 * (double)kl * c * (r + m),
+               esm * (double)kl * (r + m) + esx * r * c + 2.0 * esy * m * c);
+    }
+    return;
+  }
   if (c <= 16 && (op.i0 == 0 || kl <= 32)) {
     const int r = X.rows;
     if (op.i0 == 0) {
@@ -864,11 +1183,79 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
 // ---------------------------------------------------------------- dense update
 // p0 (FP64 dense, m x n) -= p1 p2^T
 #define LDS_ADDD (64 * 33 * 8 + 32 * 65 * 8)
+// Mixed precision, FP32 factors X (m x k) and Y (n x k): the product X Y^T
+// runs on the FP32 matrix cores with FP32 accumulation (C^T = Y X^T in
+// 16 x 16 tiles; wavefront g takes the columns 16g .. 16g + 15 of each
+// 64 x 64 block of C and its four row tiles, reading both factors straight
+// from memory in the operand layout), and is subtracted from the FP64
+// block in FP64.
+__device__ __forceinline__ void addd_f32(const PRef& C, const PRef& X, const PRef& Y, int m,
+                                         int n, int k) {
+  const GView gx = gview(X), gy = gview(Y), gc = gview(C);
+  const int tid = threadIdx.x, g = tid >> 6, l = tid & 63, lo = l & 15, hi = l >> 4;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int col0 = c0 + 16 * g;
+    for (int r0 = 0; r0 < m; r0 += 64) {
+      if (col0 >= n) continue;
+      v4f acc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < k; k0 += 32) {
+        float yv[8], xv[4][8];
+        int yi[8], yj[8], xi[8], xj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          yi[q] = min(col0 + lo, n - 1);
+          yj[q] = min(k0 + 4 * q + hi, k - 1);
+          xj[q] = yj[q];
+        }
+        gloadf(gy, yi, yj, yv);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xi[q] = min(r0 + 16 * t + lo, m - 1);
+          gloadf(gx, xi, xj, xv[t]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + 4 * q < k) {
+            const bool in = k0 + 4 * q + hi < k;
+            const float a = in ? yv[q] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mfma16x16x4f(a, in ? xv[t][q] : 0.f, acc[t]);
+          }
+      }
+      int ci[16], cj[16];
+      bool ok[16];
+      double v[16];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = r0 + 16 * t + lo, j = col0 + 4 * hi + q;
+          ci[4 * t + q] = min(i, m - 1);
+          cj[4 * t + q] = min(j, n - 1);
+          ok[4 * t + q] = i < m && j < n;
+        }
+      gload(gc, ci, cj, v);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[4 * t + q] -= (double)acc[t][q];
+      gstore(gc, ci, cj, ok, v);
+    }
+  }
+}
 __device__ __forceinline__ void addd_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef C = op.p[0], X = op.p[1], Y = op.p[2];
   const int m = C.rows, n = C.cols;
   const int k = pcols(X);
+  if (X.dt == DT_F32 && Y.dt == DT_F32 && X.kind == PK_MAT && Y.kind == PK_MAT) {
+    if (m > 0 && n > 0 && k > 0) addd_f32(C, X, Y, m, n, k);
+    put_cost(op, 2.0 * m * n * k, 16.0 * m * n + 4.0 * (double)k * (m + n));
+    return;
+  }
   double (*sa)[33] = reinterpret_cast<double (*)[33]>(smem);
   double (*sb)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 33 * 8);
   const int tid = threadIdx.x;

@@ -160,3 +160,45 @@ def test_set_refinement_arguments():
     with pytest.raises(P.HLUError) as e:
         h0.set_refinement(1e-10, 3)
     assert e.value.status == 1
+
+
+def test_import_blocks_checks_the_file_before_the_device(tmp_path):
+    """hlu_import_blocks: a file that does not match the handle's trees is
+    refused (HLU_ERR_ARG) before any device access; a matching file on an
+    unbound handle is HLU_ERR_STATE."""
+    from hblocks import write_blocks
+    P = _lib()
+    xyz, area = icosphere(3)
+    h = P.HLU(xyz, area, assemble=False, leaf=32, eta=2.0, eps=1e-6, cap=32)
+    H = O.HMatrix(xyz, area, 32, 2.0, O.Rule(eps=1e-6, cap=32))
+    good = tmp_path / "good.bin"
+    write_blocks(H, good)
+    with pytest.raises(P.HLUError) as e:
+        h.import_blocks(good)
+    assert e.value.status == 6
+    blocks = list(O.leaves_of(H.block))
+    cases = {
+        "magic": dict(magic=b"HLUBLK00"),
+        "perm": dict(perm=H.perm[::-1]),
+        "missing": dict(blocks=blocks[:-1]),
+        "twice": dict(blocks=blocks[:-1] + blocks[:1]),
+    }
+    for name, kw in cases.items():
+        f = tmp_path / f"{name}.bin"
+        write_blocks(H, f, **kw)
+        with pytest.raises(P.HLUError) as e:
+            h.import_blocks(f)
+        assert e.value.status == 1, name
+    # ranks above the handle's capacity
+    h8 = P.HLU(xyz, area, assemble=False, leaf=32, eta=2.0, eps=1e-6, cap=4)
+    with pytest.raises(P.HLUError) as e:
+        h8.import_blocks(good)
+    assert e.value.status == 1 and "capacity" in str(e.value)
+    # a handle on another tree (leaf 16)
+    h16 = P.HLU(xyz, area, assemble=False, leaf=16, eta=2.0, eps=1e-6, cap=32)
+    with pytest.raises(P.HLUError) as e:
+        h16.import_blocks(good)
+    assert e.value.status == 1
+    with pytest.raises(P.HLUError) as e:
+        h.import_blocks(tmp_path / "absent.bin")
+    assert e.value.status == 1

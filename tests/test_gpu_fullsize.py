@@ -60,6 +60,31 @@ def test_full_size_refined_solution_on_sampled_rows(full):
     _say("IR iters", inf.iters, "eta device", inf.eta_final, "eta exact sampled", eta)
     assert inf.eta_final <= 1e-10
     assert eta <= 1e-10
+    # the factor at eps 1e-5 contracts the error by ~kappa * 10 eps per
+    # step: one step reaches 1e-10 on this input, two allow for a slower
+    # column; more would mean a factor far worse than its bound
+    assert 1 <= inf.iters <= 2, inf.iters
+
+
+def test_full_size_unrefined_solve_operator_level(full):
+    """Factor accuracy at the operator level (|A - Lhat U| <= 10 eps |A|):
+    b = A_mv z with the FP64 refinement copy (eps 1e-12), one plain solve
+    without refinement; |x - z|_inf / |z|_inf <= kappa_inf * 10 eps with
+    kappa_inf <= 4 for this operator (I + single layer on the sphere)."""
+    torch, h, n, nrhs, rows, A_rows = full
+    z = rhs_normal(43, n, 4)
+    b = h.matvec(torch.tensor(z, device="cuda"))
+    h.set_refinement(0.0)
+    try:
+        _say("unrefined solve nrhs 4")
+        x = h.solve(b).cpu().numpy()
+        st, inf = h.sync(check=False)
+    finally:
+        h.set_refinement(1e-10, 10)
+    assert st == 0 and inf.iters == 0, (st, inf.iters)
+    rel = (np.abs(x - z).max(axis=0) / np.abs(z).max(axis=0)).max()
+    _say("unrefined forward error", rel)
+    assert rel <= 4 * 10 * 1e-5
 
 
 def test_full_size_matvec_on_sampled_rows(full):
