@@ -368,6 +368,25 @@ hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev,
                             int kc, int kx, int cap, double eps, int fixed_rank,
                             void* stream);
 
+/* hlu_truncate_add for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops): the same arguments and
+ * result, bit for bit, but no hipMalloc / hipFree or allocating call of any
+ * kind and no synchronisation -- it only launches kernels on `stream`.
+ * The truncation descriptor and its term table are built by a kernel in a
+ * static device array of 4096 bytes (hlu_static_scratch_bytes) that each
+ * device holds for the life of the process; an update whose descriptors
+ * would not fit returns HLU_ERR_ARG (with kx <= 16 (64 - cap) they always
+ * fit).  Every call on one device shares that array and it keeps the last
+ * call's contents: calls that overlap on one device (different streams or
+ * threads without ordering between them) race and must not be issued. */
+hlu_status hlu_truncate_add_noalloc(double* U_dev, double* V_dev, int32_t* rank_dev,
+                                    const double* X_dev, const double* Y_dev, int m, int n,
+                                    int kc, int kx, int cap, double eps, int fixed_rank,
+                                    void* stream);
+
+/* Size in bytes of the static device scratch of hlu_truncate_add_noalloc. */
+size_t hlu_static_scratch_bytes(void);
+
 #ifdef __cplusplus
 }
 #endif

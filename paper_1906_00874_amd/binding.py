@@ -106,6 +106,9 @@ _sig = {
     "hlu_getrf_batched": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
     "hlu_truncate_add": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_double, C.c_int, _P]),
+    "hlu_truncate_add_noalloc": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_int, C.c_int,
+                                           C.c_int, C.c_int, C.c_double, C.c_int, _P]),
+    "hlu_static_scratch_bytes": (C.c_size_t, []),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -404,16 +407,18 @@ def getrf_batched(a, stream=None):
     return piv, info
 
 
-def truncate_add(U, V, kc, X, Y, cap, eps, fixed_rank=0, stream=None):
+def truncate_add(U, V, kc, X, Y, cap, eps, fixed_rank=0, stream=None, noalloc=False):
     """U: (cap, m) and V: (cap, n) column-major FP64 tensors (rows = columns
-    of the factor); X: (kx, m), Y: (kx, n).  In place; returns the rank."""
+    of the factor); X: (kx, m), Y: (kx, n).  In place; returns the rank.
+    noalloc: through hlu_truncate_add_noalloc (static device scratch)."""
     m, n = U.shape[1], V.shape[1]
     kx = X.shape[0] if X is not None else 0
     for t in (U, V) + ((X, Y) if kx else ()):
         if not t.is_contiguous() or t.dtype != torch.float64:
             raise ValueError("factors must be contiguous float64 tensors")
     rank = torch.empty((1,), dtype=torch.int32, device=U.device)
-    _check(lib.hlu_truncate_add(_ptr(U), _ptr(V), _ptr(rank),
+    fn = lib.hlu_truncate_add_noalloc if noalloc else lib.hlu_truncate_add
+    _check(fn(_ptr(U), _ptr(V), _ptr(rank),
                                 _ptr(X) if kx else None, _ptr(Y) if kx else None,
                                 m, n, kc, kx, cap, eps, fixed_rank, _stream(stream)))
     return int(rank.item())

@@ -26,6 +26,12 @@ extern "C" hipError_t hlu_launch_vec(int what, const double* a, int64_t lda, dou
 extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const double* B, int ld,
                                         int n, int nrhs, double* out, hipStream_t s);
 extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s);
+extern "C" size_t hlu_static_scratch_bytes(void);
+extern "C" hipError_t hlu_static_scratch(void** out);
+extern "C" hipError_t hlu_launch_build_trunc(void* dst, const double* U, const double* V,
+                                             int32_t* rank, const double* X, const double* Y, int m,
+                                             int n, int kx, int w, int cap, double eps,
+                                             int fixed_rank, hipStream_t s);
 extern "C" hipError_t hlu_launch_keep_flag(const int32_t* src, int32_t* dst, hipStream_t s);
 extern "C" hipError_t hlu_launch_axpy_masked(const double* d, double* x, int ld, int n, int nrhs,
                                              const int32_t* active, hipStream_t s);
@@ -1504,6 +1510,37 @@ hlu_status hlu_truncate_add(double* U_dev, double* V_dev, int32_t* rank_dev, con
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(d);
   if (e != hipSuccess) return fail(HLU_ERR_DEVICE, hipGetErrorString(e));
+  return HLU_OK;
+}
+
+// The same truncated addition without any allocation: the descriptor and
+// its term table are written by a kernel into the library's static device
+// scratch (hlu_static_scratch), and everything runs asynchronously on the
+// stream.  Calls that overlap on one device share that scratch.
+hlu_status hlu_truncate_add_noalloc(double* U_dev, double* V_dev, int32_t* rank_dev,
+                                    const double* X_dev, const double* Y_dev, int m, int n,
+                                    int kc, int kx, int cap, double eps, int fixed_rank,
+                                    void* stream) {
+  if (!U_dev || !V_dev || !rank_dev || (kx > 0 && (!X_dev || !Y_dev)))
+    return fail(HLU_ERR_ARG, "NULL argument");
+  const int w = 64 - cap;
+  if (m < 1 || n < 1 || kc < 0 || kx < 0 || kc > cap || cap < 1 || cap > 32 ||
+      kx > 16 * w || fixed_rank < 0 || fixed_rank > cap)
+    return fail(HLU_ERR_ARG, "sizes out of range");
+  const size_t nterms = (size_t)(kx + w - 1) / w;
+  const size_t need = sizeof(hlu::Op) + nterms * sizeof(hlu::Term);
+  if (need > hlu_static_scratch_bytes())
+    return fail(HLU_ERR_ARG, "update needs " + std::to_string(need) +
+                                 " bytes of descriptors, above the static scratch of " +
+                                 std::to_string(hlu_static_scratch_bytes()) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  void* scr = nullptr;
+  HIPCHK(hlu_static_scratch(&scr));
+  HIPCHK(hlu_launch_set_int(rank_dev, kc, s));
+  if (kx == 0) return HLU_OK;
+  HIPCHK(hlu_launch_build_trunc(scr, U_dev, V_dev, rank_dev, X_dev, Y_dev, m, n, kx, w, cap, eps,
+                                fixed_rank, s));
+  HIPCHK(hlu_launch_ops(hlu::OP_TRUNC, scr, 1, s));
   return HLU_OK;
 }
 

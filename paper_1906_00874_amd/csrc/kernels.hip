@@ -8,6 +8,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "ops.h"
 
@@ -3410,6 +3412,86 @@ extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* star
 
 extern "C" hipError_t hlu_launch_wave(const void* ops, int count, size_t lds, hipStream_t s) {
   return hlu::launch_wave(reinterpret_cast<const hlu::Op*>(ops), count, lds, s);
+}
+
+// ---------------------------------------------------------------- static scratch
+// Staging of the allocation-free truncation entry point: one truncation
+// descriptor and its term table, written by a small kernel from scalar
+// arguments, live in this file-scope array instead of an allocation.  Every
+// device keeps its own copy for the life of the process.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): it uses the address hipGetSymbolAddress returns on the device
+// in question, looked up once per device on the entry point's first call
+// there.
+#define HLU_STATIC_SCRATCH_BYTES 4096
+static __device__ __align__(256) char scratch[HLU_STATIC_SCRATCH_BYTES];
+
+namespace hlu {
+// Op at dst, term t at dst + sizeof(Op) + t * sizeof(Term): term t covers
+// the columns [t w, min(kx, (t + 1) w)) of X (m x kx) and Y (n x kx).
+__global__ void k_build_trunc(char* dst, uint64_t U, uint64_t V, uint64_t rank, uint64_t X,
+                              uint64_t Y, int m, int n, int kx, int w, int cap, double eps,
+                              int fixed_rank) {
+  const int t = threadIdx.x;
+  const int nt = (kx + w - 1) / w;
+  Term* terms = reinterpret_cast<Term*>(dst + sizeof(Op));
+  if (t < nt) {
+    Term tm;
+    const int c0 = t * w, cw = min(w, kx - c0);
+    tm.X = PRef{X + (uint64_t)c0 * m * 8, 0, m, m, cw, DT_F64, 0, PK_MAT, 0};
+    tm.Y = PRef{Y + (uint64_t)c0 * n * 8, 0, n, n, cw, DT_F64, 0, PK_MAT, 0};
+    tm.xo = 0;
+    tm.yo = 0;
+    tm.pad[0] = tm.pad[1] = 0;
+    terms[t] = tm;
+  }
+  if (t == 0) {
+    Op o;
+    o.type = OP_TRUNC;
+    o.i0 = 0;
+    o.i1 = nt;
+    o.i2 = cap | (fixed_rank << 16);
+    o.d0 = eps;
+    o.cost = 0;
+    o.p[0] = PRef{U, rank, m, m, cap, DT_F64, 0, PK_MAT, 0};
+    o.p[1] = PRef{V, rank, n, n, cap, DT_F64, 0, PK_MAT, 0};
+    o.p[2] = PRef{(uint64_t)terms, 0, 0, 0, 0, DT_F64, 0, PK_MAT, 0};
+    o.p[3] = PRef{0, 0, 0, 0, 0, DT_F64, 0, PK_MAT, 0};
+    *reinterpret_cast<Op*>(dst) = o;
+  }
+}
+}  // namespace hlu
+
+extern "C" size_t hlu_static_scratch_bytes(void) { return HLU_STATIC_SCRATCH_BYTES; }
+
+// Device address of `scratch` on the current device (looked up once per
+// device; later calls return the kept address).
+extern "C" hipError_t hlu_static_scratch(void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+extern "C" hipError_t hlu_launch_build_trunc(void* dst, const double* U, const double* V,
+                                             int32_t* rank, const double* X, const double* Y, int m,
+                                             int n, int kx, int w, int cap, double eps,
+                                             int fixed_rank, hipStream_t s) {
+  hipLaunchKernelGGL(hlu::k_build_trunc, dim3(1), dim3(64), 0, s, (char*)dst, (uint64_t)U,
+                     (uint64_t)V, (uint64_t)rank, (uint64_t)X, (uint64_t)Y, m, n, kx, w, cap, eps,
+                     fixed_rank);
+  return hipGetLastError();
 }
 
 extern "C" hipError_t hlu_launch_ops(int type, const void* ops, int count, hipStream_t s) {
