@@ -317,7 +317,7 @@ def bench_c2(args):
     asm_s = time.perf_counter() - t
     log(f"oracle assembly {asm_s:.1f} s")
     legs = []
-    for th in sorted({1, cpu_threads()}):
+    for th in sorted({1, args.c2_threads}):
         H = copy.deepcopy(H0)
         with threadpool_limits(th):
             O.FLOPS[0] = 0.0
@@ -345,23 +345,85 @@ def bench_c2(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_batched(args):
-    """Batched factorisation: `batch_count` independent matrices (icosphere
-    levels 3-5 scaled to ellipsoids with semi-axes ~ U(0.5, 2), leaf 32, eta
-    2, eps 1e-6, cap 32, mixed precision) factored by one launch of the
-    persistent executor over the union of their schedules.  A step restores
-    every matrix from its pristine copy (not timed) and runs the batch;
-    `value` is the summed model flops over the factor time (HIP events)."""
+def bench_dense(args):
+    """Dense-only H-matrix (eta = 0: every block dense, the 2x2-recursive
+    block structure of the cluster tree down to leaf 64): the d = 1 kernel
+    on n points of [0, 1], FP64.  The H-LU is then a recursive block LU with
+    partial pivoting inside the diagonal leaves; `value` is the
+    dense-equivalent rate 2n^3/3 over the factor time (HIP events), reported
+    beside the FP64 matrix-core peak and LAPACK's dense getrf on the host's
+    cores (scipy, same matrix)."""
+    import numpy as np
+    import scipy.linalg as sla
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    import paper_1906_00874_amd as P
+    from hlu_inputs import rhs_normal, segment
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.dense_n
+    xyz, h = segment(n)
+    t = time.perf_counter()
+    hl = P.HLU(xyz, h, kernel=P.KERNEL_LOG1D, leaf=64, eta=0.0, eps=1e-6, cap=32, cap_mv=0,
+               refine_tol=0.0, precision=P.PREC_FP64, max_nrhs=4)
+    hl.set_executor(1)
+    setup_s = time.perf_counter() - t
+    st = hl.stats()
+    log(f"dense-only n={n}: setup {setup_s:.1f} s, {st['ops_factor']} ops, "
+        f"{st['bytes_total'] / 1e9:.2f} GB")
+    stream = torch.cuda.current_stream()
+    fms = []
+    for i in range(args.warmup + args.steps):
+        hl.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        hl.factor()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            fms.append(e0.elapsed_time(e1))
+    hl.sync()
+    b = rhs_normal(3, n, 4)
+    x = hl.solve(torch.tensor(b, device=dev)).cpu().numpy()
+    A = O.dense_matrix(xyz, h, O.READING_LOG1D)
+    rel_res = float(np.abs(A @ x - b).max() / (np.abs(A).sum(axis=1).max() * np.abs(x).max()))
+    with threadpool_limits(cpu_threads()):
+        t = time.perf_counter()
+        sla.lu_factor(A, overwrite_a=False, check_finite=False)
+        lapack_s = time.perf_counter() - t
+    fm = float(np.median(fms))
+    flops = 2.0 * n ** 3 / 3.0
+    out = {
+        "metric": "dense-only H-LU factor, dense-equivalent GFLOP/s (2n^3/3 / t)",
+        "value": round(flops / (fm / 1e3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fm, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"d=1 Laplace kernel on {n} points of [0,1], eta 0 (all blocks "
+                               "dense), leaf 64, FP64", "n": n},
+        "mfma_fp64_peak_frac": round(flops / (fm / 1e3) / 78.6e12, 4),
+        "ops": int(st["ops_factor"]), "setup_s": round(setup_s, 1),
+        "backward_error_solve": rel_res,
+        "lapack_host": {"threads": cpu_threads(), "getrf_s": round(lapack_s, 3),
+                        "gflops": round(flops / lapack_s / 1e9, 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _batch_leg(args, P, precision, tuning=None):
+    """Plan, assemble and bind the batch in one precision, autotune it (or
+    apply `tuning`), then time `steps` launches.  Returns (record, handles)."""
     import numpy as np
     import torch
 
-    import paper_1906_00874_amd as P
     from hlu_inputs.geometry import ellipsoid_batch_spec, ellipsoid_surface
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    from paper_1906_00874_amd import autotune
     levels, axes = ellipsoid_batch_spec(args.batch_count, seed=3)
-    kw = dict(leaf=32, eta=2.0, eps=1e-6, cap=32, precision=P.PREC_MIXED, max_nrhs=1,
+    kw = dict(leaf=32, eta=2.0, eps=1e-6, cap=32, precision=precision, max_nrhs=1,
               cap_mv=0, refine_tol=0.0, scratch_cap=256 << 20)
+    name = "mixed" if precision == P.PREC_MIXED else "fp64"
     t = time.perf_counter()
     hs = []
     for i in range(args.batch_count):
@@ -370,13 +432,18 @@ def bench_batched(args):
         h.set_executor(1)
         hs.append(h)
         if (i + 1) % 32 == 0:
-            log(f"planned and assembled {i + 1}/{args.batch_count}")
+            log(f"{name}: planned and assembled {i + 1}/{args.batch_count}")
     setup_s = time.perf_counter() - t
     dev_bytes = sum(h.required_bytes for h in hs)
     bt = P.Batch(hs)
-    log(f"setup {setup_s:.1f} s, {sum(h.n for h in hs)} unknowns, "
+    log(f"{name}: setup {setup_s:.1f} s, {sum(h.n for h in hs)} unknowns, "
         f"{sum(h.stats()['ops_factor'] for h in hs)} ops, device {dev_bytes / 1e9:.1f} GB")
     stream = torch.cuda.current_stream()
+    if tuning is None and not args.no_tune:
+        tuning = autotune.tune_batch(bt, hs, reps=1, log=log)
+        log(f"{name}: autotuned {json.dumps({k: tuning[k] for k in ('trunc_width', 'workers')})}")
+    elif tuning is not None:
+        bt.set_tuning(tuning["trunc_width"], tuning["workers"])
 
     def step():
         for h in hs:
@@ -390,7 +457,7 @@ def bench_batched(args):
     for i in range(args.warmup):
         step()
         bt.sync()
-        log(f"warmup {i + 1}/{args.warmup} done")
+        log(f"{name}: warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     rec = []
     t_start = time.perf_counter()
@@ -405,38 +472,74 @@ def bench_batched(args):
         st, inf = h.sync(check=False)
         bad += st != 0
     flops = 0.0
+    bytes_ = 0.0
     for h in hs:
         fl, by, cnt = h.factor_cost()
         flops += float(fl.sum())
-    # the first few level-3 members factored alone must match bitwise
+        bytes_ += float(by.sum() - by[7] - by[10])
+    # the first few level-3 members factored alone (same tile shapes) must
+    # match the batch bit for bit
     checked = 0
     for h in hs:
         if h.n > 1280 or checked >= 4:
             continue
         Lb, Ub = h.export_factors()
         h.reset()
+        if tuning is not None:
+            h.set_tuning(tuning["trunc_width"])
         h.factor()
         h.sync()
         La, Ua = h.export_factors()
         assert np.array_equal(La, Lb) and np.array_equal(Ua, Ub), "batched != alone"
         checked += 1
-    value = flops / (np.mean(f_ms) / 1e3) / 1e9
+    fm = float(np.mean(f_ms))
+    rec = dict(precision=name, factor_ms=round(fm, 3), factor_ms_samples=[round(v, 2) for v in f_ms],
+               ms_per_step=round((t_end - t_start) / args.steps * 1e3, 3),
+               gflops=round(flops / (fm / 1e3) / 1e9, 3), factor_gflop=round(flops / 1e9, 3),
+               matrices_per_s=round(args.batch_count / (fm / 1e3), 2),
+               hbm_gbs=round(bytes_ / (fm / 1e3) / 1e9, 2), alg_gbytes=round(bytes_ / 1e9, 3),
+               zero_pivot_or_error_handles=int(bad), checked_alone_bitwise=checked,
+               device_gb=round(dev_bytes / 1e9, 2), setup_s=round(setup_s, 1),
+               tuning=tuning, levels={str(l): int((levels == l).sum()) for l in (3, 4, 5)})
+    return rec, (hs, bt)
+
+
+def bench_batched(args):
+    """Batched factorisation: `batch_count` independent matrices (icosphere
+    levels 3-5 scaled to ellipsoids with semi-axes ~ U(0.5, 2), leaf 32, eta
+    2, eps 1e-6, cap 32) factored by one launch of the persistent executor
+    over the union of their schedules, tile shapes picked by the autotuner.
+    A step restores every matrix from its pristine copy (not timed) and runs
+    the batch; `value` is the summed model flops over the factor time (HIP
+    events), in mixed precision; the FP64 leg repeats the run on the same
+    matrices with the same tile shapes."""
+    import torch
+
+    import paper_1906_00874_amd as P
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mixed, keep = _batch_leg(args, P, P.PREC_MIXED)
+    log("mixed", json.dumps(mixed))
+    fp64 = None
+    if not args.no_fp64:
+        del keep
+        torch.cuda.empty_cache()
+        fp64, keep = _batch_leg(args, P, P.PREC_FP64, tuning=mixed["tuning"])
+        log("fp64", json.dumps(fp64))
+        del keep
     out = {
         "metric": "batched H-LU factor GFLOP/s (one persistent launch over all matrices)",
-        "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round((t_end - t_start) / args.steps * 1e3, 3),
+        "value": mixed["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "mixed (low-rank TRSM/H-GEMM f32, products on f32 MFMA with f32 accumulation; leaves, near field, truncation cores f64)",
         "data": "synthetic",
         "config": {"workload": f"{args.batch_count} matrices, icosphere levels 3-5 on ellipsoids "
                                "with semi-axes U(0.5,2) (seed 3), leaf 32, eta 2, eps 1e-6 cap 32, "
                                "scratch ring 256 MB per matrix, no refinement copy",
-                   "matrices": args.batch_count,
-                   "levels": {str(l): int((levels == l).sum()) for l in (3, 4, 5)}},
-        "factor_ms": round(float(np.mean(f_ms)), 3), "factor_gflop": round(flops / 1e9, 3),
-        "matrices_per_s": round(args.batch_count / (np.mean(f_ms) / 1e3), 2),
-        "zero_pivot_or_error_handles": int(bad), "checked_alone_bitwise": checked,
-        "device_gb": round(dev_bytes / 1e9, 2), "setup_s": round(setup_s, 1),
+                   "matrices": args.batch_count, "levels": mixed["levels"]},
+        "mixed": mixed, "fp64": fp64,
+        "speedup_mixed_vs_fp64": (round(fp64["factor_ms"] / mixed["factor_ms"], 3) if fp64 else None),
     }
     print(json.dumps(out), flush=True)
 
@@ -451,9 +554,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "c2", "batched", "serve", "copy"], default="c3",
+    ap.add_argument("--no-construct", action="store_true",
+                    help="c3: skip the device-construction leg")
+    ap.add_argument("--workload", choices=["c3", "c2", "batched", "dense", "serve", "copy"],
+                    default="c3",
                     help="c3: the headline factor + solve; c2: the n = 20480 FP64 workload "
-                         "beside the oracle on the host; batched: many matrices "
+                         "beside the oracle on the host; dense: the dense-only (eta 0) "
+                         "block LU; batched: many matrices "
                          "factored by one persistent launch; serve: continuous-batching "
                          "server over a Poisson job stream; copy: byte-counter "
                          "calibration")
@@ -462,6 +569,10 @@ def main():
     ap.add_argument("--serve-sizes", default="1280,5120,20480,81920")
     ap.add_argument("--serve-budget-frac", type=float, default=0.8)
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--no-tune", action="store_true", help="batched: default tile shapes")
+    ap.add_argument("--dense-n", type=int, default=16384)
+    ap.add_argument("--c2-threads", type=int, default=1,
+                    help="c2: host threads of the oracle's second leg (1: one leg only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library has no multi-GPU path "
@@ -472,6 +583,9 @@ def main():
         return
     if args.workload == "c2":
         bench_c2(args)
+        return
+    if args.workload == "dense":
+        bench_dense(args)
         return
     if args.workload == "serve":
         bench_serve(args)
@@ -649,6 +763,56 @@ def main():
                     status=int(s64), ir_iters=int(inf64.iters), eta=float(inf64.eta_final))
         log("fp64", json.dumps(fp64))
 
+    # construction on the device: the same matrix built by hlu_assemble from
+    # the points (cross approximation + truncation kernel), no operator
+    # copy (the refinement residual is summed directly over the exact
+    # entries); setup, factor and one refined solve
+    construct = None
+    if not args.no_construct:
+        if fp64 is not None:
+            del h64
+        torch.cuda.empty_cache()
+        t = time.perf_counter()
+        hd = P.HLU(xyz, area, precision=P.PREC_MIXED, leaf=64, eta=2.0, eps=1e-5, cap=32,
+                   cap_mv=0, refine_tol=1e-10, refine_max_iter=10, max_nrhs=nrhs,
+                   device_assembly=1, assemble=False)
+        plan_s = time.perf_counter() - t
+        hd.bind()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P.lib.hlu_assemble(hd.h, P.binding._stream(None))
+        torch.cuda.synchronize()
+        asm_ms = (time.perf_counter() - t) * 1e3
+        hd.set_executor(1)
+        fms = []
+        for i in range(3):
+            hd.reset()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            hd.factor()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            fms.append(ev[0].elapsed_time(ev[1]))
+        t = time.perf_counter()
+        hd.solve_cm(bc, xc)
+        torch.cuda.synchronize()
+        sol_ms = (time.perf_counter() - t) * 1e3
+        sd, infd = hd.sync(check=False)
+        xd = xc.cpu().numpy().T
+        rd = b[rows] - A_rows @ xd
+        eta_d = float((np.abs(rd).max(axis=0) /
+                       (anorm_s * np.abs(xd).max(axis=0) + np.abs(b).max(axis=0))).max())
+        construct = dict(plan_s=round(plan_s, 2), device_assemble_ms=round(asm_ms, 1),
+                         host_plan_and_assemble_s=round(setup_s, 2),
+                         factor_ms=round(float(np.median(fms[1:])), 2),
+                         refined_solve_ms=round(sol_ms, 1), ir_iters=int(infd.iters),
+                         eta_device=float(infd.eta_final), eta_exact_sampled=eta_d,
+                         status=int(sd), cap_hits=int(infd.cap_hits),
+                         max_rank=int(infd.max_rank),
+                         note="refinement residual by direct summation over the exact entries")
+        log("device construction", json.dumps(construct))
+        del hd
+
     cpu = None
     if not args.no_cpu:
         t = time.perf_counter()
@@ -694,6 +858,7 @@ def main():
         "roofline_solve": roof_solve,
         "kernel_breakdown": breakdown,
         "fp64": fp64,
+        "device_construction": construct,
         "speedup_mixed_vs_fp64": (round(fp64["factor_ms"] / float(np.mean(f_ms)), 3) if fp64 else None),
         "cpu_baseline": cpu,
     }

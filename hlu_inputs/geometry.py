@@ -99,6 +99,28 @@ def ellipsoid_surface(level: int, semi_axes):
     return _centroids_areas(v, f)
 
 
+def segment(n: int, a: float = 0.0, b: float = 1.0):
+    """Midpoints (n x 3, second and third coordinates zero) and lengths of the
+    uniform partition of [a, b] into n panels: the d = 1 domain."""
+    h = (b - a) / n
+    xyz = np.zeros((n, 3))
+    xyz[:, 0] = a + (np.arange(n) + 0.5) * h
+    return xyz, np.full(n, h)
+
+
+def circle(n: int, radius: float = 0.5):
+    """Chord midpoints (n x 3, third coordinate zero) and chord lengths of the
+    regular n-gon inscribed in the circle of the given radius (vertex k at
+    angle 2 pi k / n): the d = 2 boundary.  With radius <= 0.5 every pair
+    of points is within unit distance."""
+    th = 2.0 * np.pi * np.arange(n + 1) / n
+    v = radius * np.stack([np.cos(th), np.sin(th)], axis=1)
+    mid = 0.5 * (v[:-1] + v[1:])
+    xyz = np.zeros((n, 3))
+    xyz[:, :2] = mid
+    return xyz, np.linalg.norm(v[1:] - v[:-1], axis=1)
+
+
 def rhs_uniform(seed: int, n: int):
     """x ~ U(-1, 1), drawn from numpy's PCG64 generator."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n)

@@ -53,12 +53,31 @@ typedef enum {
     HLU_ERR_STATE = 6           /* call out of order (e.g. solve before factor) */
 } hlu_status;
 
-/* Entries of the collocation matrix for the d=3 Laplace kernel
- * g(x,y) = 1/(4 pi |x-y|) (Sec. 6.1) between panel centroids x_i:
- *   WEIGHTED: A_ij = area_j / (4 pi |x_i - x_j|)   (one-point quadrature)
- *   POINT:    A_ij = 1 / (4 pi |x_i - x_j|)
- * and in both A_ii = 2 sqrt(area_i/pi)/(4 pi) sqrt(pi) + 1. */
-typedef enum { HLU_KERNEL_LAPLACE3D_WEIGHTED = 0, HLU_KERNEL_LAPLACE3D_POINT = 1 } hlu_kernel;
+/* Entries of the collocation matrix for the Laplace kernels of Sec. 6.1
+ * between panel midpoints x_i (xyz rows; unused coordinates zero), with the
+ * identity added (second-kind form I + V_h):
+ *   d = 3, g(x,y) = 1/(4 pi |x-y|), `area` = panel areas:
+ *     LAPLACE3D_WEIGHTED: A_ij = area_j / (4 pi |x_i - x_j|) (one-point
+ *                         quadrature over panel j)
+ *     LAPLACE3D_POINT:    A_ij = 1 / (4 pi |x_i - x_j|)
+ *     both: A_ii = 2 sqrt(area_i/pi)/(4 pi) sqrt(pi) + 1;
+ *   d = 1, g(x,y) = -log|x-y|, `area` = panel lengths h_j > 0:
+ *     LAPLACE1D_LOG: A_ij = -h_j log|x_i - x_j|,
+ *                    A_ii = h_i (1 - log(h_i / 2)) + 1 (exact panel integral);
+ *   d = 2, g(x,y) = -log|x-y| / (2 pi), `area` = panel lengths h_j > 0:
+ *     LAPLACE2D_LOG: A_ij = -h_j log|x_i - x_j| / (2 pi),
+ *                    A_ii = h_i (1 - log(h_i / 2)) / (2 pi) + 1.
+ * The backward error of hlu_solve takes ||A||_inf as max_i (A_mv 1)_i with
+ * the matvec copy, exact when every entry is >= 0 (all d = 3 inputs; d = 1
+ * and d = 2 points within unit distance of each other) and a lower bound
+ * otherwise, which makes the reported backward error an overestimate;
+ * without the copy it is max_i sum_j |A_ij| summed directly. */
+typedef enum {
+    HLU_KERNEL_LAPLACE3D_WEIGHTED = 0,
+    HLU_KERNEL_LAPLACE3D_POINT = 1,
+    HLU_KERNEL_LAPLACE1D_LOG = 2,
+    HLU_KERNEL_LAPLACE2D_LOG = 3
+} hlu_kernel;
 
 /* FP64: all factors and all arithmetic FP64.  MIXED: the factors of
  * low-rank blocks and the H-GEMM product panels are stored in FP32, and the
@@ -71,6 +90,22 @@ typedef enum { HLU_KERNEL_LAPLACE3D_WEIGHTED = 0, HLU_KERNEL_LAPLACE3D_POINT = 1
  * FP32 panels) and the refinement residual stay FP64. */
 typedef enum { HLU_PREC_FP64 = 0, HLU_PREC_MIXED = 1 } hlu_precision;
 
+/* What hlu_factor computes.  LU: the H-LU factorisation (Sec. 3.1).
+ * PRODUCT and INVERSE: the other H-arithmetic operations on the same kernels,
+ * on a doubled H-matrix over two copies of the points, M = [M11 M12; M21
+ * M22], every quadrant on the original block tree (2n unknowns):
+ *   PRODUCT: M12 = A (kernel), M21 = B (kernel_b), M11 = M22 = 0; the
+ *     schedule is the H-GEMM M11 -= M12 M21, so M11 = -A B, truncated to
+ *     eps_factor / rank_cap_factor like every update of the H-LU;
+ *   INVERSE: M11 = A, M12 = M21 = I, M22 = 0; the schedule is the first
+ *     steps of the H-LU of M (LU of M11, the two triangular solves on M12
+ *     and M21, the Schur-complement update of M22), so
+ *     M22 = -M21 U^-1 L^-1 P M12 = -A^-1.
+ * Such plans take rank_cap_matvec = 0, host assembly and no refinement;
+ * hlu_solve, hlu_matvec and hlu_export_factors refuse them
+ * (HLU_ERR_STATE). */
+typedef enum { HLU_OP_LU = 0, HLU_OP_PRODUCT = 1, HLU_OP_INVERSE = 2 } hlu_operation;
+
 typedef struct {
     hlu_kernel kernel;
     double eta;               /* admissibility: min(diam) <= eta * dist (Sec. 2) */
@@ -81,8 +116,9 @@ typedef struct {
     int rank_cap_factor;      /* rank capacity of the factored copy (<= 32)     */
     double eps_matvec;        /* tolerance of the refinement operator copy      */
     int rank_cap_matvec;      /* rank capacity of that copy (<= 64); 0: no copy
-                                 (then refine_tol must be 0 and hlu_matvec is
-                                 unavailable)                                   */
+                                 (then the refinement residual, hlu_matvec and
+                                 ||A||_inf are summed directly over the exact
+                                 entries on the device: O(n^2 nrhs) work)      */
     hlu_precision precision;
     double refine_tol;        /* backward-error target of hlu_solve (0: no IR)  */
     int refine_max_iter;      /* at most this many refinement steps              */
@@ -92,6 +128,16 @@ typedef struct {
                                  > 0: temporaries share a ring of this many
                                  bytes (a region is reused only after every op
                                  touching its previous tenant has run)          */
+    int operation;            /* HLU_OP_LU (0): the H-LU of the kernel matrix;
+                                 HLU_OP_PRODUCT (1) / HLU_OP_INVERSE (2): see
+                                 hlu_export_result                             */
+    int kernel_b;             /* HLU_OP_PRODUCT: kernel of the right factor B  */
+    int device_assembly;      /* 0: hlu_plan assembles the blocks on the host
+                                 (cross approximation + QR/SVD recompression)
+                                 and hlu_assemble uploads them; 1: hlu_plan
+                                 builds trees, layout and schedules only, and
+                                 hlu_assemble builds every block on the device
+                                 (requires rank_cap_matvec = 0)               */
 } hlu_params;
 
 typedef struct {
@@ -132,8 +178,16 @@ size_t hlu_required_bytes(hlu_handle h);
  * (256-byte aligned) and upload the schedules.  HLU_ERR_NOMEM if too small. */
 hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes);
 
-/* Copy the assembled H-matrix (factor copy, its pristine copy and the matvec
- * copy) into the bound buffer on `stream`.  Requires hlu_bind. */
+/* Host assembly (device_assembly = 0): copy the H-matrix assembled by
+ * hlu_plan (factor copy, its pristine copy and the matvec copy) into the
+ * bound buffer on `stream`.  Device assembly (device_assembly = 1): build
+ * it on the device from the points -- dense blocks entry by entry, every
+ * admissible block by adaptive cross approximation with partial pivoting
+ * (to eps/10, at most 64 terms) recompressed by the truncation of
+ * Sec. 3.1's truncated addition to eps_factor and rank_cap_factor -- then
+ * keep the pristine copy.  Both compute ||A||_inf and synchronise the
+ * stream before returning.  Requires hlu_bind.  Cross approximations that
+ * stop at 64 terms are counted in hlu_info.cap_hits. */
 hlu_status hlu_assemble(hlu_handle h, void* stream);
 
 /* Restore the factor copy from the pristine copy (device-to-device). */
@@ -175,6 +229,29 @@ hlu_status hlu_assemble_from(hlu_handle h, hlu_handle src, void* stream);
  * set, shapes or kinds differ from the handle's trees, or a rank exceeds
  * rank_cap_factor; HLU_ERR_STATE when unbound or unassembled. */
 hlu_status hlu_import_blocks(hlu_handle h, const char* path);
+
+/* After hlu_factor on a PRODUCT or INVERSE plan: the result (A B, or A^-1)
+ * expanded densely in the original point order into host memory (out:
+ * n x n column-major, leading dimension ld >= n, n <= 16384).  Synchronous.
+ * HLU_ERR_STATE for an LU plan or before hlu_factor. */
+hlu_status hlu_export_result(hlu_handle h, double* out, int64_t ld);
+
+/* Diagnostic: write the factored copy's blocks as they are on the device
+ * (after hlu_assemble: the assembled A_H; after hlu_factor: the L and U
+ * blocks in place) to a host file in the format hlu_import_blocks reads,
+ * FP32 factors widened to FP64.  Synchronous.  HLU_ERR_STATE when unbound,
+ * HLU_ERR_ARG when the file cannot be written. */
+hlu_status hlu_export_blocks(hlu_handle h, const char* path);
+
+/* Tile shape of this handle's factorisation by the dataflow executor
+ * (hlu_set_executor(h, 1)): trunc_width is the widest stacked factor pair a
+ * truncation pass takes (the K of its Gram, Cholesky and SVD core tiles;
+ * Sec. 3.1 truncated addition), 0 for the default of 64, otherwise in
+ * [16, 64].  The rank rule is unchanged; a narrower stack means more passes
+ * over smaller cores, so results agree with the default within the
+ * truncation tolerance rather than bit for bit.  Chosen per workload by the
+ * autotuner (paper_1906_00874_amd/autotune.py). */
+hlu_status hlu_set_tuning(hlu_handle h, int trunc_width);
 
 /* Workgroups of the dataflow executor for this handle's factor and solve
  * launches: 0 (the default) one per compute unit; a smaller count leaves
@@ -251,9 +328,16 @@ hlu_status hlu_batch_factor(hlu_batch b, void* stream);
 hlu_status hlu_batch_sync(hlu_batch b, void* stream);
 void hlu_batch_destroy(hlu_batch b);
 
+/* Tile shape and launch width of a batch's later launches: trunc_width as in
+ * hlu_set_tuning (0: 64) for every matrix of the batch, workers the number
+ * of persistent workgroups (0: one per compute unit).  Synchronous when the
+ * batch is bound.  HLU_ERR_ARG for values outside those ranges. */
+hlu_status hlu_batch_set_tuning(hlu_batch b, int trunc_width, int workers);
+
 /* x = A^{-1} b for nrhs right-hand sides (b_dev, x_dev: n x nrhs, leading
  * dimension ld, original order; they may alias).  With refine_tol > 0 the
- * solution is refined with FP64 residuals of the matvec copy until the
+ * solution is refined with FP64 residuals of the matvec copy (without a
+ * copy: of the exact matrix by direct summation) until the
  * backward error max_j |r_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf) <=
  * refine_tol (this call then synchronises the stream once per step).  Each
  * column is corrected only while its own backward error exceeds refine_tol,
@@ -264,12 +348,12 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
 
 /* Refinement settings of this handle's later hlu_solve calls (initially
  * refine_tol / refine_max_iter of its parameters): refine_tol = 0 gives the
- * plain solve with the factors.  HLU_ERR_ARG for refine_tol < 0,
- * refine_max_iter outside [0, 15], or refine_tol > 0 on a handle planned
- * without the operator copy. */
+ * plain solve with the factors.  HLU_ERR_ARG for refine_tol < 0 or
+ * refine_max_iter outside [0, 15]. */
 hlu_status hlu_set_refinement(hlu_handle h, double refine_tol, int refine_max_iter);
 
-/* y = A_mv x with the matvec copy (original order, n x nrhs). */
+/* y = A_mv x with the matvec copy (original order, n x nrhs); without a
+ * copy, y = A x with the exact entries by direct summation. */
 hlu_status hlu_matvec(hlu_handle h, const double* x_dev, double* y_dev, int nrhs,
                       int64_t ld, void* stream);
 

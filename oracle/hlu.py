@@ -42,6 +42,8 @@ FOUR_PI = 4.0 * math.pi
 
 READING_WEIGHTED = 0   # A_ij = area_j / (4 pi |x_i - x_j|)
 READING_POINT = 1      # A_ij = 1 / (4 pi |x_i - x_j|)
+READING_LOG1D = 2      # A_ij = -h_j log|x_i - x_j|            (d = 1)
+READING_LOG2D = 3      # A_ij = -h_j log|x_i - x_j| / (2 pi)   (d = 2)
 
 # model flop count of the executed operations (getrf 2b^3/3 - b^2/2 + 5b/6,
 # triangular solve m^2 n, product 2 m n k, truncation as in `truncate`);
@@ -70,6 +72,8 @@ def kernel_entries(xyz, area, rows, cols, reading=READING_WEIGHTED):
     d = xyz[rows][:, None, :] - xyz[cols][None, :, :]
     r = np.sqrt(np.einsum("ijk,ijk->ij", d, d))
     same = rows[:, None] == cols[None, :]
+    if reading in (READING_LOG1D, READING_LOG2D):
+        return _log_entries(r, same, area[rows], area[cols], reading)
     with np.errstate(divide="ignore"):
         g = 1.0 / (FOUR_PI * r)
     if reading == READING_WEIGHTED:
@@ -77,6 +81,22 @@ def kernel_entries(xyz, area, rows, cols, reading=READING_WEIGHTED):
     diag = 2.0 * np.sqrt(area[rows] / math.pi) / FOUR_PI * math.sqrt(math.pi) + 1.0
     g = np.where(same, diag[:, None], g)
     return g
+
+
+def _log_entries(r, same, h_rows, h_cols, reading):
+    """d = 1 and d = 2 Laplace kernels of Sec. 6.1 (-log r and -log(r)/(2 pi))
+    collocated at panel midpoints with one-point quadrature over the column
+    panel (weight: its length h_j), plus the identity.  The self term is the
+    kernel integrated exactly over the straight panel of length h around its
+    midpoint: the integral of -log|t| over [-h/2, h/2] is h (1 - log(h/2)).
+    Parity: pinned by the integral itself (numerical quadrature), by the
+    continuous operator applied to 1 on [0, 1] (d = 1) and by the circle's
+    Fourier modes (d = 2) in the tests."""
+    scale = 1.0 if reading == READING_LOG1D else 1.0 / (2.0 * math.pi)
+    with np.errstate(divide="ignore"):
+        g = -np.log(r) * h_cols[None, :] * scale
+    diag = h_rows * (1.0 - np.log(0.5 * h_rows)) * scale + 1.0
+    return np.where(same, diag[:, None], g)
 
 
 def dense_matrix(xyz, area, reading=READING_WEIGHTED):
@@ -606,6 +626,80 @@ def factor(H):
         return info[0]
     H.factored = True
     return info[0]
+
+
+# ---------------------------------------------------------------------------
+# the other H-arithmetic operations on the same primitives (Sec. 2: H2Lib
+# offers H-matrix multiplication and inversion beside the H-LU)
+# ---------------------------------------------------------------------------
+def _blank(b, fill):
+    """A block tree with b's structure; leaves from fill(leaf) -> (F) or
+    (U, V)."""
+    c = Block(b.t, b.s, b.kind)
+    if b.kind == "H":
+        c.sons = [[_blank(x, fill) for x in row] for row in b.sons]
+    elif b.kind == "F":
+        c.F = fill(b)
+    else:
+        c.U, c.V = fill(b)
+    return c
+
+
+def _zero(b):
+    return np.zeros((b.t.size, b.s.size)) if b.kind == "F" else \
+        (np.zeros((b.t.size, 0)), np.zeros((b.s.size, 0)))
+
+
+def _ident(b):
+    if b.kind == "F":
+        return np.eye(b.t.size) if b.t is b.s else np.zeros((b.t.size, b.s.size))
+    return np.zeros((b.t.size, 0)), np.zeros((b.s.size, 0))
+
+
+def _negate(b):
+    for lf in leaves_of(b):
+        if lf.kind == "F":
+            lf.F = -lf.F
+        else:
+            lf.U = -lf.U
+
+
+def hmul(HA, HB, rule):
+    """C ~= A B in H-format on A's block tree (A and B on the same trees):
+    C starts at zero and takes the H-GEMM C := C - A B of the H-LU (every
+    update truncated to the rule), then its sign is flipped.  Returns the
+    root block of C (cluster order)."""
+    C = _blank(HA.block, _zero)
+    gemm(C, HA.block, HB.block, rule)
+    _negate(C)
+    return C
+
+
+def hinv(HA, rule):
+    """X ~= A^{-1} in H-format through the first steps of the H-LU of the
+    doubled matrix [A I; I 0] (Sec. 3.1): LU of A, the two triangular solves
+    on the identity blocks, and the Schur-complement update of the zero
+    block, which then holds -A^{-1}; its sign is flipped.  A is factored in
+    place.  Returns the root block of X (cluster order)."""
+    I12 = _blank(HA.block, _ident)
+    I21 = _blank(HA.block, _ident)
+    X = _blank(HA.block, _zero)
+    info = [0]
+    lu(HA.block, rule, info)
+    trsm_l(HA.block, I12, rule)
+    trsm_u(I21, HA.block, rule)
+    gemm(X, I21, I12, rule)
+    _negate(X)
+    return X
+
+
+def block_dense(b, n):
+    """Dense n x n expansion of a block tree (cluster order)."""
+    A = np.zeros((n, n))
+    for lf in leaves_of(b):
+        sl = (slice(lf.t.off, lf.t.off + lf.t.size), slice(lf.s.off, lf.s.off + lf.s.size))
+        A[sl] = lf.F if lf.kind == "F" else lf.U @ lf.V.T
+    return A
 
 
 def solve(H, b):

@@ -8,8 +8,10 @@ no fallback.
 """
 from .binding import (HLU, Batch, HLUError, Params, Info, PlanStats, lib, build_lib_path,
                       getrf_batched, truncate_add, KERNEL_WEIGHTED, KERNEL_POINT,
+                      KERNEL_LOG1D, KERNEL_LOG2D, OP_LU, OP_PRODUCT, OP_INVERSE,
                       PREC_FP64, PREC_MIXED)
 
 __all__ = ["HLU", "Batch", "HLUError", "Params", "Info", "PlanStats", "lib", "build_lib_path",
            "getrf_batched", "truncate_add", "KERNEL_WEIGHTED", "KERNEL_POINT",
+           "KERNEL_LOG1D", "KERNEL_LOG2D", "OP_LU", "OP_PRODUCT", "OP_INVERSE",
            "PREC_FP64", "PREC_MIXED"]

@@ -17,7 +17,8 @@ if not os.path.exists(build_lib_path):
 
 lib = C.CDLL(build_lib_path)
 
-KERNEL_WEIGHTED, KERNEL_POINT = 0, 1
+KERNEL_WEIGHTED, KERNEL_POINT, KERNEL_LOG1D, KERNEL_LOG2D = 0, 1, 2, 3
+OP_LU, OP_PRODUCT, OP_INVERSE = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 HLU_OK, HLU_ERR_ARG, HLU_ERR_NOMEM, HLU_ERR_DEVICE = 0, 1, 2, 3
@@ -33,7 +34,8 @@ class Params(C.Structure):
                 ("rank_cap_matvec", C.c_int), ("precision", C.c_int),
                 ("refine_tol", C.c_double), ("refine_max_iter", C.c_int),
                 ("max_nrhs", C.c_int), ("seed", C.c_uint64),
-                ("scratch_cap_bytes", C.c_int64)]
+                ("scratch_cap_bytes", C.c_int64), ("operation", C.c_int),
+                ("kernel_b", C.c_int), ("device_assembly", C.c_int)]
 
 
 class Info(C.Structure):
@@ -101,6 +103,10 @@ _sig = {
     "hlu_export_factors": (C.c_int, [_P, _P, _P, _P]),
     "hlu_export_pivots": (C.c_int, [_P, _P, _P]),
     "hlu_import_blocks": (C.c_int, [_P, C.c_char_p]),
+    "hlu_export_blocks": (C.c_int, [_P, C.c_char_p]),
+    "hlu_export_result": (C.c_int, [_P, _P, C.c_int64]),
+    "hlu_set_tuning": (C.c_int, [_P, C.c_int]),
+    "hlu_batch_set_tuning": (C.c_int, [_P, C.c_int, C.c_int]),
     "hlu_destroy": (None, [_P]),
     "hlu_last_error": (C.c_char_p, []),
     "hlu_getrf_batched": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
@@ -139,9 +145,11 @@ def _ptr(t):
 
 def make_params(kernel=KERNEL_WEIGHTED, eta=2.0, leaf=32, fixed_rank=0, eps=1e-6, cap=32,
                 eps_mv=1e-12, cap_mv=64, precision=PREC_FP64, refine_tol=0.0,
-                refine_max_iter=10, max_nrhs=32, seed=0, scratch_cap=0):
+                refine_max_iter=10, max_nrhs=32, seed=0, scratch_cap=0, operation=0,
+                kernel_b=0, device_assembly=0):
     return Params(kernel, eta, leaf, fixed_rank, eps, cap, eps_mv, cap_mv, precision,
-                  refine_tol, refine_max_iter, max_nrhs, seed, scratch_cap)
+                  refine_tol, refine_max_iter, max_nrhs, seed, scratch_cap, operation, kernel_b,
+                  device_assembly)
 
 
 class HLU:
@@ -181,6 +189,22 @@ class HLU:
         """Replace the factored copy's blocks by those of a block file
         (format in include/hlu.h), e.g. the oracle's A_H."""
         _check(lib.hlu_import_blocks(self.h, str(path).encode()))
+
+    def export_result(self):
+        """A B (product plan) or A^-1 (inverse plan) after factor(), dense,
+        original point order (numpy, n <= 16384)."""
+        out = np.zeros((self.n, self.n), order="F")
+        _check(lib.hlu_export_result(self.h, out.ctypes.data_as(_P), self.n))
+        return out
+
+    def export_blocks(self, path):
+        """Write the factored copy's current blocks to a block file."""
+        _check(lib.hlu_export_blocks(self.h, str(path).encode()))
+
+    def set_tuning(self, trunc_width):
+        """Widest stack of a truncation pass in later dataflow factorisations
+        (0: 64)."""
+        _check(lib.hlu_set_tuning(self.h, int(trunc_width)))
 
     def set_workers(self, workers):
         """Dataflow workgroups per launch (0: one per compute unit)."""
@@ -393,6 +417,11 @@ class Batch:
 
     def sync(self, stream=None):
         _check(lib.hlu_batch_sync(self.b, _stream(stream)))
+
+    def set_tuning(self, trunc_width, workers=0):
+        """Truncation stack width (0: 64) and persistent workgroups (0: one
+        per compute unit) of later launches."""
+        _check(lib.hlu_batch_set_tuning(self.b, int(trunc_width), int(workers)))
 
 
 def getrf_batched(a, stream=None):

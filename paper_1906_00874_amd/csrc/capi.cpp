@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -27,6 +28,13 @@ extern "C" hipError_t hlu_launch_colmax(const double* R, const double* X, const 
                                         int n, int nrhs, double* out, hipStream_t s);
 extern "C" hipError_t hlu_launch_set_int(int32_t* p, int v, hipStream_t s);
 extern "C" size_t hlu_static_scratch_bytes(void);
+extern "C" hipError_t hlu_launch_asm(const void* dense, int ndense, const void* lr, int nlr,
+                                     const double* pts, int npts, int kernel, double eps,
+                                     int kmax, int32_t* caphits, hipStream_t s);
+extern "C" hipError_t hlu_launch_direct_mv(const double* pts, int npts, int kernel,
+                                           const double* X, int ld, const double* B, double beta,
+                                           double alpha, double* Y, int nrhs, int absmode,
+                                           hipStream_t s);
 extern "C" hipError_t hlu_static_scratch(void** out);
 extern "C" hipError_t hlu_launch_build_trunc(void* dst, const double* U, const double* V,
                                              int32_t* rank, const double* X, const double* Y, int m,
@@ -286,12 +294,14 @@ struct hlu_handle_s {
   double eta_hist[16] = {0};
   double eta_final = 0.0;
   bool not_converged = false;
+  int32_t asm_cap_hits = 0;           // cross approximations stopped at their rank limit
   double refine_tol = 0.0;            // refinement target of hlu_solve (0: none)
   int refine_max_iter = 0;
   hlu_params params;
   bool use_graph = true;
   int executor = 0;                   // 0: waves, 1: dataflow
   int workers = 0;                    // dataflow workgroups (0: one per compute unit)
+  int tune = 0;                       // tuning word of the factor part (DfPart::tune)
   int n_high = 0;                     // factor ops flagged near-critical (high ring)
   int high_workers = 0;               // workgroups serving the high ring
   hipGraphExec_t graph_f = nullptr;   // factor schedule (with status reset)
@@ -328,8 +338,21 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
     return fail(HLU_ERR_ARG, "rank_cap_factor must be in [1, 32]");
   if (p->rank_cap_matvec < 0 || p->rank_cap_matvec > 64)
     return fail(HLU_ERR_ARG, "rank_cap_matvec must be in [0, 64]");
-  if (p->rank_cap_matvec == 0 && p->refine_tol != 0.0)
-    return fail(HLU_ERR_ARG, "refinement needs the operator copy (rank_cap_matvec > 0)");
+  if (p->device_assembly != 0 && p->device_assembly != 1)
+    return fail(HLU_ERR_ARG, "device_assembly must be 0 or 1");
+  if (p->operation < HLU_OP_LU || p->operation > HLU_OP_INVERSE)
+    return fail(HLU_ERR_ARG, "unknown operation");
+  if (p->operation != HLU_OP_LU) {
+    if (p->rank_cap_matvec != 0 || p->device_assembly != 0 || p->refine_tol != 0.0)
+      return fail(HLU_ERR_ARG, "products and inverses take rank_cap_matvec = 0, host "
+                               "assembly and no refinement");
+    if (n > (1LL << 28)) return fail(HLU_ERR_ARG, "n out of range for a doubled plan");
+    if (p->operation == HLU_OP_PRODUCT &&
+        (p->kernel_b < HLU_KERNEL_LAPLACE3D_WEIGHTED || p->kernel_b > HLU_KERNEL_LAPLACE2D_LOG))
+      return fail(HLU_ERR_ARG, "unknown kernel_b");
+  }
+  if (p->device_assembly == 1 && p->rank_cap_matvec != 0)
+    return fail(HLU_ERR_ARG, "device assembly builds no operator copy: rank_cap_matvec must be 0");
   if (p->scratch_cap_bytes < 0) return fail(HLU_ERR_ARG, "scratch_cap_bytes must be >= 0");
   if (p->fixed_rank < 0 || p->fixed_rank > p->rank_cap_factor)
     return fail(HLU_ERR_ARG, "fixed_rank must be in [0, rank_cap_factor]");
@@ -343,8 +366,12 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
   if (p->rank_cap_matvec > 0 && !(p->eps_matvec > 0 && p->eps_matvec < 1))
     return fail(HLU_ERR_ARG, "eps_matvec must be in (0, 1)");
   if (p->max_nrhs < 1 || p->max_nrhs > 64) return fail(HLU_ERR_ARG, "max_nrhs must be in [1, 64]");
-  if (p->kernel != HLU_KERNEL_LAPLACE3D_WEIGHTED && p->kernel != HLU_KERNEL_LAPLACE3D_POINT)
+  if (p->kernel != HLU_KERNEL_LAPLACE3D_WEIGHTED && p->kernel != HLU_KERNEL_LAPLACE3D_POINT &&
+      p->kernel != HLU_KERNEL_LAPLACE1D_LOG && p->kernel != HLU_KERNEL_LAPLACE2D_LOG)
     return fail(HLU_ERR_ARG, "unknown kernel");
+  if (p->kernel == HLU_KERNEL_LAPLACE1D_LOG || p->kernel == HLU_KERNEL_LAPLACE2D_LOG)
+    for (int64_t i = 0; i < n; ++i)
+      if (!(area[i] > 0)) return fail(HLU_ERR_ARG, "panel lengths must be > 0");
   if (p->precision != HLU_PREC_FP64 && p->precision != HLU_PREC_MIXED)
     return fail(HLU_ERR_ARG, "unknown precision");
   if (p->refine_max_iter < 0 || p->refine_max_iter > 15)
@@ -372,12 +399,21 @@ hlu_status hlu_plan(const double* xyz, const double* area, int64_t n, const hlu_
   prm.refine_max_iter = p->refine_max_iter;
   prm.max_nrhs = p->max_nrhs;
   prm.scratch_cap = (uint64_t)p->scratch_cap_bytes;
+  prm.device_asm = p->device_assembly;
+  prm.operation = p->operation;
+  prm.kernel_b = p->operation == HLU_OP_PRODUCT ? p->kernel_b : p->kernel;
   try {
     if (!hlu::build_plan(h->plan, xyz, area, n, prm)) {
       std::string e = h->plan.err;
       delete h;
       return fail(HLU_ERR_ARG, "planning failed: " + e);
     }
+    if (prm.device_asm)
+      for (const auto& b : h->plan.blk)
+        if (b.kind == 'R' && (b.m > 65536 || b.n > 65536)) {
+          delete h;
+          return fail(HLU_ERR_ARG, "device assembly: an admissible block exceeds 65536 rows");
+        }
   } catch (const std::bad_alloc&) {
     delete h;
     return fail(HLU_ERR_NOMEM, "host allocation failed while planning");
@@ -469,6 +505,32 @@ hlu_status hlu_validate(hlu_handle h) {
       if (t.T == 0 && t.c0 + t.ncol > p.n) return fail(HLU_ERR_ARG, "matvec term columns");
     }
   }
+  // device assembly: every block inside the buffer and the points, every
+  // recompression op's panels and its term inside the buffer
+  if (p.prm.device_asm) {
+    for (const auto& a : p.asm_dense)
+      if (a.U < 512 || a.U + (uint64_t)a.m * a.n * 8 > p.total || a.r0 < 0 || a.c0 < 0 ||
+          a.r0 + a.m > p.n || a.c0 + a.n > p.n)
+        return fail(HLU_ERR_ARG, "assembly dense table");
+    for (const auto& a : p.asm_lr)
+      if (a.U < p.off_asm_ws || a.U + (uint64_t)a.m * p.asm_kmax * 8 > p.off_asm_ws + p.size_asm_ws ||
+          a.V < p.off_asm_ws || a.V + (uint64_t)a.n * p.asm_kmax * 8 > p.off_asm_ws + p.size_asm_ws ||
+          a.rank < 256 || a.rank + 4 > p.total || a.r0 < 0 || a.c0 < 0 || a.r0 + a.m > p.n ||
+          a.c0 + a.n > p.n || a.m > 65536 || a.n > 65536)
+        return fail(HLU_ERR_ARG, "assembly low-rank table");
+    if (p.asm_ops.size() != p.asm_lr.size() || p.asm_terms.size() != p.asm_lr.size())
+      return fail(HLU_ERR_ARG, "assembly op count");
+    for (size_t i = 0; i < p.asm_ops.size(); ++i) {
+      const hlu::Op& o = p.asm_ops[i];
+      const hlu::Term& t = p.asm_terms[i];
+      if (o.type != hlu::OP_TRUNC || o.i0 != (int32_t)i || o.i1 != 1 ||
+          !panel_ok(o.p[0], p.total, why) || !panel_ok(o.p[1], p.total, why) ||
+          !panel_ok(t.X, p.total, why) || !panel_ok(t.Y, p.total, why) ||
+          t.X.rows != o.p[0].rows || t.Y.rows != o.p[1].rows || t.X.cols + 0 > 64 ||
+          o.p[2].ptr != p.off_asm_terms)
+        return fail(HLU_ERR_ARG, "assembly recompression op: " + why);
+    }
+  }
   return HLU_OK;
 }
 
@@ -492,7 +554,9 @@ hlu_status hlu_get_stats(hlu_handle h, hlu_plan_stats* o) {
 
 hlu_status hlu_get_perm(hlu_handle h, int64_t* perm) {
   if (!h || !perm) return fail(HLU_ERR_ARG, "NULL argument");
-  std::memcpy(perm, h->plan.perm.data(), sizeof(int64_t) * h->plan.n);
+  // doubled plans (products, inverses): the first copy's order (the second
+  // copy's is the same)
+  std::memcpy(perm, h->plan.perm.data(), sizeof(int64_t) * h->plan.n_orig);
   return HLU_OK;
 }
 
@@ -542,6 +606,8 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
     pt.indeg = base + da.indeg;
     pt.base = 0;
     pt.n = (int32_t)sc.ops.size();
+    pt.tune = da.sc == &p.fsched ? h->tune : 0;
+    pt.pad = 0;
     HIPCHK(hipMemcpy(d + da.part(), &pt, sizeof(pt), hipMemcpyHostToDevice));
   }
   std::vector<hlu::MvLR> lr = p.mv_lr;
@@ -563,6 +629,37 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
   if (!p.mv_rows.empty())
     HIPCHK(hipMemcpy(b + p.off_mv_rows, p.mv_rows.data(), p.mv_rows.size() * sizeof(hlu::MvRow), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(b + p.off_perm, p.perm.data(), sizeof(int64_t) * p.n, hipMemcpyHostToDevice));
+  {
+    // points in cluster order (x y z interleaved, then the panel weights)
+    std::vector<double> pts((size_t)4 * p.n);
+    std::memcpy(pts.data(), p.xyz.data(), sizeof(double) * 3 * (size_t)p.n);
+    std::memcpy(pts.data() + 3 * (size_t)p.n, p.area.data(), sizeof(double) * (size_t)p.n);
+    HIPCHK(hipMemcpy(b + p.off_pts, pts.data(), pts.size() * 8, hipMemcpyHostToDevice));
+  }
+  if (p.prm.device_asm) {
+    std::vector<hlu::AsmBlock> ad = p.asm_dense, al = p.asm_lr;
+    for (auto& a : ad) a.U += base;
+    for (auto& a : al) {
+      a.U += base;
+      a.V += base;
+      a.rank += base;
+    }
+    std::vector<hlu::Op> ao = p.asm_ops;
+    for (auto& op : ao) relocate(op, base);
+    std::vector<hlu::Term> at = p.asm_terms;
+    for (auto& t : at) {
+      relocate(t.X, base);
+      relocate(t.Y, base);
+    }
+    if (!ad.empty())
+      HIPCHK(hipMemcpy(b + p.off_asm_dense, ad.data(), ad.size() * sizeof(hlu::AsmBlock), hipMemcpyHostToDevice));
+    if (!al.empty())
+      HIPCHK(hipMemcpy(b + p.off_asm_lr, al.data(), al.size() * sizeof(hlu::AsmBlock), hipMemcpyHostToDevice));
+    if (!ao.empty())
+      HIPCHK(hipMemcpy(b + p.off_asm_ops, ao.data(), ao.size() * sizeof(hlu::Op), hipMemcpyHostToDevice));
+    if (!at.empty())
+      HIPCHK(hipMemcpy(b + p.off_asm_terms, at.data(), at.size() * sizeof(hlu::Term), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMemset(b + p.off_status, 0, 256));
   h->drop_graphs();
   h->base = b;
@@ -575,6 +672,12 @@ hlu_status hlu_bind(hlu_handle h, void* dev_ptr, size_t bytes) {
 static hlu_status run_mv(hlu_handle h, const double* X, const double* B, double beta, double alpha,
                          double* Y, int nrhs, hipStream_t s) {
   hlu::Plan& p = h->plan;
+  if (p.prm.cap_mv == 0) {
+    // no operator copy: the exact matrix by direct summation
+    HIPCHK(hlu_launch_direct_mv((const double*)(h->base + p.off_pts), p.n, p.prm.kernel, X, p.n, B,
+                                beta, alpha, Y, nrhs, 0, s));
+    return HLU_OK;
+  }
   HIPCHK(hlu_launch_mv(h->base + p.off_mv_lr, (int)p.mv_lr.size(), h->base + p.off_mv_rows,
                        (int)p.mv_rows.size(), h->base + p.off_mv_terms, X, p.n, B, beta, alpha,
                        Y, nrhs, s));
@@ -587,11 +690,55 @@ hlu_status hlu_assemble(hlu_handle h, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hlu::Plan& p = h->plan;
   char* b = h->base;
-  HIPCHK(hipMemcpyAsync(b + p.off_work, p.img_work.data(), p.size_work, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(b + p.off_pristine, p.img_work.data(), p.size_work, hipMemcpyHostToDevice, s));
-  if (p.size_mv)
-    HIPCHK(hipMemcpyAsync(b + p.off_mv, p.img_mv.data(), p.size_mv, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(b + p.off_status, 0, 256, s));
+  h->asm_cap_hits = 0;
+  if (p.prm.device_asm) {
+    // the blocks are built on the device from the points: dense entries,
+    // cross approximations chunk by chunk (sharing one workspace), each
+    // chunk recompressed into the factored copy by the truncation kernel
+    int32_t* caphits = (int32_t*)(b + p.off_status + 16);
+    HIPCHK(hipMemsetAsync(b + p.off_work, 0, p.size_work, s));
+    HIPCHK(hipMemsetAsync(b + p.off_status, 0, 256, s));
+    const double* pts = (const double*)(b + p.off_pts);
+    HIPCHK(hlu_launch_asm(b + p.off_asm_dense, (int)p.asm_dense.size(), nullptr, 0, pts, p.n,
+                          p.prm.kernel, p.asm_eps, p.asm_kmax, caphits, s));
+    for (const hlu::AsmChunk& c : p.asm_chunks) {
+      HIPCHK(hlu_launch_asm(nullptr, 0, b + p.off_asm_lr + (uint64_t)c.b0 * sizeof(hlu::AsmBlock),
+                            c.b1 - c.b0, pts, p.n, p.prm.kernel, p.asm_eps, p.asm_kmax, caphits, s));
+      HIPCHK(hlu_launch_ops(hlu::OP_TRUNC, b + p.off_asm_ops + (uint64_t)c.op0 * sizeof(hlu::Op),
+                            c.op1 - c.op0, s));
+    }
+    HIPCHK(hipMemcpyAsync(b + p.off_pristine, b + p.off_work, p.size_work,
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(&h->asm_cap_hits, caphits, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemsetAsync(b + p.off_status, 0, 256, s));
+  } else {
+    HIPCHK(hipMemcpyAsync(b + p.off_work, p.img_work.data(), p.size_work, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(b + p.off_pristine, p.img_work.data(), p.size_work, hipMemcpyHostToDevice, s));
+    if (p.size_mv)
+      HIPCHK(hipMemcpyAsync(b + p.off_mv, p.img_mv.data(), p.size_mv, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(b + p.off_status, 0, 256, s));
+  }
+  if (p.prm.operation != 0) {
+    // products and inverses: no solve, no backward error
+    HIPCHK(hipStreamSynchronize(s));
+    h->anorm = 0.0;
+    h->assembled = true;
+    h->factored = false;
+    return HLU_OK;
+  }
+  if (p.prm.cap_mv == 0) {
+    // |A|_inf of the exact matrix by direct summation
+    double* Y = (double*)(b + p.off_Y);
+    HIPCHK(hlu_launch_direct_mv((const double*)(b + p.off_pts), p.n, p.prm.kernel, nullptr, p.n,
+                                nullptr, 0.0, 1.0, Y, 1, 1, s));
+    std::vector<double> rs(p.n);
+    HIPCHK(hipMemcpyAsync(rs.data(), Y, sizeof(double) * p.n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->anorm = *std::max_element(rs.begin(), rs.end());
+    h->assembled = true;
+    h->factored = false;
+    return HLU_OK;
+  }
   // |A|_inf: all entries of both kernels are positive, so it is the
   // largest entry of A * ones (with the accurate matvec copy)
   std::vector<double> ones(p.n, 1.0);
@@ -719,6 +866,107 @@ hlu_status hlu_set_workers(hlu_handle h, int workers) {
   if (workers < 0 || workers > 65536) return fail(HLU_ERR_ARG, "workers must be in [0, 65536]");
   if (workers != h->workers) h->drop_graphs();
   h->workers = workers;
+  return HLU_OK;
+}
+
+// The factored copy's blocks as they are now on the device, in the file
+// format hlu_import_blocks reads (FP32 factors widened to FP64).
+hlu_status hlu_export_blocks(hlu_handle h, const char* path) {
+  if (!h || !path) return fail(HLU_ERR_ARG, "NULL argument");
+  if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
+  const hlu::Plan& p = h->plan;
+  std::vector<char> img(p.size_work);
+  HIPCHK(hipMemcpy(img.data(), h->base + p.off_work, p.size_work, hipMemcpyDeviceToHost));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(HLU_ERR_ARG, std::string("cannot create ") + path);
+  bool ok = std::fwrite("HLUBLK01", 1, 8, f) == 8;
+  int64_t hdr[2] = {p.n, (int64_t)p.blk.size()};
+  ok = ok && std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
+  ok = ok && std::fwrite(p.perm.data(), 8, p.n, f) == (size_t)p.n;
+  std::vector<double> buf;
+  for (size_t i = 0; ok && i < p.blk.size(); ++i) {
+    const hlu::LBlock& b = p.blk[i];
+    const int64_t kind = b.kind == 'R' ? 1 : 0;
+    const int64_t k = kind ? *(const int32_t*)(img.data() + (b.offRank - p.off_work)) : 0;
+    int64_t d[6] = {p.cl[b.t].off, p.cl[b.s].off, b.m, b.n, kind, k};
+    ok = std::fwrite(d, sizeof(d), 1, f) == 1;
+    if (!kind) {
+      ok = ok && std::fwrite(img.data() + (b.offF - p.off_work), 8, (size_t)b.m * b.n, f) ==
+                     (size_t)b.m * b.n;
+      continue;
+    }
+    for (int side = 0; ok && side < 2; ++side) {
+      const int64_t rows = side ? b.n : b.m;
+      const char* src = img.data() + ((side ? b.offV : b.offU) - p.off_work);
+      buf.resize((size_t)rows * k);
+      if (p.prm.mixed)
+        for (size_t e = 0; e < buf.size(); ++e) buf[e] = ((const float*)src)[e];
+      else
+        std::memcpy(buf.data(), src, 8 * buf.size());
+      ok = std::fwrite(buf.data(), 8, buf.size(), f) == buf.size();
+    }
+  }
+  if (std::fclose(f) != 0) ok = false;
+  if (!ok) return fail(HLU_ERR_ARG, std::string("write failed: ") + path);
+  return HLU_OK;
+}
+
+// Result of a product or inverse plan after hlu_factor: the result
+// quadrant (which holds -A B, or -A^-1) expanded densely with the sign
+// restored, in the original point order (out: n x n column-major, ld).
+hlu_status hlu_export_result(hlu_handle h, double* out, int64_t ld) {
+  if (!h || !out) return fail(HLU_ERR_ARG, "NULL argument");
+  const hlu::Plan& p = h->plan;
+  if (p.prm.operation == 0) return fail(HLU_ERR_STATE, "not a product or inverse plan");
+  if (!h->base || !h->factored) return fail(HLU_ERR_STATE, "hlu_factor first");
+  const int n1 = p.n_orig;
+  if (n1 > 16384) return fail(HLU_ERR_ARG, "n too large for a dense export");
+  if (ld < n1) return fail(HLU_ERR_ARG, "ld < n");
+  std::vector<char> w(p.size_work);
+  HIPCHK(hipMemcpy(w.data(), h->base + p.off_work, p.size_work, hipMemcpyDeviceToHost));
+  for (int j = 0; j < n1; ++j) std::memset(out + (size_t)j * ld, 0, sizeof(double) * n1);
+  const int q = p.prm.operation == 1 ? 0 : 1;   // quadrant (q, q)
+  for (const auto& b : p.blk) {
+    const int r0 = p.cl[b.t].off - q * n1, c0 = p.cl[b.s].off - q * n1;
+    if (r0 < 0 || c0 < 0 || r0 >= n1 || c0 >= n1) continue;
+    auto put = [&](int i, int j, double v) {
+      out[(size_t)p.perm[r0 + i] + (size_t)p.perm[c0 + j] * ld] = -v;
+    };
+    if (b.kind == 'F') {
+      const double* F = (const double*)(w.data() + (b.offF - p.off_work));
+      for (int j = 0; j < b.n; ++j)
+        for (int i = 0; i < b.m; ++i) put(i, j, F[i + (size_t)j * b.m]);
+      continue;
+    }
+    const int k = *(const int32_t*)(w.data() + (b.offRank - p.off_work));
+    const char* U = w.data() + (b.offU - p.off_work);
+    const char* V = w.data() + (b.offV - p.off_work);
+    auto at = [&](const char* base, size_t e) {
+      return p.prm.mixed ? (double)((const float*)base)[e] : ((const double*)base)[e];
+    };
+    for (int j = 0; j < b.n; ++j)
+      for (int i = 0; i < b.m; ++i) {
+        double v = 0.0;
+        for (int l = 0; l < k; ++l) v += at(U, i + (size_t)l * b.m) * at(V, j + (size_t)l * b.n);
+        put(i, j, v);
+      }
+  }
+  return HLU_OK;
+}
+
+hlu_status hlu_set_tuning(hlu_handle h, int trunc_width) {
+  if (!h) return fail(HLU_ERR_ARG, "NULL handle");
+  if (trunc_width != 0 && (trunc_width < 16 || trunc_width > 64))
+    return fail(HLU_ERR_ARG, "trunc_width must be 0 or in [16, 64]");
+  h->tune = trunc_width;
+  if (h->base) {
+    // the factor part's tuning word, in place (read by every later launch)
+    const hlu::Plan& p = h->plan;
+    const uint64_t at = df_factor(p).part() + offsetof(hlu::DfPart, tune);
+    int32_t v = h->tune;
+    HIPCHK(hipMemcpy(h->base + at, &v, 4, hipMemcpyHostToDevice));
+  }
+  h->drop_graphs();
   return HLU_OK;
 }
 
@@ -937,8 +1185,6 @@ hlu_status hlu_set_refinement(hlu_handle h, double refine_tol, int refine_max_it
     return fail(HLU_ERR_ARG, "refine_tol must be >= 0");
   if (refine_max_iter < 0 || refine_max_iter > 15)
     return fail(HLU_ERR_ARG, "refine_max_iter must be in [0, 15]");
-  if (refine_tol > 0.0 && h->plan.prm.cap_mv == 0)
-    return fail(HLU_ERR_ARG, "refinement needs the operator copy (rank_cap_matvec > 0)");
   h->refine_tol = refine_tol;
   h->refine_max_iter = refine_max_iter;
   return HLU_OK;
@@ -994,6 +1240,8 @@ struct hlu_batch_s {
   int64_t ntot = 0;
   uint64_t off_parts = 0, off_queue = 0, off_ready0 = 0, off_ctrl = 0, total = 0;
   char* dev = nullptr;
+  int tune = 0;                   // tuning word of every part (DfPart::tune)
+  int workers = 0;                // workgroups of the launch (0: one per compute unit)
 };
 
 hlu_status hlu_batch_create(const hlu_handle* hs, int count, hlu_batch* out) {
@@ -1067,6 +1315,8 @@ hlu_status hlu_batch_bind(hlu_batch b, void* dev_ptr, size_t bytes) {
     parts[i].indeg = hb + p.off_df_indeg;
     parts[i].base = b->base[i];
     parts[i].n = (int32_t)p.fsched.ops.size();
+    parts[i].tune = b->tune;
+    parts[i].pad = 0;
   }
   char* d = (char*)dev_ptr;
   HIPCHK(hipMemcpy(d + b->off_parts, parts.data(), parts.size() * sizeof(hlu::DfPart),
@@ -1076,6 +1326,23 @@ hlu_status hlu_batch_bind(hlu_batch b, void* dev_ptr, size_t bytes) {
                      hipMemcpyHostToDevice));
   HIPCHK(hipMemset(d + b->off_ctrl, 0, 256));
   b->dev = d;
+  return HLU_OK;
+}
+
+hlu_status hlu_batch_set_tuning(hlu_batch b, int trunc_width, int workers) {
+  if (!b) return fail(HLU_ERR_ARG, "NULL batch");
+  if (trunc_width != 0 && (trunc_width < 16 || trunc_width > 64))
+    return fail(HLU_ERR_ARG, "trunc_width must be 0 or in [16, 64]");
+  if (workers < 0 || workers > 65536) return fail(HLU_ERR_ARG, "workers must be in [0, 65536]");
+  b->tune = trunc_width;
+  b->workers = workers;
+  if (b->dev) {
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+      const uint64_t at = b->off_parts + i * sizeof(hlu::DfPart) + offsetof(hlu::DfPart, tune);
+      int32_t v = b->tune;
+      HIPCHK(hipMemcpy(b->dev + at, &v, 4, hipMemcpyHostToDevice));
+    }
+  }
   return HLU_OK;
 }
 
@@ -1091,6 +1358,7 @@ hlu_status hlu_batch_factor(hlu_batch b, void* stream) {
   long long tps = 0;
   hlu_status st = device_facts(&cus, &tps);
   if (st != HLU_OK) return st;
+  if (b->workers > 0) cus = b->workers;
   for (hlu_handle h : b->hs)
     HIPCHK(hlu_launch_set_int((int32_t*)(h->base + h->plan.off_status), 0, s));
   HIPCHK(hlu_launch_dataflow(0, b->dev + b->off_parts, (int)b->hs.size(), (int*)(b->dev + b->off_queue),
@@ -1119,6 +1387,7 @@ hlu_status hlu_solve(hlu_handle h, const double* b_dev, double* x_dev, int nrhs,
   if (!h || !b_dev || !x_dev) return fail(HLU_ERR_ARG, "NULL argument");
   if (!h->factored) return fail(HLU_ERR_STATE, "hlu_factor first");
   hlu::Plan& p = h->plan;
+  if (p.prm.operation != 0) return fail(HLU_ERR_STATE, "not an LU plan");
   if (nrhs < 1 || nrhs > p.prm.max_nrhs) return fail(HLU_ERR_ARG, "nrhs out of range");
   if (ld < p.n) return fail(HLU_ERR_ARG, "ld < n");
   hipStream_t s = (hipStream_t)stream;
@@ -1190,7 +1459,7 @@ hlu_status hlu_matvec(hlu_handle h, const double* x_dev, double* y_dev, int nrhs
   if (!h || !x_dev || !y_dev) return fail(HLU_ERR_ARG, "NULL argument");
   if (!h->assembled) return fail(HLU_ERR_STATE, "hlu_assemble first");
   hlu::Plan& p = h->plan;
-  if (p.prm.cap_mv == 0) return fail(HLU_ERR_STATE, "planned without the operator copy");
+  if (p.prm.operation != 0) return fail(HLU_ERR_STATE, "not an LU plan");
   if (nrhs < 1 || nrhs > p.prm.max_nrhs) return fail(HLU_ERR_ARG, "nrhs out of range");
   if (ld < p.n) return fail(HLU_ERR_ARG, "ld < n");
   hipStream_t s = (hipStream_t)stream;
@@ -1231,6 +1500,7 @@ hlu_status hlu_sync(hlu_handle h, void* stream, hlu_info* out) {
     HIPCHK(hipMemcpy(c.data(), h->base + h->plan.off_cost, no * hlu::kCostRecBytes,
                      hipMemcpyDeviceToHost));
     for (size_t i = 0; i < no; ++i) inf.cap_hits += (int64_t)c[R * i + 2];
+    inf.cap_hits += h->asm_cap_hits;
     // ranks of the low-rank blocks live at the start of the work region
     size_t nr = 0;
     for (const auto& b : h->plan.blk) nr += b.kind == 'R';
@@ -1355,6 +1625,7 @@ hlu_status hlu_export_factors(hlu_handle h, double* lhat, double* u, void* strea
   if (!h->base) return fail(HLU_ERR_STATE, "hlu_bind first");
   const hlu::Plan& p = h->plan;
   const int n = p.n;
+  if (p.prm.operation != 0) return fail(HLU_ERR_STATE, "not an LU plan (use hlu_export_result)");
   if (n > 8192) return fail(HLU_ERR_ARG, "n too large for a dense export");
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   std::vector<char> w(p.size_work);

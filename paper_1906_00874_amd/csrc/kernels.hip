@@ -1248,6 +1248,67 @@ __device__ __forceinline__ void addd_f32(const PRef& C, const PRef& X, const PRe
     }
   }
 }
+// FP64 factors (plain FP64 mode, dense near-field panels): C^T = Y X^T on
+// the FP64 matrix cores in 16 x 16 tiles, wavefront g taking the columns
+// 16g .. 16g + 15 of each 64 x 64 block of C and its four row tiles, both
+// factors read straight from memory in the operand layout (sixteen
+// consecutive rows of one column per load for column-major panels).
+__device__ __forceinline__ void addd_f64(const PRef& C, const PRef& X, const PRef& Y, int m,
+                                         int n, int k) {
+  const GView gx = gview(X), gy = gview(Y), gc = gview(C);
+  const int tid = threadIdx.x, g = tid >> 6, l = tid & 63, lo = l & 15, hi = l >> 4;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int col0 = c0 + 16 * g;
+    for (int r0 = 0; r0 < m; r0 += 64) {
+      if (col0 >= n) continue;
+      v4d acc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        double yv[4], xv[4][4];
+        int yi[4], yj[4], xi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          yi[q] = min(col0 + lo, n - 1);
+          yj[q] = min(k0 + 4 * q + hi, k - 1);
+        }
+        gload(gy, yi, yj, yv);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) xi[q] = min(r0 + 16 * t + lo, m - 1);
+          gload(gx, xi, yj, xv[t]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + 4 * q < k) {
+            const bool in = k0 + 4 * q + hi < k;
+            const double a = in ? yv[q] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = mfma16x16x4(a, in ? xv[t][q] : 0.0, acc[t]);
+          }
+      }
+      int ci[16], cj[16];
+      bool ok[16];
+      double v[16];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = r0 + 16 * t + lo, j = col0 + hi + 4 * q;
+          ci[4 * t + q] = min(i, m - 1);
+          cj[4 * t + q] = min(j, n - 1);
+          ok[4 * t + q] = i < m && j < n;
+        }
+      gload(gc, ci, cj, v);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[4 * t + q] -= acc[t][q];
+      gstore(gc, ci, cj, ok, v);
+    }
+  }
+}
 __device__ __forceinline__ void addd_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef C = op.p[0], X = op.p[1], Y = op.p[2];
@@ -1256,6 +1317,11 @@ __device__ __forceinline__ void addd_body(const Op& op) {
   if (X.dt == DT_F32 && Y.dt == DT_F32 && X.kind == PK_MAT && Y.kind == PK_MAT) {
     if (m > 0 && n > 0 && k > 0) addd_f32(C, X, Y, m, n, k);
     put_cost(op, 2.0 * m * n * k, 16.0 * m * n + 4.0 * (double)k * (m + n));
+    return;
+  }
+  if (X.dt == DT_F64 && Y.dt == DT_F64 && X.kind == PK_MAT && Y.kind == PK_MAT) {
+    if (m > 0 && n > 0 && k > 0) addd_f64(C, X, Y, m, n, k);
+    put_cost(op, 2.0 * m * n * k, 16.0 * m * n + 8.0 * (double)k * (m + n));
     return;
   }
   double (*sa)[33] = reinterpret_cast<double (*)[33]>(smem);
@@ -2044,7 +2110,7 @@ __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, dou
 }
 
 #define LDS_TRUNC (sizeof(TruncShared))
-__device__ __forceinline__ void d_trunc(const Op& op) {
+__device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
   char* const smem = hlu_lds;
   const PRef U = op.p[0], V = op.p[1];
   const Term* terms = reinterpret_cast<const Term*>(op.p[2].ptr) + op.i0;
@@ -2059,6 +2125,9 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
   double flops = 0.0, bytes = 0.0;
   const double es = U.dt == DT_F64 ? 8.0 : 4.0;
   int capped_any = 0, Kmax = 0, passes = 0, sweeps_all = 0, rxmax = 0, rymax = 0;
+  // widest stack of one pass (tuned per run; the first term of a pass is
+  // always taken, so any width makes progress)
+  const int kwide = (tune & 0xff) > 0 && (tune & 0xff) < KM ? (tune & 0xff) : KM;
   if (tid == 0) sh.te = 0;
   __syncthreads();
   while (sh.te < nterms) {
@@ -2069,7 +2138,7 @@ __device__ __forceinline__ void d_trunc(const Op& op) {
       const int tb = t;
       while (t < nterms && t - tb < TMAX) {
         const int w = pcols(terms[t].X);
-        if (t > tb && K + w > KM) break;
+        if (t > tb && K + w > kwide) break;
         for (int j = 0; j < w; ++j) {
           sh.colt[K + j] = (int8_t)(t - tb);
           sh.colj[K + j] = (int8_t)j;
@@ -3058,7 +3127,7 @@ constexpr unsigned DF_FACTOR_TYPES = (1u << OP_GETRF) | (1u << OP_TRSM_L) | (1u 
 constexpr unsigned DF_SOLVE_TYPES = (1u << OP_MVT) | (1u << OP_MVROW) | (1u << OP_INVAPPLY);
 
 template <unsigned MASK>
-__device__ __forceinline__ bool run_op_masked(const Op& op) {
+__device__ __forceinline__ bool run_op_masked(const Op& op, int tune) {
   start_tick(op);
   switch (op.type) {
     case OP_GETRF: if constexpr ((MASK >> OP_GETRF) & 1) { d_getrf(op); return true; } break;
@@ -3071,7 +3140,7 @@ __device__ __forceinline__ bool run_op_masked(const Op& op) {
       }
       break;
     case OP_PGEMM: if constexpr ((MASK >> OP_PGEMM) & 1) { pgemm_body(op); return true; } break;
-    case OP_TRUNC: if constexpr ((MASK >> OP_TRUNC) & 1) { d_trunc(op); return true; } break;
+    case OP_TRUNC: if constexpr ((MASK >> OP_TRUNC) & 1) { d_trunc(op, tune); return true; } break;
     case OP_ADDD: if constexpr ((MASK >> OP_ADDD) & 1) { addd_body(op); return true; } break;
     case OP_ZERO: if constexpr ((MASK >> OP_ZERO) & 1) { zero_body(op); return true; } break;
     case OP_MVT:
@@ -3147,7 +3216,7 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     if (g < 0) break;
     const DfPart& pt = parts[np == 1 ? 0 : df_part(parts, np, g)];
     const int idx = g - pt.base;
-    if (!run_op_masked<MASK>(reinterpret_cast<const Op*>(pt.ops)[idx]) && tid == 0)
+    if (!run_op_masked<MASK>(reinterpret_cast<const Op*>(pt.ops)[idx], pt.tune) && tid == 0)
       __hip_atomic_store(&ctrl[2], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // one release fence (first wavefront, after the barrier that completed
     // every wavefront's stores) publishes the op's writes; then all threads
@@ -3412,6 +3481,319 @@ extern "C" hipError_t hlu_build_wave_graph(const void* ops_base, const int* star
 
 extern "C" hipError_t hlu_launch_wave(const void* ops, int count, size_t lds, hipStream_t s) {
   return hlu::launch_wave(reinterpret_cast<const hlu::Op*>(ops), count, lds, s);
+}
+
+// ---------------------------------------------------------------- construction
+// Building the H-matrix on the device from the points (cluster order, x y z
+// interleaved, then the panel weights): the dense near field entry by entry,
+// each admissible block by adaptive cross approximation with partial
+// pivoting (one workgroup per block), recompressed afterwards by the
+// truncation kernel.  Entries as in include/hlu.h (kernels of Sec. 6.1).
+namespace hlu {
+
+__device__ __forceinline__ double kentry(const double* __restrict__ pts, int npts, int kernel,
+                                         int i, int j) {
+  const double* a = pts + 3 * (size_t)npts;
+  if (i == j) {
+    if (kernel == 2) return a[i] * (1.0 - log(0.5 * a[i])) + 1.0;
+    if (kernel == 3) return a[i] * (1.0 - log(0.5 * a[i])) * (0.5 / M_PI) + 1.0;
+    return 2.0 * sqrt(a[i] / M_PI) / (4.0 * M_PI) * sqrt(M_PI) + 1.0;
+  }
+  const double dx = pts[3 * i] - pts[3 * j], dy = pts[3 * i + 1] - pts[3 * j + 1],
+               dz = pts[3 * i + 2] - pts[3 * j + 2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if (kernel == 2) return -a[j] * 0.5 * log(r2);
+  if (kernel == 3) return -a[j] * 0.5 * log(r2) * (0.5 / M_PI);
+  const double g = rsqrt(r2) * (0.25 / M_PI);
+  return kernel == 0 ? g * a[j] : g;
+}
+
+__global__ void __launch_bounds__(NT) k_asm_dense(const AsmBlock* __restrict__ tab,
+                                                  const double* __restrict__ pts, int npts,
+                                                  int kernel) {
+  const AsmBlock b = tab[blockIdx.x];
+  HLU_G double* F = gptr<double>(b.U);
+  const int tot = b.m * b.n;
+  for (int e = threadIdx.x; e < tot; e += NT) {
+    const int i = e % b.m, j = e / b.m;
+    F[e] = kentry(pts, npts, kernel, b.r0 + i, b.c0 + j);
+  }
+}
+
+// block-wide argmax of (v, index) with the smallest index among equal
+// values; the result is returned to every thread
+__device__ __forceinline__ void block_argmax(double& v, int& ix, double* rv, int* ri) {
+  wave_argmax(v, ix);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rv[w] = v;
+    ri[w] = ix;
+  }
+  __syncthreads();
+  v = rv[0];
+  ix = ri[0];
+  for (int q = 1; q < NT / 64; ++q)
+    if (rv[q] > v || (rv[q] == v && ri[q] < ix)) {
+      v = rv[q];
+      ix = ri[q];
+    }
+  __syncthreads();
+}
+__device__ __forceinline__ double block_sum_d(double v, double* rv) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) rv[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < NT / 64; ++q) t += rv[q];
+  __syncthreads();
+  return t;
+}
+
+#define ASM_KMAX 64
+#define ASM_MAXDIM 65536
+#define LDS_ASM (2 * (ASM_MAXDIM / 32) * 4 + 2 * ASM_KMAX * 8 + 16 * 8 + 16 * 4)
+// Adaptive cross approximation with partial pivoting (one block per
+// workgroup): step k takes the residual row i of the block, its largest
+// entry |.| over the unused columns as pivot (column js), the residual
+// column js, and the rank-one term col * row / pivot; the next pivot row is
+// the largest entry of that column over the unused rows.  Stops after two
+// consecutive terms with |u||v| <= eps |S_k|_F (S_k the current sum, its
+// Frobenius norm updated exactly from the new term's inner products), at
+// kmax terms (counted in *caphits), or when no usable row is left.  U keeps
+// the columns negated on exit.
+__global__ void __launch_bounds__(NT) k_asm_aca(const AsmBlock* __restrict__ tab,
+                                                const double* __restrict__ pts, int npts,
+                                                int kernel, double eps, int kmax,
+                                                int32_t* caphits) {
+  extern __shared__ __align__(16) char lds[];
+  uint32_t* urow = reinterpret_cast<uint32_t*>(lds);
+  uint32_t* ucol = urow + ASM_MAXDIM / 32;
+  double* bu = reinterpret_cast<double*>(ucol + ASM_MAXDIM / 32);
+  double* bv = bu + ASM_KMAX;
+  double* rv = bv + ASM_KMAX;
+  int* ri = reinterpret_cast<int*>(rv + 16);
+  const AsmBlock b = tab[blockIdx.x];
+  const int m = b.m, n = b.n, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  HLU_G double* U = gptr<double>(b.U);
+  HLU_G double* V = gptr<double>(b.V);
+  for (int q = tid; q < (m + 31) / 32; q += NT) urow[q] = 0u;
+  for (int q = tid; q < (n + 31) / 32; q += NT) ucol[q] = 0u;
+  __syncthreads();
+  int k = 0, i = 0, small = 0, zero_tries = 0;
+  double norm2 = 0.0;
+  kmax = min(kmax, min(min(m, n), ASM_KMAX));
+  while (k < kmax) {
+    // residual row i -> V[:, k]
+    if (tid < k) bu[tid] = U[i + (size_t)tid * m];
+    __syncthreads();
+    double best = -1.0;
+    int js = n;
+    for (int j = tid; j < n; j += NT) {
+      double v = kentry(pts, npts, kernel, b.r0 + i, b.c0 + j);
+      for (int l = 0; l < k; ++l) v -= bu[l] * V[j + (size_t)l * n];
+      V[j + (size_t)k * n] = v;
+      const bool used = (ucol[j >> 5] >> (j & 31)) & 1u;
+      if (!used && fabs(v) > best) {
+        best = fabs(v);
+        js = j;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) urow[i >> 5] |= 1u << (i & 31);
+    block_argmax(best, js, rv, ri);
+    if (js >= n || !(best > 0.0)) {
+      // zero residual row: try the first unused row instead
+      int nx = m;
+      for (int q = tid; q < m; q += NT)
+        if (!((urow[q >> 5] >> (q & 31)) & 1u)) {
+          nx = q;
+          break;
+        }
+      double d = -(double)nx;
+      block_argmax(d, nx, rv, ri);   // the smallest candidate (largest -q)
+      if (nx >= m || ++zero_tries > 3) break;
+      i = nx;
+      continue;
+    }
+    if (tid == 0) ucol[js >> 5] |= 1u << (js & 31);
+    const double piv = V[js + (size_t)k * n];
+    // residual column js -> U[:, k]
+    if (tid < k) bv[tid] = V[js + (size_t)tid * n];
+    __syncthreads();
+    double nu = 0.0, bestc = -1.0;
+    int inext = m;
+    for (int q = tid; q < m; q += NT) {
+      double v = kentry(pts, npts, kernel, b.r0 + q, b.c0 + js);
+      for (int l = 0; l < k; ++l) v -= bv[l] * U[q + (size_t)l * m];
+      U[q + (size_t)k * m] = v;
+      nu += v * v;
+      const bool used = (urow[q >> 5] >> (q & 31)) & 1u;
+      if (!used && fabs(v) > bestc) {
+        bestc = fabs(v);
+        inext = q;
+      }
+    }
+    double nv = 0.0;
+    const double ip = 1.0 / piv;
+    for (int j = tid; j < n; j += NT) {
+      const double v = V[j + (size_t)k * n] * ip;
+      V[j + (size_t)k * n] = v;
+      nv += v * v;
+    }
+    __syncthreads();   // U[:, k] and V[:, k] complete before other lanes read them
+    // cross terms sum_l (u_l . u_k)(v_l . v_k): wavefront w takes l = w, w + 4, ...
+    double cross = 0.0;
+    for (int l = wid; l < k; l += NT / 64) {
+      double a = 0.0, c = 0.0;
+      for (int q = lane; q < m; q += 64) a += U[q + (size_t)l * m] * U[q + (size_t)k * m];
+      for (int j = lane; j < n; j += 64) c += V[j + (size_t)l * n] * V[j + (size_t)k * n];
+      a = wave_sum(a);
+      c = wave_sum(c);
+      if (lane == 0) cross += a * c;
+    }
+    nu = block_sum_d(nu, rv);
+    nv = block_sum_d(nv, rv);
+    cross = block_sum_d(cross, rv);
+    norm2 += nu * nv + 2.0 * cross;
+    ++k;
+    block_argmax(bestc, inext, rv, ri);
+    if (sqrt(nu * nv) <= eps * sqrt(fabs(norm2))) {
+      if (++small >= 2) break;
+    } else {
+      small = 0;
+    }
+    if (inext >= m || !(bestc >= 0.0)) break;
+    if (k == kmax && tid == 0) atomicAdd(caphits, 1);
+    i = inext;
+  }
+  for (int e = tid; e < m * k; e += NT) U[e] = -U[e];
+  if (tid == 0) *gptr<int32_t>(b.rank) = k;
+}
+
+// Y = beta B + alpha A X by direct summation over the exact entries (no
+// compression): thread t of workgroup g owns row g * NT + t; the columns go
+// by tiles of DMV_TJ points staged in LDS with their X rows.  With absmode,
+// Y_i = sum_j |A_ij| (X, B unused).  NRB >= nrhs.
+#define DMV_TJ 64
+template <int KER, int NRB>
+__global__ void __launch_bounds__(NT) k_direct_mv(const double* __restrict__ pts, int npts,
+                                                  const double* __restrict__ X, int ldx,
+                                                  const double* __restrict__ B, double beta,
+                                                  double alpha, double* __restrict__ Y, int nrhs,
+                                                  int absmode) {
+  __shared__ double sp[DMV_TJ * 4];
+  __shared__ double sx[DMV_TJ * (NRB + 1)];
+  const int i = blockIdx.x * NT + threadIdx.x;
+  const int ii = min(i, npts - 1);
+  const double* a = pts + 3 * (size_t)npts;
+  const double xi = pts[3 * ii], yi = pts[3 * ii + 1], zi = pts[3 * ii + 2];
+  double acc[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) acc[r] = 0.0;
+  for (int j0 = 0; j0 < npts; j0 += DMV_TJ) {
+    const int nj = min(DMV_TJ, npts - j0);
+    for (int e = threadIdx.x; e < DMV_TJ * 4; e += NT) {
+      const int jj = e >> 2, c = e & 3, j = j0 + min(jj, nj - 1);
+      sp[e] = c < 3 ? pts[3 * j + c] : a[j];
+    }
+    // X rows of the tile: consecutive threads read consecutive rows of one
+    // column (coalesced); padded rows keep the LDS stores conflict-free
+    if (!absmode)
+      for (int e = threadIdx.x; e < DMV_TJ * NRB; e += NT) {
+        const int jj = e % DMV_TJ, r = e / DMV_TJ;
+        sx[jj * (NRB + 1) + r] = (jj < nj && r < nrhs) ? X[(j0 + jj) + (size_t)r * ldx] : 0.0;
+      }
+    __syncthreads();
+    for (int jj = 0; jj < nj; ++jj) {
+      const int j = j0 + jj;
+      double g;
+      if (j == ii) {
+        g = kentry(pts, npts, KER, ii, ii);
+      } else {
+        const double dx = xi - sp[4 * jj], dy = yi - sp[4 * jj + 1], dz = zi - sp[4 * jj + 2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (KER == 2) g = -sp[4 * jj + 3] * 0.5 * log(r2);
+        else if (KER == 3) g = -sp[4 * jj + 3] * 0.5 * log(r2) * (0.5 / M_PI);
+        else if (KER == 0) g = rsqrt(r2) * (0.25 / M_PI) * sp[4 * jj + 3];
+        else g = rsqrt(r2) * (0.25 / M_PI);
+      }
+      if (absmode) {
+        acc[0] += fabs(g);
+      } else {
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) acc[r] += g * sx[jj * (NRB + 1) + r];
+      }
+    }
+    __syncthreads();
+  }
+  if (i < npts) {
+    if (absmode) {
+      Y[i] = acc[0];
+    } else {
+      for (int r = 0; r < nrhs; ++r) {
+        const double bv = beta != 0.0 ? beta * B[i + (size_t)r * ldx] : 0.0;
+        Y[i + (size_t)r * ldx] = bv + alpha * acc[r];
+      }
+    }
+  }
+}
+
+}  // namespace hlu
+
+extern "C" size_t hlu_asm_lds_bytes(void) { return LDS_ASM; }
+
+extern "C" hipError_t hlu_launch_asm(const void* dense, int ndense, const void* lr, int nlr,
+                                     const double* pts, int npts, int kernel, double eps,
+                                     int kmax, int32_t* caphits, hipStream_t s) {
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&hlu::k_asm_aca), hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)LDS_ASM);
+  if (attr != hipSuccess) return attr;
+  if (ndense > 0)
+    hipLaunchKernelGGL(hlu::k_asm_dense, dim3(ndense), dim3(NT), 0, s,
+                       reinterpret_cast<const hlu::AsmBlock*>(dense), pts, npts, kernel);
+  if (nlr > 0)
+    hipLaunchKernelGGL(hlu::k_asm_aca, dim3(nlr), dim3(NT), LDS_ASM, s,
+                       reinterpret_cast<const hlu::AsmBlock*>(lr), pts, npts, kernel, eps, kmax,
+                       caphits);
+  return hipGetLastError();
+}
+
+template <int KER>
+static void launch_dmv(dim3 g, const double* pts, int npts, const double* X, int ldx,
+                       const double* B, double beta, double alpha, double* Y, int nrhs,
+                       int absmode, hipStream_t s) {
+  if (absmode || nrhs <= 4)
+    hipLaunchKernelGGL((hlu::k_direct_mv<KER, 4>), g, dim3(NT), 0, s, pts, npts, X, ldx, B, beta,
+                       alpha, Y, nrhs, absmode);
+  else if (nrhs <= 16)
+    hipLaunchKernelGGL((hlu::k_direct_mv<KER, 16>), g, dim3(NT), 0, s, pts, npts, X, ldx, B,
+                       beta, alpha, Y, nrhs, absmode);
+  else if (nrhs <= 32)
+    hipLaunchKernelGGL((hlu::k_direct_mv<KER, 32>), g, dim3(NT), 0, s, pts, npts, X, ldx, B,
+                       beta, alpha, Y, nrhs, absmode);
+  else
+    hipLaunchKernelGGL((hlu::k_direct_mv<KER, 64>), g, dim3(NT), 0, s, pts, npts, X, ldx, B,
+                       beta, alpha, Y, nrhs, absmode);
+}
+
+// Y = beta B + alpha A X (n x nrhs, leading dimension ld, nrhs <= 64) with
+// the exact matrix by direct summation; absmode: Y = |A| 1 (nrhs ignored).
+extern "C" hipError_t hlu_launch_direct_mv(const double* pts, int npts, int kernel,
+                                           const double* X, int ld, const double* B, double beta,
+                                           double alpha, double* Y, int nrhs, int absmode,
+                                           hipStream_t s) {
+  if (npts <= 0) return hipSuccess;
+  if (nrhs > 64 || kernel < 0 || kernel > 3) return hipErrorInvalidValue;
+  dim3 g((npts + NT - 1) / NT);
+  switch (kernel) {
+    case 0: launch_dmv<0>(g, pts, npts, X, ld, B, beta, alpha, Y, nrhs, absmode, s); break;
+    case 1: launch_dmv<1>(g, pts, npts, X, ld, B, beta, alpha, Y, nrhs, absmode, s); break;
+    case 2: launch_dmv<2>(g, pts, npts, X, ld, B, beta, alpha, Y, nrhs, absmode, s); break;
+    default: launch_dmv<3>(g, pts, npts, X, ld, B, beta, alpha, Y, nrhs, absmode, s); break;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- static scratch

@@ -87,6 +87,20 @@ struct DfPart {
   uint64_t indeg0;     // const int32[n]
   uint64_t indeg;      // int32[n], consumed by the run
   int32_t base, n;
+  int32_t tune;        // tile shapes of this part's ops: bits 0-7 the widest
+                       // stack a truncation pass takes (0: 64)
+  int32_t pad;
+};
+
+// Device assembly: one block to build from the points.  Dense: its entries
+// into U (ld m).  Low-rank: adaptive cross approximation into the FP64
+// workspace panels U (m x kmax, ld m) and V (n x kmax, ld n), the rank
+// reached written to the int32 at `rank`; the block is then U V^T with
+// U's columns negated (the form the truncation that recompresses it into
+// the factored copy takes).
+struct AsmBlock {
+  uint64_t U, V, rank;
+  int32_t r0, c0, m, n;
 };
 
 // Matvec with the refinement copy: per low-rank block, T = V^T X[s];

@@ -32,15 +32,43 @@ namespace hlu {
 static const double kFourPi = 4.0 * M_PI;
 
 // ---------------------------------------------------------------- entries
+// Collocation entries between panel midpoints x_i with one-point quadrature
+// over the column panel (weight a_j: area, or length for the 1D and 2D
+// kernels) plus the identity.  Kernels (Sec. 6.1): 1/(4 pi r) (d = 3),
+// -log r (d = 1), -log(r) / (2 pi) (d = 2).  The self term of a d = 1 or
+// d = 2 panel is the exact integral of the kernel over the straight panel
+// of length h around its midpoint: h (1 - log(h / 2)), times 1 / (2 pi) for
+// d = 2.
 struct Entries {
   const double* x;
   const double* a;
   int kernel;
+  // doubled plans: positions [0, n1) and [n1, 2 n1) are two copies of the
+  // same points; each quadrant holds 0, A (kernel), B (kernel_b) or I
+  int n1 = 0, op = 0, kernel_b = 0;
   inline double operator()(int i, int j) const {
-    if (i == j) return 2.0 * std::sqrt(a[i] / M_PI) / kFourPi * std::sqrt(M_PI) + 1.0;
+    if (op == 0) return base(kernel, i, j);
+    const int qi = i >= n1, qj = j >= n1, ii = i - qi * n1, jj = j - qj * n1;
+    if (op == 1) {
+      if (qi == 0 && qj == 1) return base(kernel, ii, jj);
+      if (qi == 1 && qj == 0) return base(kernel_b, ii, jj);
+      return 0.0;
+    }
+    if (qi == 0 && qj == 0) return base(kernel, ii, jj);
+    if (qi != qj) return ii == jj ? 1.0 : 0.0;
+    return 0.0;
+  }
+  inline double base(int kernel, int i, int j) const {
+    if (i == j) {
+      if (kernel == 2) return a[i] * (1.0 - std::log(0.5 * a[i])) + 1.0;
+      if (kernel == 3) return a[i] * (1.0 - std::log(0.5 * a[i])) / (2.0 * M_PI) + 1.0;
+      return 2.0 * std::sqrt(a[i] / M_PI) / kFourPi * std::sqrt(M_PI) + 1.0;
+    }
     double dx = x[3 * i] - x[3 * j], dy = x[3 * i + 1] - x[3 * j + 1],
            dz = x[3 * i + 2] - x[3 * j + 2];
     double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+    if (kernel == 2) return -a[j] * std::log(r);
+    if (kernel == 3) return -a[j] * std::log(r) / (2.0 * M_PI);
     double g = 1.0 / (kFourPi * r);
     return kernel == 0 ? g * a[j] : g;
   }
@@ -1307,6 +1335,39 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   p.cl.clear();
   p.leaves.clear();
   build_cluster(p, idx, 0, n, xyz, order);
+  p.n_orig = n;
+  int croot = 0;
+  if (prm.operation != 0) {
+    // second copy of every cluster (same boxes, offsets + n) under a new
+    // root, so every quadrant of the doubled matrix has the original block
+    // tree; the second copy's positions map to the same points
+    const int nc = (int)p.cl.size(), nl = (int)p.leaves.size();
+    for (int c = 0; c < nc; ++c) {
+      Cluster c2 = p.cl[c];
+      c2.off += n;
+      if (c2.son[0] >= 0) {
+        c2.son[0] += nc;
+        c2.son[1] += nc;
+      }
+      if (c2.leaf >= 0) c2.leaf += nl;
+      c2.first_leaf += nl;
+      p.cl.push_back(c2);
+    }
+    for (int l = 0; l < nl; ++l) p.leaves.push_back(p.leaves[l] + nc);
+    for (int i = 0; i < n; ++i) order.push_back(order[i]);
+    Cluster r = p.cl[0];
+    r.off = 0;
+    r.size = 2 * n;
+    r.son[0] = 0;
+    r.son[1] = nc;
+    r.leaf = -1;
+    r.first_leaf = 0;
+    r.nleaves = 2 * nl;
+    croot = (int)p.cl.size();
+    p.cl.push_back(r);
+    n = 2 * n;
+    p.n = n;
+  }
   p.perm = order;
   p.xyz.resize((size_t)3 * n);
   p.area.resize(n);
@@ -1317,7 +1378,14 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   // block tree
   p.bn.clear();
   p.blk.clear();
-  p.broot = build_blocks(p, 0, 0);
+  p.broot = build_blocks(p, croot, croot);
+  if (prm.operation != 0) {
+    if (p.bn[p.broot].kind != 'H') {
+      p.err = "doubled matrix without a 2 x 2 root";
+      return false;
+    }
+    p.result_node = p.bn[p.broot].son[prm.operation == 1 ? 0 : 3];
+  }
 
   // ---- layout of the work region: ranks | dense | low-rank
   const int es_lr = prm.mixed ? 4 : 8;
@@ -1361,7 +1429,7 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   cur = align256(cur + (uint64_t)n * 64 * 8);
 
   // ---- host assembly
-  Entries E{p.xyz.data(), p.area.data(), prm.kernel};
+  Entries E{p.xyz.data(), p.area.data(), prm.kernel, p.n_orig, prm.operation, prm.kernel_b};
   p.img_work.assign(p.size_work, 0);
   std::vector<int> rids;
   for (size_t i = 0; i < p.blk.size(); ++i) rids.push_back((int)i);
@@ -1376,7 +1444,7 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   if (prm.cap_mv > 0) eps_need = std::min(eps_need, prm.eps_mv);
   double eps_aca = eps_need * 0.1;
   char* img = p.img_work.data();
-  parallel_for((int)rids.size(), [&](int q) {
+  if (!prm.device_asm) parallel_for((int)rids.size(), [&](int q) {
     LBlock& b = p.blk[rids[q]];
     const Cluster &ct = p.cl[b.t], &cs = p.cl[b.s];
     if (b.kind == 'F') {
@@ -1441,6 +1509,92 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     std::memcpy(p.img_mv.data() + (b.mvV - p.off_mv), mvV[i].data(), mvV[i].size() * 8);
   }
   cur = align256(cur + mw);
+
+  // ---- points in cluster order (device assembly, direct-summation residual)
+  p.off_pts = cur;
+  cur = align256(cur + (uint64_t)n * 4 * 8);
+
+  // ---- device assembly: block tables, ACA workspace in chunks, and the
+  // truncations that recompress each cross approximation into the factored
+  // copy (C = 0 minus one term: -U_aca V_aca^T with U_aca negated)
+  p.asm_dense.clear();
+  p.asm_lr.clear();
+  p.asm_chunks.clear();
+  p.asm_ops.clear();
+  p.asm_terms.clear();
+  if (prm.device_asm) {
+    const int KA = p.asm_kmax;
+    p.asm_eps = eps_aca;
+    int nlr = 0;
+    for (auto& b : p.blk) nlr += b.kind == 'R';
+    p.off_asm_ranks = cur;
+    cur = align256(cur + (uint64_t)std::max(1, nlr) * 4);
+    // workspace: at most 1 GiB (or the largest single block) per chunk
+    const uint64_t cap_ws = (uint64_t)1 << 30;
+    uint64_t ws = 0, ws_max = 0;
+    int lr_i = 0;
+    AsmChunk ch{0, 0, 0, 0};
+    for (auto& b : p.blk) {
+      const Cluster &ct = p.cl[b.t], &cs = p.cl[b.s];
+      if (b.kind == 'F') {
+        p.asm_dense.push_back(AsmBlock{b.offF, 0, 0, ct.off, cs.off, b.m, b.n});
+        continue;
+      }
+      const uint64_t need = align256((uint64_t)b.m * KA * 8) + align256((uint64_t)b.n * KA * 8);
+      if (ws > 0 && ws + need > cap_ws) {
+        ch.b1 = lr_i;
+        ch.op1 = (int)p.asm_ops.size();
+        p.asm_chunks.push_back(ch);
+        ch = AsmChunk{lr_i, lr_i, (int)p.asm_ops.size(), 0};
+        ws = 0;
+      }
+      AsmBlock a{ws, ws + align256((uint64_t)b.m * KA * 8), p.off_asm_ranks + 4 * (uint64_t)lr_i,
+                 ct.off, cs.off, b.m, b.n};   // U, V relative to the workspace for now
+      ws += need;
+      ws_max = std::max(ws_max, ws);
+      p.asm_lr.push_back(a);
+      Term t;
+      std::memset(&t, 0, sizeof(t));
+      t.X = PRef{a.U, a.rank, b.m, b.m, KA, DT_F64, 0, PK_MAT, 0};
+      t.Y = PRef{a.V, a.rank, b.n, b.n, KA, DT_F64, 0, PK_MAT, 0};
+      Op o;
+      std::memset(&o, 0, sizeof(o));
+      o.type = OP_TRUNC;
+      o.i0 = (int32_t)p.asm_terms.size();
+      o.i1 = 1;
+      o.i2 = prm.cap_f | (prm.fixed_rank << 16);
+      o.d0 = prm.fixed_rank > 0 ? 0.0 : prm.eps_f;
+      const uint8_t dt = prm.mixed ? DT_F32 : DT_F64;
+      o.p[0] = PRef{b.offU, b.offRank, b.m, b.m, prm.cap_f, dt, 0, PK_MAT, 0};
+      o.p[1] = PRef{b.offV, b.offRank, b.n, b.n, prm.cap_f, dt, 0, PK_MAT, 0};
+      p.asm_terms.push_back(t);
+      p.asm_ops.push_back(o);
+      ++lr_i;
+    }
+    ch.b1 = lr_i;
+    ch.op1 = (int)p.asm_ops.size();
+    if (ch.b1 > ch.b0) p.asm_chunks.push_back(ch);
+    p.off_asm_ws = cur;
+    p.size_asm_ws = align256(ws_max);
+    cur = align256(cur + std::max<uint64_t>(256, p.size_asm_ws));
+    for (auto& a : p.asm_lr) {
+      a.U += p.off_asm_ws;
+      a.V += p.off_asm_ws;
+    }
+    for (auto& t : p.asm_terms) {
+      t.X.ptr += p.off_asm_ws;
+      t.Y.ptr += p.off_asm_ws;
+    }
+    p.off_asm_dense = cur;
+    cur = align256(cur + std::max<size_t>(1, p.asm_dense.size()) * sizeof(AsmBlock));
+    p.off_asm_lr = cur;
+    cur = align256(cur + std::max<size_t>(1, p.asm_lr.size()) * sizeof(AsmBlock));
+    p.off_asm_ops = cur;
+    cur = align256(cur + std::max<size_t>(1, p.asm_ops.size()) * sizeof(Op));
+    p.off_asm_terms = cur;
+    cur = align256(cur + std::max<size_t>(1, p.asm_terms.size()) * sizeof(Term));
+    for (auto& o : p.asm_ops) o.p[2].ptr = p.off_asm_terms;
+  }
 
   // ---- solve / refinement workspace
   int nr = prm.max_nrhs;
@@ -1542,7 +1696,20 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
       }
     }
     B.cost_cur = 0;
-    B.lu(p.broot);
+    if (prm.operation == 0) {
+      B.lu(p.broot);
+    } else {
+      const BNode& R = p.bn[p.broot];
+      const int q00 = R.son[0], q01 = R.son[1], q10 = R.son[2], q11 = R.son[3];
+      if (prm.operation == 1) {
+        B.gemm(q00, q01, q10);
+      } else {
+        B.lu(q00);
+        B.trsm_l(q00, q01);
+        B.trsm_u(q10, q00);
+        B.gemm(q11, q10, q01);
+      }
+    }
     if (!p.err.empty()) return false;
     B.finish();
     if (std::getenv("HLU_DEBUG"))
@@ -1577,8 +1744,10 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
     Y.rank = p.off_nrhs;
     Y.cl = 0;
     Y.dt = DT_F64;
-    B.fwd(p.broot, Y);
-    B.bwd(p.broot, Y);
+    if (prm.operation == 0) {
+      B.fwd(p.broot, Y);
+      B.bwd(p.broot, Y);
+    }
     B.finish();
     p.off_cost_s = cur;
     for (auto& op : p.ssched.ops) op.cost += p.off_cost_s;

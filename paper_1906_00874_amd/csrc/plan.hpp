@@ -23,6 +23,22 @@ struct Params {
   int refine_max_iter = 10;
   int max_nrhs = 32;
   uint64_t scratch_cap = 0;   // 0: no reuse of H-GEMM temporaries
+  int device_asm = 0;         // 1: blocks built on the device (hlu_assemble)
+  // 0: H-LU of the kernel matrix.  1 and 2: a doubled matrix on two copies
+  // of the points, M = [M11 M12; M21 M22] with every quadrant on the
+  // original block tree; 1 (product): M12 = A, M21 = B (kernel_b), M11 =
+  // M22 = 0, schedule M11 -= M12 M21, so M11 = -A B; 2 (inverse): M11 = A,
+  // M12 = M21 = I, M22 = 0, schedule LU(M11), M12 := L^-1 P M12,
+  // M21 := M21 U^-1, M22 -= M21 M12, so M22 = -A^-1.
+  int operation = 0;
+  int kernel_b = 0;
+};
+
+// Device assembly of the low-rank blocks in chunks that share one ACA
+// workspace: blocks [b0, b1) of the low-rank table, their recompression ops
+// [op0, op1) of asm_ops.
+struct AsmChunk {
+  int b0, b1, op0, op1;
 };
 
 struct Cluster {
@@ -81,6 +97,8 @@ struct Plan {
   std::vector<BNode> bn;
   std::vector<LBlock> blk;
   int broot = 0;
+  int n_orig = 0;                  // points per copy (n / 2 for doubled plans)
+  int result_node = -1;            // block node of the result quadrant (operation 1, 2)
 
   // device layout (byte offsets from the bound base)
   uint64_t off_status = 0;         // int32 info, int32 flags, ...
@@ -116,6 +134,18 @@ struct Plan {
   std::vector<MvLR> mv_lr;
   std::vector<MvTerm> mv_terms;
   std::vector<MvRow> mv_rows;
+
+  // points in cluster order on the device (x, y, z interleaved; then area)
+  uint64_t off_pts = 0;
+  // device assembly (prm.device_asm)
+  std::vector<AsmBlock> asm_dense, asm_lr;   // offsets relative to the base
+  std::vector<AsmChunk> asm_chunks;
+  std::vector<Op> asm_ops;                   // recompression (OP_TRUNC), one per low-rank block
+  std::vector<Term> asm_terms;
+  uint64_t off_asm_dense = 0, off_asm_lr = 0, off_asm_ranks = 0, off_asm_ops = 0,
+           off_asm_terms = 0, off_asm_ws = 0, size_asm_ws = 0;
+  int asm_kmax = 64;
+  double asm_eps = 0.0;                      // cross-approximation tolerance
 
   double anorm_inf = 0.0;          // max row sum of |A| (exact)
   double flops_model = 0.0;

@@ -437,3 +437,85 @@ def test_refinement_not_converged_is_reported(P):
     st, inf = h.sync(check=False)
     assert st == 5
     assert inf.eta_final > 1e-15
+
+
+def test_autotuned_batch_matches_alone_at_the_chosen_shape(P):
+    """The autotuner picks a (truncation stack width, workers) pair by timing
+    the batch; at that choice the batch still equals each matrix factored
+    alone with the same stack width, bit for bit, and a narrow stack (32)
+    keeps the factor accuracy bound |A - Lhat U| <= 10 eps |A| (+ |A - A_H|)."""
+    from hlu_inputs.geometry import ellipsoid_surface
+    from paper_1906_00874_amd import autotune
+    geo = [icosphere(3), ellipsoid_surface(3, (1.5, 0.7, 1.0)), ellipsoid_surface(2, (0.6, 1.8, 1.2))]
+    hs = [P.HLU(x, a, leaf=32, eta=2.0, eps=1e-6, cap=32, precision=P.PREC_MIXED, max_nrhs=1)
+          for x, a in geo]
+    for h in hs:
+        h.set_executor(1)
+    bt = P.Batch(hs)
+    res = autotune.tune_batch(bt, hs, reps=1, log=_say)
+    _say("autotune choice", res["trunc_width"], res["workers"], res["table"])
+    assert res["trunc_width"] in autotune.WIDTHS and res["workers"] in autotune.WORKERS
+    assert len(res["table"]) == len(autotune.WIDTHS) + len(autotune.WORKERS) - 1
+    for h in hs:
+        h.reset()
+    bt.factor()
+    bt.sync()
+    got = [(h.export_factors(), h.export_pivots()) for h in hs]
+    for h, ((L0, U0), p0) in zip(hs, got):
+        h.reset()
+        h.set_tuning(res["trunc_width"])
+        h.factor()
+        st, inf = h.sync(check=False)
+        assert st == 0
+        L, U = h.export_factors()
+        assert np.array_equal(h.export_pivots(), p0)
+        assert np.array_equal(L, L0) and np.array_equal(U, U0)
+    xyz, area = geo[0]
+    h = hs[0]
+    h.reset()
+    h.set_tuning(32)
+    h.factor()
+    h.sync()
+    Lg, Ug = h.export_factors()
+    A = O.dense_matrix(xyz, area)[np.ix_(h.perm(), h.perm())]
+    rel = np.linalg.norm(A - Lg @ Ug) / np.linalg.norm(A)
+    _say("stack width 32: |A - LU|/|A|", rel)
+    assert rel <= 11 * 1e-6
+
+
+@pytest.mark.parametrize("kernel,reading,geo,prec", [
+    (2, O.READING_LOG1D, "segment", 0), (3, O.READING_LOG2D, "circle", 1)])
+def test_log_kernels_factor_and_refined_solve(P, kernel, reading, geo, prec):
+    """Second workloads of Sec. 6.1: the d = 1 (-log r on [0, 1]) and d = 2
+    (-log(r)/(2 pi) on a circle) kernels, n = 4096: factor accuracy against
+    the exact matrix, refined backward error against the exact operator and
+    the solution against the oracle's (P9(b) bound)."""
+    import torch
+    from hlu_inputs import circle, segment
+    xyz, h = (segment if geo == "segment" else circle)(4096)
+    _say("log kernel", kernel, geo, "precision", prec)
+    hl = P.HLU(xyz, h, kernel=kernel, leaf=32, eta=2.0, eps=1e-6, cap=32, precision=prec,
+               refine_tol=1e-10, max_nrhs=4)
+    hl.set_executor(1)
+    hl.factor()
+    st, inf = hl.sync(check=False)
+    assert st == 0
+    Lg, Ug = hl.export_factors()
+    perm = hl.perm()
+    A = O.dense_matrix(xyz, h, reading)[np.ix_(perm, perm)]
+    rel = np.linalg.norm(A - Lg @ Ug) / np.linalg.norm(A)
+    del Lg, Ug, A
+    b = rhs_normal(17, hl.n, 4)
+    x = hl.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    st, inf = hl.sync(check=False)
+    assert st == 0
+    eta = O.backward_error(xyz, h, x, b, reading)
+    H = O.HMatrix(xyz, h, 32, 2.0, O.Rule(eps=1e-6, cap=32), reading=reading)
+    O.factor(H)
+    xo, hist = O.refine(H, b, tol=1e-10)
+    e = np.abs(x - xo).max() / np.abs(xo).max()
+    _say("log kernel", kernel, "|A - LU|/|A|", rel, "iters", inf.iters, "eta", eta,
+         "|x - x_oracle|", e)
+    assert rel <= 11 * 1e-6
+    assert eta <= 1e-10 and inf.eta_final <= 1e-10
+    assert e <= 4 * 4.0 * max(eta, hist[-1], 1e-12)
