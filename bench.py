@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--serve-budget-frac", type=float, default=0.8)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-tune", action="store_true", help="batched: default tile shapes")
+    ap.add_argument("--tune", action="store_true",
+                    help="c3: pick the tile shapes with the autotuner before timing")
     ap.add_argument("--dense-n", type=int, default=16384)
     ap.add_argument("--c2-threads", type=int, default=1,
                     help="c2: host threads of the oracle's second leg (1: one leg only)")
@@ -615,6 +617,12 @@ def main():
     launches = int(h.batches().sum())
     log(f"plan+assemble n={n}: {setup_s:.1f} s, ops {st['ops_factor']}, waves {st['waves_factor']}, "
         f"launches {launches}, device bytes {st['bytes_total'] / 1e9:.2f} GB")
+    tuning = None
+    if args.tune:
+        # tile shapes of this workload picked by the autotuner (untimed)
+        from paper_1906_00874_amd import autotune
+        tuning = autotune.tune_handle(h, reps=2, log=log)
+        log("autotuned", json.dumps({k: tuning[k] for k in ("trunc_width", "workers")}))
 
     b = rhs_normal(2, n, nrhs)
     bc = torch.tensor(np.ascontiguousarray(b.T), device=dev)
@@ -741,6 +749,9 @@ def main():
         t = time.perf_counter()
         h64 = P.HLU(xyz, area, precision=P.PREC_FP64, **common)
         h64.set_executor(1)
+        if tuning is not None:
+            h64.set_tuning(tuning["trunc_width"])
+            h64.set_workers(tuning["workers"])
         log(f"fp64 plan+assemble {time.perf_counter() - t:.1f} s")
         fms, sms = [], []
         for i in range(1 + max(5, args.steps)):
@@ -854,6 +865,7 @@ def main():
         "schedule": {"ops": int(st["ops_factor"]), "waves": int(st["waves_factor"]),
                      "executor": "dataflow: one persistent launch per factorisation",
                      "wave_executor_launches": launches},
+        "tuning": tuning,
         "roofline": roof,
         "roofline_solve": roof_solve,
         "kernel_breakdown": breakdown,
