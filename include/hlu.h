@@ -155,6 +155,7 @@ typedef struct {
     int64_t ops_factor, waves_factor, ops_solve, waves_solve;
     double flops_factor_model;   /* model flops at capacity ranks (upper bound) */
     int64_t bytes_factor_region, bytes_matvec_region, bytes_scratch, bytes_total;
+    int64_t offset_scratch;      /* byte offset of the scratch region in the buffer */
 } hlu_plan_stats;
 
 /* Build the cluster tree and block tree for n points (xyz: n x 3 row-major,

@@ -49,7 +49,8 @@ class PlanStats(C.Structure):
                 ("waves_factor", C.c_int64), ("ops_solve", C.c_int64),
                 ("waves_solve", C.c_int64), ("flops_factor_model", C.c_double),
                 ("bytes_factor_region", C.c_int64), ("bytes_matvec_region", C.c_int64),
-                ("bytes_scratch", C.c_int64), ("bytes_total", C.c_int64)]
+                ("bytes_scratch", C.c_int64), ("bytes_total", C.c_int64),
+                ("offset_scratch", C.c_int64)]
 
 
 OP_TYPES = 12   # HLU_OP_TYPES of the C header

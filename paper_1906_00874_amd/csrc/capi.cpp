@@ -549,6 +549,7 @@ hlu_status hlu_get_stats(hlu_handle h, hlu_plan_stats* o) {
   o->bytes_matvec_region = (int64_t)p.size_mv;
   o->bytes_scratch = (int64_t)p.size_scratch;
   o->bytes_total = (int64_t)p.total;
+  o->offset_scratch = (int64_t)p.off_scratch;
   return HLU_OK;
 }
 

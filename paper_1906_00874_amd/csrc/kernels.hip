@@ -147,7 +147,8 @@ __device__ __forceinline__ void stage_32x64(double (*dst)[65], const GView& g, F
 // all loads first, then all stores (a store could alias a later load
 // otherwise, and every element would cost a round trip)
 __device__ __forceinline__ void tile_update(const PRef& Y, int r0, int c0, int h, int w, int ti,
-                                            int tj, double s, const double (&acc)[4][4]) {
+                                            int tj, double s, const double (&acc)[4][4],
+                                            bool ow = false) {
   const GView g = gview(Y);
   int ri[16], cj[16];
   bool ok[16];
@@ -161,7 +162,12 @@ __device__ __forceinline__ void tile_update(const PRef& Y, int r0, int c0, int h
       ri[4 * u + q] = r0 + min(i, h - 1);
       cj[4 * u + q] = c0 + min(j, w - 1);
     }
-  gload(g, ri, cj, v);
+  if (ow) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = 0.0;
+  } else {
+    gload(g, ri, cj, v);
+  }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -649,7 +655,7 @@ __device__ __forceinline__ void narrow_finish(const GView& gy, const double* red
 // partials meet in LDS.  The old values of the tile and the first chunk
 // are loaded together.
 __device__ __forceinline__ void pgemm_narrow_dense(const Op& op, const PRef& X, const PRef& Y,
-                                                   int m, int c, double sg) {
+                                                   int m, int c, double sg, bool ow) {
   double* const sm = reinterpret_cast<double*>(hlu_lds);
   double* const sx = sm + 64 * 65;
   double* const red = sx + 64 * 17;
@@ -659,7 +665,12 @@ __device__ __forceinline__ void pgemm_narrow_dense(const Op& op, const PRef& X, 
   for (int r0 = 0; r0 < m; r0 += 64) {
     const int h = min(64, m - r0);
     TileRegs<64, 16> yo;
-    yo.load(gy, r0, 0, h, c);
+    if (ow) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) yo.v[u] = 0.0;
+    } else {
+      yo.load(gy, r0, 0, h, c);
+    }
     double acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -707,7 +718,8 @@ __device__ __forceinline__ void pgemm_narrow_dense(const Op& op, const PRef& X, 
 // the first tile's A rows and old values loading with the first chunk and
 // every later tile's while the previous one is computed.
 __device__ __forceinline__ void pgemm_narrow_lr(const PRef& A, const PRef& B, const PRef& X,
-                                                const PRef& Y, int m, int c, int k, double sg) {
+                                                const PRef& Y, int m, int c, int k, double sg,
+                                                bool ow) {
   double* const sb = reinterpret_cast<double*>(hlu_lds);
   double* const sx = sb + 64 * 33;
   double* const st = sx + 64 * 17;
@@ -719,7 +731,12 @@ __device__ __forceinline__ void pgemm_narrow_lr(const PRef& A, const PRef& B, co
   TileRegs<64, 32> at;
   TileRegs<64, 16> yo;
   at.load(ga, 0, 0, min(64, m), k);
-  yo.load(gy, 0, 0, min(64, m), c);
+  if (ow) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yo.v[u] = 0.0;
+  } else {
+    yo.load(gy, 0, 0, min(64, m), c);
+  }
   {
     const int q = tid >> 5, ta = tid & 7, tb = (tid >> 3) & 3;
     double acc[4][4];
@@ -781,7 +798,7 @@ __device__ __forceinline__ void pgemm_narrow_lr(const PRef& A, const PRef& B, co
     for (int u = 0; u < 4; ++u) old[u] = yo.v[u];
     if (r0 + 64 < m) {
       at.load(ga, r0 + 64, 0, min(64, m - r0 - 64), k);
-      yo.load(gy, r0 + 64, 0, min(64, m - r0 - 64), c);
+      if (!ow) yo.load(gy, r0 + 64, 0, min(64, m - r0 - 64), c);
     }
     double o[4][4];
 #pragma unroll
@@ -824,7 +841,7 @@ __device__ __forceinline__ void pgemm_narrow_lr(const PRef& A, const PRef& B, co
 #define PGF_LR_FLT (64 * 33 + 64 * 17 + 4 * 16 * 33 + 16 * 33)
 __device__ __forceinline__ void pgemm_lr_f32(const PRef& A, const PRef& B, const PRef& X,
                                              const PRef& Y, int m, int c0, int c, int k,
-                                             float sg) {
+                                             float sg, bool ow) {
   float* const sb = reinterpret_cast<float*>(hlu_lds);   // [64][33]: B chunk
   float* const sx = sb + 64 * 33;                        // [64][17]: X chunk
   float* const red = sx + 64 * 17;                       // [4][16][33]: partials
@@ -907,7 +924,12 @@ __device__ __forceinline__ void pgemm_lr_f32(const PRef& A, const PRef& B, const
       ok[q] = row < m && 4 * hi + q < c;
     }
     gloadf(ga, ri, cj, av);
-    gloadf(gy, yr, yc, yv);
+    if (ow) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yv[q] = 0.f;
+    } else {
+      gloadf(gy, yr, yc, yv);
+    }
     v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < 8; ++q)
@@ -928,7 +950,7 @@ __device__ __forceinline__ void pgemm_lr_f32(const PRef& A, const PRef& B, const
 // rows straight from memory in the operand layout (Y^T = X^T M^T).
 #define PGF_DENSE_FLT (64 * 17)
 __device__ __forceinline__ void pgemm_dense_f32(const Op& op, const PRef& X, const PRef& Y,
-                                                int m, int c0, int c, float sg) {
+                                                int m, int c0, int c, float sg, bool ow) {
   float* const sx = reinterpret_cast<float*>(hlu_lds);   // [64][17]
   const GView gm = gview(op.p[0], op.i1 != 0), gx = gview(X), gy = gview(Y);
   const int r = X.rows;
@@ -945,7 +967,12 @@ __device__ __forceinline__ void pgemm_dense_f32(const Op& op, const PRef& X, con
       yc[q] = c0 + min(4 * hi + q, c - 1);
       ok[q] = row < m && 4 * hi + q < c;
     }
-    gloadf(gy, yr, yc, yv);
+    if (ow) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yv[q] = 0.f;
+    } else {
+      gloadf(gy, yr, yc, yv);
+    }
     for (int k0 = 0; k0 < r; k0 += 64) {
       const int d = min(64, r - k0);
       float px[4], mv[16];
@@ -993,7 +1020,32 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
   const int c = min(cy, cx);
   const int m = Y.rows;
   const double esx = X.dt == DT_F64 ? 8.0 : 4.0;
-  const double esy = Y.dt == DT_F64 ? 8.0 : 4.0;
+  // i2 bit 0: the first product into a fresh panel overwrites it (Y := ...)
+  // instead of accumulating; its old values are then neither read nor counted
+  const bool ow = (op.i2 & 1) != 0;
+  const double esy = (Y.dt == DT_F64 ? 8.0 : 4.0) * (ow ? 0.5 : 1.0);
+  if (ow && op.i0 == 1 && kl == 0) {
+    // a rank-0 operand: the product is zero, and the fresh panel must still
+    // be written (later products accumulate into it)
+    const GView gy = gview(Y);
+    const int tot = m * cy;
+    for (int e0 = 0; e0 < tot; e0 += NT * 4) {
+      int ri[4], cj[4];
+      bool ok[4];
+      double z[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + threadIdx.x + NT * u, tot - 1);
+        ri[u] = e % m;
+        cj[u] = e / m;
+        ok[u] = e0 + (int)threadIdx.x + NT * u < tot;
+        z[u] = 0.0;
+      }
+      gstore(gy, ri, cj, ok, z);
+    }
+    put_cost(op, 0.0, esy * m * cy);
+    return;
+  }
   if (Y.dt == DT_F32 && (op.i0 == 0 || kl <= 32)) {
     // FP32 output panel (mixed precision): FP32 arithmetic on the matrix
     // cores, 16 columns at a time
@@ -1003,10 +1055,10 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
       for (int c0 = 0; c0 < c; c0 += 16) {
         const int cw = min(16, c - c0);
         if (op.i0 == 0)
-          pgemm_dense_f32(op, X, Y, m, c0, cw, (float)sg);
+          pgemm_dense_f32(op, X, Y, m, c0, cw, (float)sg, ow);
         else
           pgemm_lr_f32(tr ? op.p[1] : op.p[0], tr ? op.p[0] : op.p[1], X, Y, m, c0, cw, kl,
-                       (float)sg);
+                       (float)sg, ow);
         __syncthreads();
       }
     }
@@ -1022,12 +1074,12 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
   if (c <= 16 && (op.i0 == 0 || kl <= 32)) {
     const int r = X.rows;
     if (op.i0 == 0) {
-      if (c > 0 && m > 0) pgemm_narrow_dense(op, X, Y, m, c, sg);
+      if (c > 0 && m > 0) pgemm_narrow_dense(op, X, Y, m, c, sg, ow);
       put_cost(op, 2.0 * m * r * c, 8.0 * m * r + esx * r * c + 2.0 * esy * m * c);
     } else {
       const bool tr = op.i1 != 0;
       if (c > 0 && m > 0 && kl > 0)
-        pgemm_narrow_lr(tr ? op.p[1] : op.p[0], tr ? op.p[0] : op.p[1], X, Y, m, c, kl, sg);
+        pgemm_narrow_lr(tr ? op.p[1] : op.p[0], tr ? op.p[0] : op.p[1], X, Y, m, c, kl, sg, ow);
       const double esm = op.p[0].dt == DT_F64 ? 8.0 : 4.0;
       put_cost(op, 2.0 * (double)kl * c * (r + m),
                esm * (double)kl * (r + m) + esx * r * c + 2.0 * esy * m * c);
@@ -1076,7 +1128,7 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
           }
           __syncthreads();
         }
-        tile_update(Y, r0, c0, h, w, ti, tj, sg, acc);
+        tile_update(Y, r0, c0, h, w, ti, tj, sg, acc, ow);
       }
     }
     put_cost(op, 2.0 * m * r * c, 8.0 * m * r + esx * r * c + 2.0 * esy * m * c);
@@ -1174,7 +1226,7 @@ __device__ __forceinline__ void pgemm_body(const Op& op) {
         }
         __syncthreads();
       }
-      tile_update(Y, r0, c0, h, w, ti, tj, sg, o);
+      tile_update(Y, r0, c0, h, w, ti, tj, sg, o, ow);
     }
     __syncthreads();
   }
@@ -3731,10 +3783,14 @@ __global__ void __launch_bounds__(NT) k_direct_mv(const double* __restrict__ pts
     if (absmode) {
       Y[i] = acc[0];
     } else {
-      for (int r = 0; r < nrhs; ++r) {
-        const double bv = beta != 0.0 ? beta * B[i + (size_t)r * ldx] : 0.0;
-        Y[i + (size_t)r * ldx] = bv + alpha * acc[r];
-      }
+      // unrolled with a guard (a loop to nrhs would index acc dynamically
+      // and move it to scratch memory)
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+        if (r < nrhs) {
+          const double bv = beta != 0.0 ? beta * B[i + (size_t)r * ldx] : 0.0;
+          Y[i + (size_t)r * ldx] = bv + alpha * acc[r];
+        }
     }
   }
 }

@@ -35,7 +35,8 @@ enum OpType : int32_t {
   OP_TRSM_UT = 2,  // p0: factored leaf; p1 := U^{-T} p1
   OP_TRSM_U = 3,   // p0: factored leaf; p1 := U^{-1} p1
   OP_PGEMM = 4,    // p3 += d0 * op(M) p2; i0 = 0: M dense p0;
-                   // i0 = 1: M = p0 p1^T (low-rank); i1: transpose M
+                   // i0 = 1: M = p0 p1^T (low-rank); i1: transpose M;
+                   // i2 bit 0: p3 := d0 * op(M) p2 (first write of a fresh panel)
   OP_TRUNC = 5,    // C = p0 p1^T (rank at p0.rankp, capacity i2 & 0xffff,
                    // fixed rank i2 >> 16); C := best approx of C - sum X Y^T
                    // over the terms [i0, i0 + i1) of the term table at

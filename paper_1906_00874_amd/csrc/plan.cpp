@@ -784,13 +784,36 @@ class Builder {
     v.rank = rank;
     v.cl = cl;
     v.dt = dt;
-    // zero it (static capacity columns)
-    Op z = blank(OP_ZERO);
-    PV zz = v;
-    zz.rank = 0;
-    z.p[0] = ref(zz);
-    emit(z, {acc_of(v, true)});
+    if (ring_cap > 0) {
+      // zero it (static capacity columns); in a ring the zeroing op also
+      // orders the new tenant after every op that touched the extent
+      Op z = blank(OP_ZERO);
+      PV zz = v;
+      zz.rank = 0;
+      z.p[0] = ref(zz);
+      emit(z, {acc_of(v, true)});
+    } else {
+      // fresh memory: the first product into each row range overwrites it
+      // (every scratch panel is filled by one panel product over its row
+      // cluster right after its allocation; consumers read live columns only)
+      if ((int)fresh_rows.size() <= v.obj) fresh_rows.resize(v.obj + 1);
+      fresh_rows[v.obj].clear();
+      fresh_rows[v.obj].push_back(-1);   // marker: tracked, nothing written yet
+    }
     return v;
+  }
+  // per fresh scratch object: [lo, hi) row ranges written so far (first
+  // entry -1 marks a tracked object)
+  std::vector<std::vector<int64_t>> fresh_rows;
+  // true iff rows [lo, hi) of object obj are tracked and untouched; marks them
+  bool first_write(int obj, int64_t lo, int64_t hi) {
+    if (obj < 0 || obj >= (int)fresh_rows.size() || fresh_rows[obj].empty()) return false;
+    std::vector<int64_t>& w = fresh_rows[obj];
+    for (size_t q = 1; q + 1 < w.size(); q += 2)
+      if (lo < w[q + 1] && w[q] < hi) return false;
+    w.push_back(lo);
+    w.push_back(hi);
+    return true;
   }
 
   const BNode& node(int b) const { return P.bn[b]; }
@@ -872,6 +895,13 @@ class Builder {
     Op op = blank(OP_PGEMM);
     op.d0 = sign;
     op.i1 = tr ? 1 : 0;
+    {
+      // rows of Y this product writes (Y is restricted to this block's
+      // row cluster, or its column cluster when transposed)
+      const Cluster& rc = P.cl[Y.cl];
+      const int64_t lo = (int64_t)rc.off, hi = lo + rc.size;
+      if (first_write(Y.obj, lo, hi)) op.i2 = 1;
+    }
     op.p[2] = ref(X);
     op.p[3] = ref(Y);
     std::vector<Acc> acc = {acc_of(X, false), acc_of(Y, true), racc(X), racc(Y)};

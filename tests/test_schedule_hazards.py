@@ -161,3 +161,35 @@ def test_scratch_ring_shrinks_scratch():
     full = P.HLU(xyz, area, scratch_cap=0, **kw).stats()["bytes_scratch"]
     ring = P.HLU(xyz, area, scratch_cap=32768, **kw).stats()["bytes_scratch"]
     assert ring <= 32768 < full
+
+
+@pytest.mark.parametrize("operation", [0, 2])
+def test_scratch_is_written_before_it_is_read(operation):
+    """Without a ring the scratch panels are not zero-filled: the first panel
+    product into each row range overwrites it.  Every scratch byte an op
+    reads (at full static capacity) was written by an earlier op of the
+    schedule, and there is no zeroing op at all; the H-LU plan and the
+    inverse plan (identity and zero blocks) are both checked."""
+    xyz, area = icosphere(2)
+    h = P.HLU(xyz, area, assemble=False, leaf=16, eta=2.0, eps=1e-6, cap=16,
+              precision=P.PREC_MIXED, max_nrhs=2, cap_mv=0, refine_tol=0.0, operation=operation)
+    st = h.stats()
+    lo_s, hi_s = st["offset_scratch"], st["offset_scratch"] + st["bytes_scratch"]
+    ops, waves, terms = h.schedule_ops(0)
+    assert not np.any(ops["type"] == OP_ZERO)
+    assert np.any((ops["type"] == OP_PGEMM) & ((ops["i2"] & 1) == 1))
+    acc = [accesses(ops[k], terms) for k in range(len(ops))]
+    bounds = np.unique(np.array([x for a in acc for (lo, hi, _) in a for x in (lo, hi)]
+                                + [lo_s, hi_s], dtype=np.int64))
+    written = np.zeros(len(bounds), dtype=bool)
+    unread = 0
+    for k in range(len(ops)):
+        for lo, hi, w in acc[k]:
+            if w or hi <= lo_s or lo >= hi_s:
+                continue
+            a, b = np.searchsorted(bounds, lo), np.searchsorted(bounds, hi)
+            unread += int((~written[a:b]).sum())
+        for lo, hi, w in acc[k]:
+            if w:
+                written[np.searchsorted(bounds, lo):np.searchsorted(bounds, hi)] = True
+    assert unread == 0
