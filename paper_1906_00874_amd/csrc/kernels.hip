@@ -2182,7 +2182,11 @@ __device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
   const int kwide = (tune & 0xff) > 0 && (tune & 0xff) < KM ? (tune & 0xff) : KM;
   if (tid == 0) sh.te = 0;
   __syncthreads();
-  while (sh.te < nterms) {
+  for (;;) {
+    // every thread reads the term cursor before thread 0 advances it
+    const int te0 = sh.te;
+    __syncthreads();
+    if (te0 >= nterms) break;
     // choose this pass's terms and map the stacked columns
     if (tid == 0) {
       const int kc = pcols(U);
