@@ -1978,6 +1978,91 @@ __device__ __forceinline__ void trunc_apply2(TruncShared& sh, const PRef& U, con
 // disjoint LDS bank windows.
 __device__ __forceinline__ int jphys(int p) { return ((p & 7) << 3) | (p >> 3); }
 
+// One-sided Jacobi on at most 16 columns held in the registers of
+// wavefront 0: lane l keeps column l & 15 at rows 4t + (l >> 4), t < T
+// (rx <= 4T).  The columns stay in their lanes; round r of a sweep pairs
+// them by the round-robin tournament on ncol (even) columns: column ncol-1
+// meets column r and every other column c meets (2r - c) mod (ncol - 1).
+// The partner's rows arrive by lane permutes, the inner product and the
+// squared norms are reduced over the four row blocks by lane exchanges, and
+// both lanes of a pair form the same rotation from the same values, so no
+// round touches LDS.  Squared norms are recomputed at every sweep and
+// carried through the rotations in between; sweeps stop once no pair had a
+// squared cosine above stop.  The result goes back to m (columns by
+// position, as the LDS version leaves them).
+template <int T>
+__device__ __forceinline__ void trunc_jacobi_reg(TruncShared& sh, int rx, int ncol, double ms,
+                                                 double stop, int& sweeps_out) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int c = tid & 15, rb = tid >> 4;
+    const bool col_in = c < ncol;
+    double a[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int i = 4 * t + rb;
+      a[t] = (col_in && i < rx) ? sh.m[i][jphys(c)] : 0.0;
+    }
+    const double tiny = 1e-30 * ms;
+    const int nm1 = ncol - 1;
+    int sweeps = 0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double al = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) al += a[t] * a[t];
+      al += __shfl_xor(al, 16);
+      al += __shfl_xor(al, 32);
+      double mu = 0.0;
+      for (int r = 0; r < nm1; ++r) {
+        int pc = c == nm1 ? r : (c == r ? nm1 : (2 * r - c + nm1) % nm1);
+        if (!col_in) pc = c;
+        const int src = (tid & 48) | pc;
+        double b[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) b[t] = __shfl(a[t], src);
+        const double be_ = __shfl(al, src);
+        double ga = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) ga += a[t] * b[t];
+        ga += __shfl_xor(ga, 16);
+        ga += __shfl_xor(ga, 32);
+        // the pair (p, q), p < q, seen the same way from both of its lanes
+        const bool first = c < pc;
+        const double ap = first ? al : be_, aq = first ? be_ : al;
+        double cs = 1.0, sn = 0.0, ap2 = ap, aq2 = aq;
+        if (col_in && pc != c && ap > tiny && aq > tiny && ga * ga > 1e-30 * ap * aq) {
+          mu = fmax(mu, ga * ga / (ap * aq));
+          const double d = aq - ap, g2 = 2.0 * ga;
+          const double rr = sqrt(d * d + g2 * g2), ad = fabs(d);
+          const double y = 2.0 * rr * (rr + ad);
+          double qy = __builtin_amdgcn_rsq(y);
+          qy = qy * (1.5 - 0.5 * y * qy * qy);
+          sn = (d >= 0.0 ? g2 : -g2) * qy;
+          cs = (rr + ad) * qy;
+          const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * ga;
+          ap2 = c2 * ap - cg + s2 * aq;
+          aq2 = s2 * ap + cg + c2 * aq;
+        }
+        // p' = cs p - sn q, q' = sn p + cs q
+#pragma unroll
+        for (int t = 0; t < T; ++t) a[t] = first ? cs * a[t] - sn * b[t] : sn * b[t] + cs * a[t];
+        al = first ? ap2 : aq2;
+      }
+      ++sweeps;
+      for (int o = 32; o > 0; o >>= 1) mu = fmax(mu, __shfl_xor(mu, o));
+      if (!(mu > stop)) break;
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int i = 4 * t + rb;
+      if (col_in && i < rx) sh.m[i][jphys(c)] = a[t];
+    }
+    if (tid == 0) sh.jsweeps = sweeps;
+  }
+  __syncthreads();
+  sweeps_out = sh.jsweeps;
+}
+
 // One-sided Jacobi on the columns of M (rx rows, ry columns, initially
 // position j = column j of m).  Round-robin ordering by the circle method:
 // position 0 stays, positions 1..n-1 advance by one each round, position p
@@ -1987,7 +2072,8 @@ __device__ __forceinline__ int jphys(int p) { return ((p & 7) << 3) | (p >> 3); 
 // registers.  Squared column norms (by position) are recomputed at every
 // sweep and carried through the rotations in between, so a round reduces
 // one inner product.  Sweeps stop once no pair had a squared cosine above
-// stop.  Returns the buffer holding the result (0: m, 1: gy).
+// stop.  At most 16 columns go to the register version above instead.
+// Returns the buffer holding the result (0: m, 1: gy).
 __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, double ms,
                                             double stop, int& sweeps) {
   const int tid = threadIdx.x;
@@ -1996,92 +2082,10 @@ __device__ __forceinline__ int trunc_jacobi(TruncShared& sh, int rx, int ry, dou
   if (ncol < 2 || rx <= 0 || !(ms > 0.0)) return 0;
   const int npair = ncol / 2, nm1 = ncol - 1;
   if (npair <= 8) {
-    // at most 16 columns: every pair on eight lanes of wavefront 0, whose
-    // rounds need no block barrier (the wavefront's LDS accesses complete in
-    // order; the fences keep the compiler from moving them across rounds)
-    if (tid < 64) {
-      const int q = tid >> 3, l = tid & 7;
-      const bool act = q < npair;
-      const int p0 = q, p1 = nm1 - q;
-      const int n0 = q == 0 ? 0 : q + 1, n1 = q == 0 ? 1 : ncol - q;
-      const int f0 = jphys(p0), f1 = jphys(p1), g0 = jphys(n0), g1 = jphys(n1);
-      const double tiny = 1e-30 * ms;
-      int cur = 0;
-      for (int sweep = 0; sweep < 30; ++sweep) {
-        {
-          double (*A)[KM + 1] = cur ? sh.gy : sh.m;
-          const int j = tid >> 2, part = tid & 3;
-          double s2 = 0.0;
-          if (j < ncol) {
-            const int fj = jphys(j);
-            for (int i = part; i < rx; i += 4) s2 += A[i][fj] * A[i][fj];
-          }
-          s2 += dpp_d<0xB1>(s2);
-          s2 += dpp_d<0x4E>(s2);
-          if (part == 0 && j < ncol) sh.nrm[cur][j] = s2;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        double mu = 0.0;
-        for (int round = 0; round < nm1; ++round) {
-          double (*S)[KM + 1] = cur ? sh.gy : sh.m;
-          double (*D)[KM + 1] = cur ? sh.m : sh.gy;
-          double ma[8], mb[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int i = l + 8 * t;
-            ma[t] = (act && i < rx) ? S[i][f0] : 0.0;
-            mb[t] = (act && i < rx) ? S[i][f1] : 0.0;
-          }
-          const double al = act ? sh.nrm[cur][p0] : 0.0, be = act ? sh.nrm[cur][p1] : 0.0;
-          double ga = 0.0;
-#pragma unroll
-          for (int t = 0; t < 8; ++t) ga += ma[t] * mb[t];
-          ga = group_sum(ga, 8);
-          double cs = 1.0, sn = 0.0, al2 = al, be2 = be;
-          if (act && al > tiny && be > tiny && ga * ga > 1e-30 * al * be) {
-            mu = fmax(mu, ga * ga / (al * be));
-            const double d = be - al, g2 = 2.0 * ga;
-            const double rr = sqrt(d * d + g2 * g2), ad = fabs(d);
-            const double y = 2.0 * rr * (rr + ad);
-            double qy = __builtin_amdgcn_rsq(y);
-            qy = qy * (1.5 - 0.5 * y * qy * qy);
-            sn = (d >= 0.0 ? g2 : -g2) * qy;
-            cs = (rr + ad) * qy;
-            const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * ga;
-            al2 = c2 * al - cg + s2 * be;
-            be2 = s2 * al + cg + c2 * be;
-          }
-          if (act) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int i = l + 8 * t;
-              if (i < rx) {
-                D[i][g0] = cs * ma[t] - sn * mb[t];
-                D[i][g1] = sn * ma[t] + cs * mb[t];
-              }
-            }
-            if (l == 0) {
-              sh.nrm[cur ^ 1][n0] = al2;
-              sh.nrm[cur ^ 1][n1] = be2;
-            }
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          cur ^= 1;
-        }
-        ++sweeps;
-        for (int o = 32; o > 0; o >>= 1) mu = fmax(mu, __shfl_xor(mu, o));
-        if (!(mu > stop)) break;
-      }
-      if (tid == 0) {
-        sh.jcur = cur;
-        sh.jsweeps = sweeps;
-      }
-    }
-    __syncthreads();
-    sweeps = sh.jsweeps;
-    return sh.jcur;
+    if (rx <= 16) trunc_jacobi_reg<4>(sh, rx, ncol, ms, stop, sweeps);
+    else if (rx <= 32) trunc_jacobi_reg<8>(sh, rx, ncol, ms, stop, sweeps);
+    else trunc_jacobi_reg<16>(sh, rx, ncol, ms, stop, sweeps);
+    return 0;
   }
   int grp = 64;
   while (grp > 8 && grp * npair > NT) grp >>= 1;
