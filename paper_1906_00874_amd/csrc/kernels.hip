@@ -1793,6 +1793,27 @@ __device__ __forceinline__ void trunc_gram2(TruncShared& sh, int m, int n, int K
 // step s), piv[0..r) are the pivots in order, piv[r..K) the remaining
 // columns, and r is the numerical rank.  lv (64 doubles, 16-byte aligned)
 // carries each step's row of R to every lane.
+// Pivot of the next step from the trailing diagonal d (wave-uniform p and
+// v = d[p]); false once the pivoted Cholesky stops: no candidate left, a
+// pivot below 1e-14 of the largest initial diagonal, or (TRACE_STOP) a
+// residual diagonal summing to at most trace_stop.
+template <bool TRACE_STOP>
+__device__ __forceinline__ bool pchol_pick(double d, bool alive, double dmax0, double inv_dmax0,
+                                           double trace_stop, int& p, double& v) {
+  // straight-line (no early exit), so that the caller's LDS reads issued
+  // before it stay in flight across it
+  bool ok = dmax0 > 0.0;
+  if constexpr (TRACE_STOP) {
+    // the squared distances of the remaining rows from the span of the
+    // chosen ones
+    const double trace = wave_sum(alive ? fmax(d, 0.0) : 0.0);
+    ok = ok && trace > trace_stop;
+  }
+  p = wave_argmax_key(d, alive, inv_dmax0);
+  v = readlane_d(d, p < 0 ? 0 : p);
+  return ok && p >= 0 && v > 1e-14 * dmax0;
+}
+
 template <bool TRACE_STOP = false>
 __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv, int* piv, int K,
                                                  int* r_out, double trace_stop = 0.0,
@@ -1808,55 +1829,51 @@ __device__ __forceinline__ void trunc_pchol_wave(double (*G)[KM + 1], double* lv
   wave_argmax(dmax0, dummy);
   const double inv_dmax0 = dmax0 > 0.0 ? 1.0 / dmax0 : 0.0;
   bool alive = in;
-  int r = 0;
-  double trace = 0.0;
-  for (int s = 0; s < K; ++s) {
-    if constexpr (TRACE_STOP) {
-      // stop once the residual diagonal (the squared distances of the
-      // remaining rows from the span of the chosen ones) sums to at most
-      // trace_stop
-      trace = wave_sum(alive ? fmax(d, 0.0) : 0.0);
-      if (!(trace > trace_stop)) break;
-    }
-    const int p = wave_argmax_key(d, alive, inv_dmax0);
-    if (p < 0) break;
-    const double v = readlane_d(d, p);
-    if (!(v > 1e-14 * dmax0) || !(dmax0 > 0.0)) break;
+  int r = 0, p = 0;
+  double v = 0.0;
+  bool go = pchol_pick<TRACE_STOP>(d, alive, dmax0, inv_dmax0, trace_stop, p, v);
+  while (go) {
     // 1 / sqrt(v) by the hardware estimate and one Newton step, sqrt(v) from it
     double inv = __builtin_amdgcn_rsq(v);
     inv = inv * (1.5 - 0.5 * v * inv * inv);
     const double rp = v * inv;
     const double l = alive ? (lane == p ? rp : pick64(g, p) * inv) : 0.0;
-    if (in) G[s][lane] = l;
+    if (in) G[r][lane] = l;
     lv[lane] = l;
-    if (lane == 0) piv[s] = p;
+    if (lane == 0) piv[r] = p;
     if (lane == p) alive = false;
+    d -= l * l;
+    ++r;
     // rank-one update of the trailing columns (same wavefront: the loads
     // below see the stores above).  Straight-line over all 64 entries: lanes
     // at or beyond K hold l = 0, so their entries stay zero, and without a
-    // branch per entry the reads are issued together.
-    // (two halves of 32 rows: all reads of a half are issued together, and
-    // the batch stays within the register budget of the inlined executor)
+    // branch per entry the reads are issued together.  Two halves of 32
+    // rows keep the batch within the register budget of the inlined
+    // executor; the next pivot, which needs only the diagonal, is chosen
+    // while the first half's reads are in flight.
     const double2* l2 = reinterpret_cast<const double2*>(lv);
+    double2 lr[KM / 4];
 #pragma unroll
-    for (int h = 0; h < KM; h += KM / 2) {
-      double2 lr[KM / 4];
+    for (int i = 0; i < KM / 2; i += 2) lr[i >> 1] = l2[i >> 1];
+    go = pchol_pick<TRACE_STOP>(d, alive, dmax0, inv_dmax0, trace_stop, p, v);
 #pragma unroll
-      for (int i = 0; i < KM / 2; i += 2) lr[i >> 1] = l2[(h + i) >> 1];
-#pragma unroll
-      for (int i = 0; i < KM / 2; i += 2) {
-        g[h + i] -= lr[i >> 1].x * l;
-        g[h + i + 1] -= lr[i >> 1].y * l;
-      }
+    for (int i = 0; i < KM / 2; i += 2) {
+      g[i] -= lr[i >> 1].x * l;
+      g[i + 1] -= lr[i >> 1].y * l;
     }
-    d -= l * l;
-    ++r;
+#pragma unroll
+    for (int i = 0; i < KM / 2; i += 2) lr[i >> 1] = l2[(KM / 2 + i) >> 1];
+#pragma unroll
+    for (int i = 0; i < KM / 2; i += 2) {
+      g[KM / 2 + i] -= lr[i >> 1].x * l;
+      g[KM / 2 + i + 1] -= lr[i >> 1].y * l;
+    }
   }
   const unsigned long long mask = __ballot(alive);
   if (alive) piv[r + __popcll(mask & ((1ull << lane) - 1ull))] = lane;
   if (lane == 0) *r_out = r;
   if constexpr (TRACE_STOP) {
-    trace = wave_sum(alive ? fmax(d, 0.0) : 0.0);
+    const double trace = wave_sum(alive ? fmax(d, 0.0) : 0.0);
     if (lane == 0) *trace_out = trace;
   }
 }
