@@ -1495,6 +1495,7 @@ struct TruncShared {
   Term tm[TMAX];
   int px[KM], py[KM], ord[KM];
   int8_t colt[KM], colj[KM];
+  int tw[TMAX];             // live widths of the candidate terms of a pass
   int rx, ry, k, capped, K, kc, te, jcur, jsweeps;
   double mnorm;
 };
@@ -2208,26 +2209,44 @@ __device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
     const int te0 = sh.te;
     __syncthreads();
     if (te0 >= nterms) break;
-    // choose this pass's terms and map the stacked columns
-    if (tid == 0) {
-      const int kc = pcols(U);
-      int K = kc, t = sh.te;
-      const int tb = t;
-      while (t < nterms && t - tb < TMAX) {
-        const int w = pcols(terms[t].X);
-        if (t > tb && K + w > kwide) break;
-        for (int j = 0; j < w; ++j) {
-          sh.colt[K + j] = (int8_t)(t - tb);
-          sh.colj[K + j] = (int8_t)j;
-        }
-        sh.tm[t - tb] = terms[t];
-        K += w;
-        ++t;
+    // choose this pass's terms and map the stacked columns: the candidate
+    // terms and their live widths are read by one thread each, then
+    // thread 0 takes terms while the stack fits (the first always)
+    {
+      const int cand = min(TMAX, nterms - te0);
+      if (tid < cand) {
+        const Term tt = terms[te0 + tid];
+        sh.tm[tid] = tt;
+        sh.tw[tid] = pcols(tt.X);
+      } else if (tid == 64) {
+        sh.kc = pcols(U);
       }
-      sh.kc = kc;
-      sh.K = K;
-      sh.te = t;
-      sh.capped = 0;
+      __syncthreads();
+      if (tid == 0) {
+        int K = sh.kc, t = 0;
+        while (t < cand) {
+          const int w = sh.tw[t];
+          if (t > 0 && K + w > kwide) break;
+          K += w;
+          ++t;
+        }
+        sh.K = K;
+        sh.te = te0 + t;
+        sh.capped = 0;
+      }
+      __syncthreads();
+      // stacked column j of the terms: term t, column j - (kc + widths before t)
+      for (int j = tid; j < KM; j += NT) {
+        int c = j - sh.kc, t = 0;
+        if (c >= 0 && j < sh.K) {
+          while (c >= sh.tw[t]) {
+            c -= sh.tw[t];
+            ++t;
+          }
+          sh.colt[j] = (int8_t)t;
+          sh.colj[j] = (int8_t)c;
+        }
+      }
     }
     __syncthreads();
     const int K = __builtin_amdgcn_readfirstlane(sh.K);
