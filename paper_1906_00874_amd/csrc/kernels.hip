@@ -3211,6 +3211,7 @@ __global__ void k_df_reset(const DfPart* parts, int np, int* queue, const int* r
     ctrl[2] = 0;        // error flag
     ctrl[3] = 0;        // high ring: next ticket
     ctrl[4] = 0;        // high ring: next free slot
+    ctrl[6] = 0;        // ops finished
   }
 }
 
@@ -3268,12 +3269,17 @@ __device__ __forceinline__ bool run_op_masked(const Op& op, int tune) {
 // flagged as near-critical (bit 30 of their initial in-degree).  Workgroups
 // 0 .. nhw - 1 serve the high ring, the others the low ring, each with the
 // same protocol: take a ticket, wait for the op pushed into that slot.
-// The initially ready ops are never flagged, so exactly nhigh ops enter the
-// high ring.  With nhw == 0 the flags are ignored (one ring).
+// The initially ready ops are never flagged.  With nhw == 0 the flags are
+// ignored (one ring).  A workgroup whose decrements make successors ready
+// keeps the first of them (lowest position in its successor list, among the
+// first NT) and runs it next without going through a ring; the others are
+// pushed.  Kept ops leave slots of the rings unfilled, so a waiting
+// workgroup also leaves once all n ops have finished (a counter).
 template <unsigned MASK>
 __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np, int* queue,
                                        int* ctrl, int n, int nhigh, int nhw, long long timeout) {
   __shared__ int s_op;
+  __shared__ int s_keep;
   const int tid = threadIdx.x;
   if (nhw <= 0) nhigh = 0;
   const int nlow = n - nhigh;
@@ -3281,28 +3287,41 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
   int* const head = hw ? &ctrl[3] : &ctrl[0];
   int* const ring = hw ? queue + nlow : queue;
   const int cnt = hw ? nhigh : nlow;
+  int* const finished = &ctrl[6];
+  int next = -1;            // successor kept by the last op (thread 0)
   for (;;) {
     if (tid == 0) {
-      int v = -1;
-      const int s = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (s < cnt) {
-        const long long t0 = (long long)wall_clock64();
-        // spin with relaxed loads: an acquire per iteration would invalidate
-        // this chiplet's L2 under the ops running beside it
-        for (;;) {
-          v = __hip_atomic_load(&ring[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (v >= 0) {
-            // pairs with the release store that pushed v: the op's inputs
-            // (every predecessor's writes) are visible from here on
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            break;
+      int v = next;
+      next = -1;
+      if (v >= 0) {
+        // made ready by this workgroup's own decrement, whose wavefront
+        // acquired; once more here for the wavefront that reads the inputs
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      } else {
+        const int s = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s < cnt) {
+          const long long t0 = (long long)wall_clock64();
+          // spin with relaxed loads: an acquire per iteration would
+          // invalidate this chiplet's L2 under the ops running beside it
+          for (int it = 1;; ++it) {
+            v = __hip_atomic_load(&ring[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v >= 0) {
+              // pairs with the release store that pushed v: the op's inputs
+              // (every predecessor's writes) are visible from here on
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+              break;
+            }
+            if ((it & 31) == 0) {
+              if (__hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n)
+                break;   // every op has run: this slot stays empty
+              if (__hip_atomic_load(&ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+              if ((long long)wall_clock64() - t0 > timeout) {
+                __hip_atomic_store(&ctrl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+              }
+            }
+            __builtin_amdgcn_s_sleep(2);
           }
-          if (__hip_atomic_load(&ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-          if ((long long)wall_clock64() - t0 > timeout) {
-            __hip_atomic_store(&ctrl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
         }
       }
       s_op = v;
@@ -3322,15 +3341,17 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     // the others' through the chain of read-modify-writes, so their fences
     // synchronise with it) and pushes the successor with a release store
     // into the ring its flag names; each wavefront reserves the slots of its
-    // pushes with one atomic per ring.
+    // pushes with one atomic per ring.  The lowest ready position among the
+    // first NT successors is not pushed: this workgroup runs it next.
     __syncthreads();
     if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (tid == 0) s_keep = 0x7fffffff;
     __syncthreads();
+    const HLU_G int* succ_off = gptr<const int>(pt.succ_off);
+    const HLU_G int* succ = gptr<const int>(pt.succ);
+    const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
     {
-      const HLU_G int* succ_off = gptr<const int>(pt.succ_off);
-      const HLU_G int* succ = gptr<const int>(pt.succ);
       HLU_G int* indeg = gptr<int>(pt.indeg);
-      const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
       const int lane = tid & 63;
       for (int eb = e0; eb < e1; eb += NT) {
         const int e = eb + tid;
@@ -3343,8 +3364,17 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
           ready = (old & 0x3fffffff) == 1;
           hi = nhigh > 0 && ((old >> 30) & 1);
         }
-        const unsigned long long mlo = __ballot(ready && !hi), mhi = __ballot(ready && hi);
-        if (mlo | mhi) {
+        const unsigned long long mr = __ballot(ready);
+        bool keep = false;
+        if (eb == e0) {
+          // the lowest ready position of the first chunk is kept
+          if (mr && lane == __ffsll((long long)mr) - 1) atomicMin(&s_keep, e - e0);
+          __syncthreads();
+          keep = ready && e - e0 == s_keep;
+        }
+        const unsigned long long mlo = __ballot(ready && !keep && !hi);
+        const unsigned long long mhi = __ballot(ready && !keep && hi);
+        if (mr) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
           for (int r = 0; r < 2; ++r) {
@@ -3369,6 +3399,11 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
       }
     }
     __syncthreads();
+    if (tid == 0) {
+      const int kp = s_keep;
+      if (kp != 0x7fffffff) next = pt.base + succ[e0 + kp];
+      __hip_atomic_fetch_add(finished, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
