@@ -233,15 +233,22 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
         const hlu::PRef& Y = o.p[3];
         if (!panel_ok(Y, T, why)) return bad(why.c_str());
         if (Y.rows > 64 || Y.cols > 64 || Y.dt != hlu::DT_F64 || Y.trans) return bad("row target");
-        if (o.i1 < 1 || o.i1 > 256 || o.i0 < 0 || (size_t)o.i0 + o.i1 > sc.terms.size())
-          return bad("row update term list");
-        if (o.p[2].ptr != p.off_terms_s) return bad("row update term table");
-        for (int t = o.i0; t < o.i0 + o.i1; ++t) {
-          const hlu::Term& tm = sc.terms[t];
-          if (!panel_ok(tm.X, T, why) || !panel_ok(tm.Y, T, why)) return bad(why.c_str());
-          if (tm.X.rows != Y.rows || tm.X.cols > 64 || tm.X.trans) return bad("row term factor");
-          if (tm.Y.dt != hlu::DT_F64 || tm.Y.trans || tm.Y.rows < tm.X.cols || tm.Y.cols < Y.cols)
+        auto term_ok = [&](const hlu::PRef& X, const hlu::PRef& Yt) {
+          if (!panel_ok(X, T, why) || !panel_ok(Yt, T, why)) return bad(why.c_str());
+          if (X.rows != Y.rows || X.cols > 64 || X.trans) return bad("row term factor");
+          if (Yt.dt != hlu::DT_F64 || Yt.trans || Yt.rows < X.cols || Yt.cols < Y.cols)
             return bad("row term operand");
+          return true;
+        };
+        if (o.i0 == -1) {   // one term inline: factor in p1, operand in p2
+          if (o.i1 != 1) return bad("inline row term count");
+          if (!term_ok(o.p[1], o.p[2])) return false;
+        } else {
+          if (o.i1 < 1 || o.i1 > 256 || o.i0 < 0 || (size_t)o.i0 + o.i1 > sc.terms.size())
+            return bad("row update term list");
+          if (o.p[2].ptr != p.off_terms_s) return bad("row update term table");
+          for (int t = o.i0; t < o.i0 + o.i1; ++t)
+            if (!term_ok(sc.terms[t].X, sc.terms[t].Y)) return false;
         }
         if (o.i2 != 0 && o.i2 != 1) return bad("row update flag");
         if (o.i2 == 1) {   // fused leaf inverse in p0

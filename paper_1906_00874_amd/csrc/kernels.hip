@@ -2613,7 +2613,17 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
       sw[i][j] = v[u];
     }
   }
-  {
+  if (op.i0 < 0) {
+    // one term carried in the op itself (p1 its factor, p2 its operand)
+    if (tid == 0) {
+      Term tm;
+      tm.X = op.p[1];
+      tm.Y = op.p[2];
+      tm.xo = tm.yo = 0;
+      tm.pad[0] = tm.pad[1] = 0;
+      st[0] = tm;
+    }
+  } else {
     const HLU_G uint64_t* src = gptr<const uint64_t>(op.p[2].ptr) + (size_t)op.i0 * 10;
     uint64_t* dst = reinterpret_cast<uint64_t*>(st);
     for (int e = tid; e < nt * 10; e += NT) dst[e] = src[e];

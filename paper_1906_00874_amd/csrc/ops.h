@@ -46,8 +46,9 @@ enum OpType : int32_t {
   OP_MVT = 8,      // solve: p3 (FP64, rows = live cols of p0) := p0^T p2
   OP_MVROW = 9,    // solve: p3 += d0 * sum over the terms [i0, i0 + i1) of the
                    // table at p2.ptr of X_t Y_t (X_t: rows of p3 x live cols,
-                   // Y_t: FP64 with at least that many rows); i2 = 1: then
-                   // p3 := p0 p3 with the leaf inverse p0 (rows x rows)
+                   // Y_t: FP64 with at least that many rows); i0 = -1: one
+                   // term carried in the op, X in p1 and Y in p2; i2 = 1:
+                   // then p3 := p0 p3 with the leaf inverse p0 (rows x rows)
   OP_TRINV = 10,   // factor: from the factored leaf p0 (b x b) and its pivots
                    // at p1.ptr, p2 := L^{-1} P and p3 := U^{-1} (FP64, b x b)
   OP_INVAPPLY = 11,  // solve: p1 := p0 p1 (p0: b x b FP64, p1: b x live cols)

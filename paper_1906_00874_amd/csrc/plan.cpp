@@ -1794,7 +1794,18 @@ bool build_plan(Plan& p, const double* xyz, const double* area, int64_t n64,
   p.off_terms_s = cur;
   cur = align256(cur + std::max<size_t>(1, p.ssched.terms.size()) * sizeof(Term));
   for (auto& op : p.ssched.ops)
-    if (op.type == OP_MVROW) op.p[2].ptr = p.off_terms_s;
+    if (op.type == OP_MVROW) {
+      if (op.i1 == 1) {
+        // one term: carried in the op (p1 its factor, p2 its operand, i0 = -1),
+        // so its loads need not wait for a term record
+        const Term& tm = p.ssched.terms[op.i0];
+        op.p[1] = tm.X;
+        op.p[2] = tm.Y;
+        op.i0 = -1;
+      } else {
+        op.p[2].ptr = p.off_terms_s;
+      }
+    }
   {
     const uint64_t N = p.fsched.ops.size();
     p.off_df_succ_off = cur;

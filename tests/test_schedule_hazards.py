@@ -73,9 +73,13 @@ def accesses(o, terms):
         _segs(p[3], True, a)
         if o["i2"] == 1:
             _segs(p[0], False, a)
-        for q in range(int(o["i0"]), int(o["i0"]) + int(o["i1"])):
-            _segs(terms[q]["X"], False, a)
-            _segs(terms[q]["Y"], False, a)
+        if int(o["i0"]) == -1:   # one term carried in the op
+            _segs(p[1], False, a)
+            _segs(p[2], False, a)
+        else:
+            for q in range(int(o["i0"]), int(o["i0"]) + int(o["i1"])):
+                _segs(terms[q]["X"], False, a)
+                _segs(terms[q]["Y"], False, a)
     elif t == OP_TRINV:
         _segs(p[0], False, a)
         a.append((int(p[1]["ptr"]), int(p[1]["ptr"]) + 4 * int(p[0]["rows"]), False))
