@@ -2646,7 +2646,8 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     while (t + 1 < nt && first[t + 1] <= item) ++t;
     c0 = (item - first[t]) * 16;
   };
-  double (*pb2)[33] = reinterpret_cast<double (*)[33]>(smem);   // 2 x 64 rows x 32
+  // the four wavefronts' partials side by side (staging area, free after the terms)
+  double (*part)[64][33] = reinterpret_cast<double (*)[64][33]>(smem);
   // right-hand sides in groups of 32 (one group when nrhs <= 32)
   // chunk `item` (16 columns of one term) of the A panel (lane = row) and of
   // the B panel (lane = right-hand side h0 + lane) into registers
@@ -2672,13 +2673,14 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   };
   for (int h0 = 0; h0 < nr; h0 += 32) {
     const int nh = min(32, nr - h0);
-    // the old values of the rows (wavefront 0), in flight while the terms
-    // are multiplied; lanes beyond the rows read a clamped element
-    double yv[32];
-    if (w == 0) {
+    // the old values of the rows, eight right-hand sides per wavefront (the
+    // ones it finishes below), in flight while the terms are multiplied;
+    // lanes beyond the rows or right-hand sides read a clamped element
+    double yv[8];
+    {
       const HLU_G double* y = gptr<const double>(Y.ptr) + min(lane, rows - 1) + (size_t)h0 * Y.ld;
 #pragma unroll
-      for (int v = 0; v < 32; ++v) yv[v] = y[(size_t)min(v, nh - 1) * Y.ld];
+      for (int v = 0; v < 8; ++v) yv[v] = y[(size_t)min(8 * w + v, nh - 1) * Y.ld];
     }
     double o[32];
 #pragma unroll
@@ -2703,34 +2705,25 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
         for (int v = 0; v < 32; ++v) o[v] += a * bv[v];
       }
     }
-    // sum the four partials pairwise through the (now free) staging area:
-    // wavefronts 2, 3 hand theirs to 0, 1, then 1 to 0, which updates Y
+    // the four partials side by side in the (now free) staging area; then
+    // wavefront w sums right-hand sides 8w .. 8w + 7 of all four and
+    // updates them (in a fixed order: partial 0, 1, 2, 3)
     __syncthreads();
-    if (w >= 2) {
 #pragma unroll
-      for (int v = 0; v < 32; ++v) pb2[(w - 2) * 64 + lane][v] = o[v];
-    }
+    for (int v = 0; v < 32; ++v) part[w][lane][v] = o[v];
     __syncthreads();
-    if (w < 2) {
-#pragma unroll
-      for (int v = 0; v < 32; ++v) o[v] += pb2[w * 64 + lane][v];
-    }
-    __syncthreads();
-    if (w == 1) {
-#pragma unroll
-      for (int v = 0; v < 32; ++v) pb2[lane][v] = o[v];
-    }
-    __syncthreads();
-    if (w == 0 && lane < rows) {
+    if (lane < rows) {
       HLU_G double* y = gptr<double>(Y.ptr) + lane + (size_t)h0 * Y.ld;
-      if (fused) {
 #pragma unroll
-        for (int v = 0; v < 32; ++v)
-          if (v < nh) sy[lane][h0 + v] = yv[v] + d0 * (o[v] + pb2[lane][v]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < 32; ++v)
-          if (v < nh) y[(size_t)v * Y.ld] = yv[v] + d0 * (o[v] + pb2[lane][v]);
+      for (int v = 0; v < 8; ++v) {
+        const int c = 8 * w + v;
+        if (c < nh) {
+          const double sum = ((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) +
+                             part[3][lane][c];
+          const double val = yv[v] + d0 * sum;
+          if (fused) sy[lane][h0 + c] = val;
+          else y[(size_t)c * Y.ld] = val;
+        }
       }
     }
     __syncthreads();
@@ -2738,23 +2731,31 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   if (fused) {
     // p3 := W (updated rows) on the matrix cores, taken transposed
     // ((W S)^T = S^T W^T) so that the sixteen lanes of a result register
-    // hold consecutive rows; 16 x 16 tiles dealt to the four wavefronts
+    // hold consecutive rows; wavefront w takes rows 16w .. 16w + 15 and the
+    // column tiles two at a time (one read of W per step, two independent
+    // accumulation chains)
     const int ntj = (nr + 15) >> 4, nq = (rows + 3) >> 2;
     HLU_G double* gy = gptr<double>(Y.ptr);
-    for (int t = w; t < 4 * ntj; t += 4) {
-      const int i0 = 16 * (t & 3), j0 = 16 * (t >> 2);
-      if (i0 >= rows) continue;
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-      for (int q = 0; q < nq; ++q) {
-        const int k = 4 * q + (lane >> 4);
-        const double a = k < rows ? sy[k][j0 + (lane & 15)] : 0.0;
-        const double b = sw[i0 + (lane & 15)][k];
-        acc = mfma16x16x4(a, b, acc);
-      }
+    const int i0 = 16 * w;
+    if (i0 < rows) {
+      for (int jt = 0; jt < ntj; jt += 2) {
+        const int j0 = 16 * jt, j1 = j0 + 16;
+        const bool two = jt + 1 < ntj;
+        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < nq; ++q) {
+          const int k = 4 * q + (lane >> 4);
+          const double b = sw[i0 + (lane & 15)][k];
+          const double a0 = k < rows ? sy[k][j0 + (lane & 15)] : 0.0;
+          const double a1 = (two && k < rows) ? sy[k][j1 + (lane & 15)] : 0.0;
+          acc0 = mfma16x16x4(a0, b, acc0);
+          acc1 = mfma16x16x4(a1, b, acc1);
+        }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + (lane & 15), j = j0 + (lane >> 4) + 4 * r;
-        if (i < rows && j < nr) gy[i + (size_t)j * Y.ld] = acc[r];
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + (lane & 15), j = j0 + (lane >> 4) + 4 * r;
+          if (i < rows && j < nr) gy[i + (size_t)j * Y.ld] = acc0[r];
+          if (two && i < rows && j + 16 < nr) gy[i + (size_t)(j + 16) * Y.ld] = acc1[r];
+        }
       }
     }
   }
