@@ -2682,9 +2682,11 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
 #pragma unroll
       for (int v = 0; v < 8; ++v) yv[v] = y[(size_t)min(8 * w + v, nh - 1) * Y.ld];
     }
-    double o[32];
+    // this wavefront's partial (64 rows x 32 right-hand sides) as eight
+    // 16 x 16 matrix-core tiles: row block ti, column block tj in acc[2 ti + tj]
+    v4d acc[8];
 #pragma unroll
-    for (int v = 0; v < 32; ++v) o[v] = 0.0;
+    for (int q = 0; q < 8; ++q) acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
     for (int item = w; item < nitems; item += 4) {
       double ra[16], rb[16];
       int kc;
@@ -2695,14 +2697,21 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
         sa[lane][u] = ra[u];
         sb[u][lane] = rb[u];
       }
-      for (int c = 0; c < kc; ++c) {
-        // the whole row of B first (the reads overlap), then the updates
-        const double a = sa[lane][c];
-        double bv[32];
+      // partial += A B over the chunk's 16 columns, four per step (columns
+      // at or beyond kc hold clamped copies and enter as zeros)
 #pragma unroll
-        for (int v = 0; v < 32; ++v) bv[v] = sb[c][v];
+      for (int q = 0; q < 4; ++q) {
+        const int c = 4 * q + (lane >> 4);
+        const bool in = c < kc;
+        double bq[2];
 #pragma unroll
-        for (int v = 0; v < 32; ++v) o[v] += a * bv[v];
+        for (int tj = 0; tj < 2; ++tj) bq[tj] = in ? sb[c][16 * tj + (lane & 15)] : 0.0;
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) {
+          const double aq = in ? sa[16 * ti + (lane & 15)][c] : 0.0;
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) acc[2 * ti + tj] = mfma16x16x4(aq, bq[tj], acc[2 * ti + tj]);
+        }
       }
     }
     // the four partials side by side in the (now free) staging area; then
@@ -2710,7 +2719,12 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     // updates them (in a fixed order: partial 0, 1, 2, 3)
     __syncthreads();
 #pragma unroll
-    for (int v = 0; v < 32; ++v) part[w][lane][v] = o[v];
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[w][16 * ti + (lane >> 4) + 4 * r][16 * tj + (lane & 15)] = acc[2 * ti + tj][r];
     __syncthreads();
     if (lane < rows) {
       HLU_G double* y = gptr<double>(Y.ptr) + lane + (size_t)h0 * Y.ld;
