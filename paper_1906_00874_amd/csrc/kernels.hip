@@ -2598,19 +2598,16 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   const bool fused = op.i2 == 1;
   double (*sw)[65] = reinterpret_cast<double (*)[65]>(smem + MVR_W);
   double (*sy)[65] = reinterpret_cast<double (*)[65]>(smem + MVR_Y);
+  // W's loads are issued here and stay in flight through the term products;
+  // it reaches LDS only before the first reduction barrier
+  double wv[16];
   if (fused) {
     const PRef W = op.p[0];
     const HLU_G double* gw = gptr<const double>(W.ptr);
-    double v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = tid + NT * u, i = e & 63, j = e >> 6;
-      v[u] = (i < rows && j < rows) ? gw[i + (size_t)j * W.ld] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = tid + NT * u, i = e & 63, j = e >> 6;
-      sw[i][j] = v[u];
+      wv[u] = (i < rows && j < rows) ? gw[i + (size_t)j * W.ld] : 0.0;
     }
   }
   if (op.i0 < 0) {
@@ -2717,6 +2714,13 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     // the four partials side by side in the (now free) staging area; then
     // wavefront w sums right-hand sides 8w .. 8w + 7 of all four and
     // updates them (in a fixed order: partial 0, 1, 2, 3)
+    if (fused && h0 == 0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + NT * u, i = e & 63, j = e >> 6;
+        sw[i][j] = wv[u];
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
@@ -3305,6 +3309,7 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
                                        int* ctrl, int n, int nhigh, int nhw, long long timeout) {
   __shared__ int s_op;
   __shared__ int s_keep;
+  __shared__ int s_next;
   const int tid = threadIdx.x;
   if (nhw <= 0) nhigh = 0;
   const int nlow = n - nhigh;
@@ -3396,6 +3401,7 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
           if (mr && lane == __ffsll((long long)mr) - 1) atomicMin(&s_keep, e - e0);
           __syncthreads();
           keep = ready && e - e0 == s_keep;
+          if (keep) s_next = pt.base + t;   // read by thread 0 after the barrier below
         }
         const unsigned long long mlo = __ballot(ready && !keep && !hi);
         const unsigned long long mhi = __ballot(ready && !keep && hi);
@@ -3425,8 +3431,7 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     }
     __syncthreads();
     if (tid == 0) {
-      const int kp = s_keep;
-      if (kp != 0x7fffffff) next = pt.base + succ[e0 + kp];
+      if (s_keep != 0x7fffffff) next = s_next;
       __hip_atomic_fetch_add(finished, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
