@@ -3361,6 +3361,12 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     if (g < 0) break;
     const DfPart& pt = parts[np == 1 ? 0 : df_part(parts, np, g)];
     const int idx = g - pt.base;
+    // the successor list is static: it is read as the op starts and arrives
+    // while the op runs, so only the decrements follow the op
+    const HLU_G int* succ_off = gptr<const int>(pt.succ_off);
+    const HLU_G int* succ = gptr<const int>(pt.succ);
+    const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
+    const int t_first = e0 + tid < e1 ? succ[e0 + tid] : -1;
     if (!run_op_masked<MASK>(reinterpret_cast<const Op*>(pt.ops)[idx], pt.tune) && tid == 0)
       __hip_atomic_store(&ctrl[2], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // one release fence (first wavefront, after the barrier that completed
@@ -3377,9 +3383,6 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (tid == 0) s_keep = 0x7fffffff;
     __syncthreads();
-    const HLU_G int* succ_off = gptr<const int>(pt.succ_off);
-    const HLU_G int* succ = gptr<const int>(pt.succ);
-    const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
     {
       HLU_G int* indeg = gptr<int>(pt.indeg);
       const int lane = tid & 63;
@@ -3388,7 +3391,7 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
         int t = -1;
         bool ready = false, hi = false;
         if (e < e1) {
-          t = succ[e];
+          t = eb == e0 ? t_first : succ[e];
           const int old = __hip_atomic_fetch_add(&indeg[t], -1, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
           ready = (old & 0x3fffffff) == 1;
