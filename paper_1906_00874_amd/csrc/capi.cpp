@@ -227,6 +227,7 @@ bool validate(const hlu::Plan& p, const hlu::Schedule& sc, std::string& why) {
           return bad("V^T X operands");
         if (Tt.dt != hlu::DT_F64 || Tt.trans || Tt.rankp || Tt.rows < V.cols || Tt.cols < X.cols)
           return bad("V^T X target");
+        if (o.i2 != 0 && o.i2 != 1) return bad("V^T X accumulate flag");
         break;
       }
       case hlu::OP_MVROW: {

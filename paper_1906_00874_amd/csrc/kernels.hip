@@ -2556,7 +2556,11 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = a0 + (l & 15), b = b0 + (l >> 4) + 4 * r;
-        if (a < k && b < nr) t[a + (size_t)b * T.ld] = acc[j][r];
+        if (a < k && b < nr) {
+          // i2 = 1: accumulate onto the partial product of the other rows
+          const size_t o = a + (size_t)b * T.ld;
+          t[o] = op.i2 == 1 ? t[o] + acc[j][r] : acc[j][r];
+        }
       }
     }
   }

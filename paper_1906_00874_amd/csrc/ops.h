@@ -44,6 +44,7 @@ enum OpType : int32_t {
   OP_ADDD = 6,     // p0 (dense FP64) -= p1 p2^T
   OP_ZERO = 7,     // p0 := 0 (static columns)
   OP_MVT = 8,      // solve: p3 (FP64, rows = live cols of p0) := p0^T p2
+                   // (i2 = 1: p3 += p0^T p2)
   OP_MVROW = 9,    // solve: p3 += d0 * sum over the terms [i0, i0 + i1) of the
                    // table at p2.ptr of X_t Y_t (X_t: rows of p3 x live cols,
                    // Y_t: FP64 with at least that many rows); i0 = -1: one

@@ -633,6 +633,14 @@ class Builder {
     r.cl = child;
     return r;
   }
+  PV row_range(const PV& v, int r0, int nrows) {   // rows r0 .. r0 + nrows - 1
+    PV r = v;
+    const int es = v.dt == DT_F64 ? 8 : 4;
+    r.off = v.off + (uint64_t)(v.trans ? (uint64_t)r0 * v.ld : (uint64_t)r0) * es;
+    r.rows = nrows;
+    r.cl = -1;
+    return r;
+  }
   PV dense_panel(int b) {             // F block as panel over its rows
     const LBlock& B = P.blk[b];
     PV v;
@@ -970,12 +978,40 @@ class Builder {
       if (Tobj[M.blk] < 0) Tobj[M.blk] = new_obj(-1, true);
       PV Xs = sub(X, M.s);
       PV T = tslot(M.blk, X.cols);
-      Op op = blank(OP_MVT);
-      op.p[0] = ref(v_panel(M.blk));
-      op.p[2] = ref(Xs);
-      op.p[3] = ref(T);
-      emit(op, {whole(B.objV, false), whole(B.objRank, false), acc_of(Xs, false), racc(Xs),
-                whole(T.obj, true)});
+      const Cluster& sc = P.cl[M.s];
+      if (sc.nleaves == 1) {
+        Op op = blank(OP_MVT);
+        op.p[0] = ref(v_panel(M.blk));
+        op.p[2] = ref(Xs);
+        op.p[3] = ref(T);
+        emit(op, {whole(B.objV, false), whole(B.objRank, false), acc_of(Xs, false), racc(Xs),
+                  whole(T.obj, true)});
+        continue;
+      }
+      // several leaves: the rows of all but the leaf this sweep solves last
+      // first (ready before that leaf, off the sweep's chain), then that
+      // leaf's rows accumulated (i2 = 1)
+      const int ll = P.leaves[backward ? sc.first_leaf : sc.first_leaf + sc.nleaves - 1];
+      const Cluster& lc = P.cl[ll];
+      const int rest0 = backward ? lc.size : 0, nrest = sc.size - lc.size;
+      PV V = v_panel(M.blk);
+      const int rl0 = backward ? sc.first_leaf + 1 : sc.first_leaf;
+      Acc xr = acc_of(Xs, false);
+      if (xr.l0 >= 0) xr = Acc{Xs.obj, rl0, rl0 + sc.nleaves - 1, false};
+      Op a = blank(OP_MVT);
+      a.p[0] = ref(row_range(V, rest0, nrest));
+      a.p[2] = ref(row_range(Xs, rest0, nrest));
+      a.p[3] = ref(T);
+      emit(a, {whole(B.objV, false), whole(B.objRank, false), xr, racc(Xs),
+               whole(T.obj, true)});
+      PV Xl = sub(Xs, ll);
+      Op b = blank(OP_MVT);
+      b.i2 = 1;
+      b.p[0] = ref(sub(V, ll));
+      b.p[2] = ref(Xl);
+      b.p[3] = ref(T);
+      emit(b, {whole(B.objV, false), whole(B.objRank, false), acc_of(Xl, false), racc(Xl),
+               whole(T.obj, true)});
     }
     std::vector<int> rows;
     cluster_leaves(node(nb).t, rows);

@@ -69,6 +69,8 @@ def accesses(o, terms):
         _segs(p[0], False, a)
         _segs(p[2], False, a)
         _segs(p[3], True, a)
+        if o["i2"] == 1:   # accumulates onto p3
+            _segs(p[3], False, a)
     elif t == OP_MVROW:
         _segs(p[3], True, a)
         if o["i2"] == 1:
