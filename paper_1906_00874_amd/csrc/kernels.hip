@@ -3308,12 +3308,19 @@ __device__ __forceinline__ bool run_op_masked(const Op& op, int tune) {
 // first NT) and runs it next without going through a ring; the others are
 // pushed.  Kept ops leave slots of the rings unfilled, so a waiting
 // workgroup also leaves once all n ops have finished (a counter).
+// an op descriptor as 32-bit words (staged in LDS by the dataflow executor)
+constexpr int DF_OPW = (int)(sizeof(Op) / 4);
+static_assert(sizeof(Op) % 4 == 0 && DF_OPW + 2 <= 64, "descriptor staging by the first wavefront");
+__device__ __forceinline__ int* s_desc_w(Op& o) { return reinterpret_cast<int*>(&o); }
+
 template <unsigned MASK>
 __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np, int* queue,
                                        int* ctrl, int n, int nhigh, int nhw, long long timeout) {
   __shared__ int s_op;
   __shared__ int s_keep;
   __shared__ int s_next;
+  __shared__ Op s_desc;       // the running op's descriptor
+  __shared__ int s_soff[2];   // and its successor range
   const int tid = threadIdx.x;
   if (nhw <= 0) nhigh = 0;
   const int nlow = n - nhigh;
@@ -3323,6 +3330,7 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
   const int cnt = hw ? nhigh : nlow;
   int* const finished = &ctrl[6];
   int next = -1;            // successor kept by the last op (thread 0)
+  bool have = false;        // s_desc and s_soff already hold that op's (uniform)
   for (;;) {
     if (tid == 0) {
       int v = next;
@@ -3365,13 +3373,21 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     if (g < 0) break;
     const DfPart& pt = parts[np == 1 ? 0 : df_part(parts, np, g)];
     const int idx = g - pt.base;
-    // the successor list is static: it is read as the op starts and arrives
-    // while the op runs, so only the decrements follow the op
     const HLU_G int* succ_off = gptr<const int>(pt.succ_off);
     const HLU_G int* succ = gptr<const int>(pt.succ);
-    const int e0 = succ_off[idx], e1 = succ_off[idx + 1];
+    const HLU_G int* opw = gptr<const int>(pt.ops);
+    // the descriptor and successor range go to LDS in one round trip (a
+    // kept op's were fetched while its predecessor's fence and decrements ran)
+    if (!have) {
+      if (tid < DF_OPW) s_desc_w(s_desc)[tid] = opw[(size_t)idx * DF_OPW + tid];
+      else if (tid < DF_OPW + 2) s_soff[tid - DF_OPW] = succ_off[idx + tid - DF_OPW];
+      __syncthreads();
+    }
+    // the successor list is static: it is read as the op starts and arrives
+    // while the op runs, so only the decrements follow the op
+    const int e0 = s_soff[0], e1 = s_soff[1];
     const int t_first = e0 + tid < e1 ? succ[e0 + tid] : -1;
-    if (!run_op_masked<MASK>(reinterpret_cast<const Op*>(pt.ops)[idx], pt.tune) && tid == 0)
+    if (!run_op_masked<MASK>(s_desc, pt.tune) && tid == 0)
       __hip_atomic_store(&ctrl[2], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // one release fence (first wavefront, after the barrier that completed
     // every wavefront's stores) publishes the op's writes; then all threads
@@ -3384,6 +3400,13 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
     // pushes with one atomic per ring.  The lowest ready position among the
     // first NT successors is not pushed: this workgroup runs it next.
     __syncthreads();
+    // the first successor is the one kept whenever it becomes ready: its
+    // descriptor and successor range are fetched now (first wavefront,
+    // thread 0's candidate), under the fence and the decrements
+    int pre = 0;
+    const int c = __builtin_amdgcn_readfirstlane(t_first);
+    if (tid < DF_OPW + 2 && c >= 0)
+      pre = tid < DF_OPW ? opw[(size_t)c * DF_OPW + tid] : succ_off[c + tid - DF_OPW];
     if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (tid == 0) s_keep = 0x7fffffff;
     __syncthreads();
@@ -3437,6 +3460,13 @@ __device__ __forceinline__ void df_run(const DfPart* __restrict__ parts, int np,
       }
     }
     __syncthreads();
+    // position 0 kept: that is c, whose descriptor is in flight above (the
+    // next iteration's first barrier orders these writes before its reads)
+    have = s_keep == 0;
+    if (have && tid < DF_OPW + 2) {
+      if (tid < DF_OPW) s_desc_w(s_desc)[tid] = pre;
+      else s_soff[tid - DF_OPW] = pre;
+    }
     if (tid == 0) {
       if (s_keep != 0x7fffffff) next = s_next;
       __hip_atomic_fetch_add(finished, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
