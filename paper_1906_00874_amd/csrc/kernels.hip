@@ -2487,33 +2487,33 @@ __device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
 }
 
 // ---------------------------------------------------------------- solve updates
-// T := V^T X (V: n x k panel, X: n x nrhs FP64, T: FP64 with ld >= k), rows
-// streamed in chunks of 32; each thread prefetches the next chunk into
-// registers while the current one is multiplied.
-#define LDS_MVT (2 * 32 * 65 * 8)
+// T := V^T X (V: n x k panel, X: n x nrhs FP64, T: FP64 with ld >= k; with
+// i2 = 1, T += V^T X), rows streamed in chunks of 64; each thread prefetches
+// the next chunk into registers while the current one is multiplied.
+#define LDS_MVT (2 * 64 * 65 * 8)
 __device__ __forceinline__ void mvt_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef V = op.p[0], X = op.p[2], T = op.p[3];
   const int n = V.rows, k = pcols(V), nr = pcols(X);
   double (*sv)[65] = reinterpret_cast<double (*)[65]>(smem);
-  double (*sx)[65] = reinterpret_cast<double (*)[65]>(smem + 32 * 65 * 8);
+  double (*sx)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   // T^T = X^T V on the matrix cores (the sixteen lanes of a result register
   // then hold consecutive rows of T): 16 x 16 tiles over (nrhs, k), tile
-  // w + 4j to wavefront w
+  // w + 4j to wavefront w; rows in chunks of 64 (one leaf: one round trip)
   const int nta = (k + 15) >> 4, ntile = nta * ((nr + 15) >> 4);
   v4d acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
-  double pv[8], px[8];
+  double pv[16], px[16];
   const GView gv = gview(V), gx = gview(X);
   // loads only: lanes outside V or X read a clamped element and are zeroed
   // when the chunk is stored to LDS, so the prefetch stays in flight
   auto fetch = [&](int r0) {
-    int ri[8], cv[8], cx[8];
+    int ri[16], cv[16], cx[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = tid + NT * u, i = q & 31, j = q >> 5;
+    for (int u = 0; u < 16; ++u) {
+      const int q = tid + NT * u, i = q & 63, j = q >> 6;
       ri[u] = min(r0 + i, n - 1);
       cv[u] = min(j, k - 1);
       cx[u] = min(j, nr - 1);
@@ -2523,17 +2523,17 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
   };
   const int nn = (k > 0 && nr > 0) ? n : 0;
   if (nn > 0) fetch(0);
-  for (int r0 = 0; r0 < nn; r0 += 32) {
+  for (int r0 = 0; r0 < nn; r0 += 64) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = tid + NT * u, i = q & 31, j = q >> 5;
+    for (int u = 0; u < 16; ++u) {
+      const int q = tid + NT * u, i = q & 63, j = q >> 6;
       const bool in = r0 + i < n;
       sv[i][j] = (in && j < k) ? pv[u] : 0.0;
       sx[i][j] = (in && j < nr) ? px[u] : 0.0;
     }
     __syncthreads();
-    if (r0 + 32 < nn) fetch(r0 + 32);
-    const int nq = (min(32, n - r0) + 3) >> 2;   // rows beyond n are zero
+    if (r0 + 64 < nn) fetch(r0 + 64);
+    const int nq = (min(64, n - r0) + 3) >> 2;   // rows beyond n are zero
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int tt = w + 4 * j;
@@ -2614,33 +2614,29 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
       wv[u] = (i < rows && j < rows) ? gw[i + (size_t)j * W.ld] : 0.0;
     }
   }
-  if (op.i0 < 0) {
-    // one term carried in the op itself (p1 its factor, p2 its operand)
-    if (tid == 0) {
-      Term tm;
-      tm.X = op.p[1];
-      tm.Y = op.p[2];
-      tm.xo = tm.yo = 0;
-      tm.pad[0] = tm.pad[1] = 0;
-      st[0] = tm;
-    }
+  // one term carried in the op itself (p1 its factor, p2 its operand): read
+  // from the descriptor, with no staging and no barrier before the loads
+  const bool inl = op.i0 < 0;
+  int kk0 = 0;
+  if (inl) {
+    kk0 = pcols(op.p[1]);
   } else {
     const HLU_G uint64_t* src = gptr<const uint64_t>(op.p[2].ptr) + (size_t)op.i0 * 10;
     uint64_t* dst = reinterpret_cast<uint64_t*>(st);
     for (int e = tid; e < nt * 10; e += NT) dst[e] = src[e];
-  }
-  __syncthreads();
-  for (int t = tid; t < nt; t += NT) kk[t] = pcols(st[t].X);
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int t = 0; t < nt; ++t) {
-      first[t] = acc;
-      acc += (kk[t] + 15) >> 4;
+    __syncthreads();
+    for (int t = tid; t < nt; t += NT) kk[t] = pcols(st[t].X);
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int t = 0; t < nt; ++t) {
+        first[t] = acc;
+        acc += (kk[t] + 15) >> 4;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  const int nitems = nt > 0 ? first[nt - 1] + ((kk[nt - 1] + 15) >> 4) : 0;
+  const int nitems = inl ? (kk0 + 15) >> 4 : nt > 0 ? first[nt - 1] + ((kk[nt - 1] + 15) >> 4) : 0;
   // item -> (term, first column): a short scan over the terms
   auto locate = [&](int item, int& t, int& c0) {
     t = 0;
@@ -2656,19 +2652,20 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
   // clamped element: their products land only in outputs that are never
   // stored, so nothing is zeroed and all 32 loads are issued together.
   auto fetch = [&](int item, int h0, int nh, double (&ra)[16], double (&rb)[16], int& kc) {
-    int t, c0;
-    locate(item, t, c0);
-    const Term& tp = st[t];
-    kc = min(16, kk[t] - c0);
+    int t = 0, c0 = item * 16;
+    if (!inl) locate(item, t, c0);
+    const PRef& tX = inl ? op.p[1] : st[t].X;
+    const PRef& tY = inl ? op.p[2] : st[t].Y;
+    kc = min(16, (inl ? kk0 : kk[t]) - c0);
     int ri[16], cj[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       ri[u] = min(lane, rows - 1);
       cj[u] = c0 + min(u, kc - 1);
     }
-    gload(gview(tp.X), ri, cj, ra);
+    gload(gview(tX), ri, cj, ra);
     const HLU_G double* pb =
-        gptr<const double>(tp.Y.ptr) + (size_t)(h0 + min(lane, nh - 1)) * tp.Y.ld;
+        gptr<const double>(tY.ptr) + (size_t)(h0 + min(lane, nh - 1)) * tY.ld;
 #pragma unroll
     for (int u = 0; u < 16; ++u) rb[u] = pb[cj[u]];
   };
@@ -2785,9 +2782,10 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     double fl = fused ? 2.0 * rows * rows * nr : 0.0;
     double by = 16.0 * rows * nr + (fused ? 8.0 * rows * rows : 0.0);
     for (int t = 0; t < nt; ++t) {
-      const PRef A = st[t].X;
-      fl += 2.0 * rows * kk[t] * nr;
-      by += (A.dt == DT_F64 ? 8.0 : 4.0) * rows * kk[t] + 8.0 * kk[t] * nr;
+      const PRef A = inl ? op.p[1] : st[t].X;
+      const int k = inl ? kk0 : kk[t];
+      fl += 2.0 * rows * k * nr;
+      by += (A.dt == DT_F64 ? 8.0 : 4.0) * rows * k + 8.0 * k * nr;
     }
     put_cost(op, fl, by);
   }
