@@ -2494,6 +2494,9 @@ __device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
 __device__ __forceinline__ void mvt_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef V = op.p[0], X = op.p[2], T = op.p[3];
+  // the live rank k and right-hand-side count nr are read from device
+  // memory; the loads are addressed by the stored widths, so they need not
+  // wait for those reads, and k and nr only mask the chunks in LDS
   const int n = V.rows, k = pcols(V), nr = pcols(X);
   double (*sv)[65] = reinterpret_cast<double (*)[65]>(smem);
   double (*sx)[65] = reinterpret_cast<double (*)[65]>(smem + 64 * 65 * 8);
@@ -2515,13 +2518,13 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
     for (int u = 0; u < 16; ++u) {
       const int q = tid + NT * u, i = q & 63, j = q >> 6;
       ri[u] = min(r0 + i, n - 1);
-      cv[u] = min(j, k - 1);
-      cx[u] = min(j, nr - 1);
+      cv[u] = min(j, V.cols - 1);
+      cx[u] = min(j, X.cols - 1);
     }
     gload(gv, ri, cv, pv);
     gload(gx, ri, cx, px);
   };
-  const int nn = (k > 0 && nr > 0) ? n : 0;
+  const int nn = (V.cols > 0 && X.cols > 0) ? n : 0;
   if (nn > 0) fetch(0);
   for (int r0 = 0; r0 < nn; r0 += 64) {
 #pragma unroll
@@ -2585,7 +2588,11 @@ static_assert(sizeof(Term) == 80, "term records are staged as ten 8-byte words")
 __device__ __forceinline__ void mvrow_body(const Op& op) {
   char* const smem = hlu_lds;
   const PRef Y = op.p[3];
-  const int nt = min(op.i1, MVR_TMAX), rows = Y.rows, nr = pcols(Y);
+  // nr (the live right-hand sides) and a low-rank term's live width are read
+  // from device memory; loads are addressed by the static capacities (Y.cols,
+  // the term's cols) so they need not wait for those reads, and the live
+  // counts only mask products and stores
+  const int nt = min(op.i1, MVR_TMAX), rows = Y.rows, nr = pcols(Y), ncap = Y.cols;
   const double d0 = op.d0;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   double (*sa)[17] = reinterpret_cast<double (*)[17]>(smem + w * (64 * 17 + 16 * 65) * 8);
@@ -2636,7 +2643,8 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     }
     __syncthreads();
   }
-  const int nitems = inl ? (kk0 + 15) >> 4 : nt > 0 ? first[nt - 1] + ((kk[nt - 1] + 15) >> 4) : 0;
+  const int nitems = inl ? (op.p[1].cols + 15) >> 4
+                         : nt > 0 ? first[nt - 1] + ((kk[nt - 1] + 15) >> 4) : 0;
   // item -> (term, first column): a short scan over the terms
   auto locate = [&](int item, int& t, int& c0) {
     t = 0;
@@ -2656,21 +2664,23 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     if (!inl) locate(item, t, c0);
     const PRef& tX = inl ? op.p[1] : st[t].X;
     const PRef& tY = inl ? op.p[2] : st[t].Y;
-    kc = min(16, (inl ? kk0 : kk[t]) - c0);
+    // columns clamped to the stored width (inline) or the live one
+    const int kcs = min(16, (inl ? tX.cols : kk[t]) - c0);
     int ri[16], cj[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       ri[u] = min(lane, rows - 1);
-      cj[u] = c0 + min(u, kc - 1);
+      cj[u] = c0 + min(u, kcs - 1);
     }
+    kc = min(kcs, (inl ? kk0 : kk[t]) - c0);
     gload(gview(tX), ri, cj, ra);
     const HLU_G double* pb =
         gptr<const double>(tY.ptr) + (size_t)(h0 + min(lane, nh - 1)) * tY.ld;
 #pragma unroll
     for (int u = 0; u < 16; ++u) rb[u] = pb[cj[u]];
   };
-  for (int h0 = 0; h0 < nr; h0 += 32) {
-    const int nh = min(32, nr - h0);
+  for (int h0 = 0; h0 < ncap; h0 += 32) {
+    const int nh = min(32, nr - h0), nhs = min(32, ncap - h0);   // live, stored
     // the old values of the rows, eight right-hand sides per wavefront (the
     // ones it finishes below), in flight while the terms are multiplied;
     // lanes beyond the rows or right-hand sides read a clamped element
@@ -2678,7 +2688,7 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     {
       const HLU_G double* y = gptr<const double>(Y.ptr) + min(lane, rows - 1) + (size_t)h0 * Y.ld;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) yv[v] = y[(size_t)min(8 * w + v, nh - 1) * Y.ld];
+      for (int v = 0; v < 8; ++v) yv[v] = y[(size_t)min(8 * w + v, nhs - 1) * Y.ld];
     }
     // this wavefront's partial (64 rows x 32 right-hand sides) as eight
     // 16 x 16 matrix-core tiles: row block ti, column block tj in acc[2 ti + tj]
@@ -2688,7 +2698,7 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     for (int item = w; item < nitems; item += 4) {
       double ra[16], rb[16];
       int kc;
-      fetch(item, h0, nh, ra, rb, kc);
+      fetch(item, h0, nhs, ra, rb, kc);
       // the slices were last read by this wavefront's previous chunk (program order)
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
