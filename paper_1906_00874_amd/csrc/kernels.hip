@@ -256,8 +256,10 @@ __device__ __forceinline__ void put_cost(const Op& op, double flops, double byte
   }
 }
 
-__device__ __forceinline__ void start_tick(const Op& op) {
-  if (op.cost && threadIdx.x == 0) gptr<double>(op.cost)[4] = (double)wall_clock64();
+// an op's start time, taken as it starts and stored in its record once the
+// op has run (a store at the start would wait for the loads in flight)
+__device__ __forceinline__ void put_start(const Op& op, long long t0) {
+  if (op.cost && threadIdx.x == 0) gptr<double>(op.cost)[4] = (double)t0;
 }
 
 // one step of a wave argmax (largest value, smallest index among equals)
@@ -3191,8 +3193,7 @@ __device__ __noinline__ void d_invapply(const Op& op) { invapply_body(op); }
 // types (one launch per wave of the schedule).  Each op type carves its
 // tiles out of the same dynamic LDS buffer, so a launch requests the
 // largest footprint among the types it contains.
-__device__ __forceinline__ void run_op(const Op& op) {
-  start_tick(op);
+__device__ __forceinline__ void run_op_body(const Op& op) {
   switch (op.type) {
     case OP_GETRF: d_getrf(op); break;
     case OP_TRSM_L:
@@ -3208,6 +3209,11 @@ __device__ __forceinline__ void run_op(const Op& op) {
     case OP_INVAPPLY: d_invapply(op); break;
     default: break;
   }
+}
+__device__ __forceinline__ void run_op(const Op& op) {
+  const long long t0 = wall_clock64();
+  run_op_body(op);
+  put_start(op, t0);
 }
 
 __global__ void __launch_bounds__(NT) k_wave(const Op* __restrict__ ops) {
@@ -3265,8 +3271,7 @@ constexpr unsigned DF_FACTOR_TYPES = (1u << OP_GETRF) | (1u << OP_TRSM_L) | (1u 
 constexpr unsigned DF_SOLVE_TYPES = (1u << OP_MVT) | (1u << OP_MVROW) | (1u << OP_INVAPPLY);
 
 template <unsigned MASK>
-__device__ __forceinline__ bool run_op_masked(const Op& op, int tune) {
-  start_tick(op);
+__device__ __forceinline__ bool run_op_masked_body(const Op& op, int tune) {
   switch (op.type) {
     case OP_GETRF: if constexpr ((MASK >> OP_GETRF) & 1) { d_getrf(op); return true; } break;
     case OP_TRSM_L:
@@ -3303,6 +3308,13 @@ __device__ __forceinline__ bool run_op_masked(const Op& op, int tune) {
     default: break;
   }
   return false;
+}
+template <unsigned MASK>
+__device__ __forceinline__ bool run_op_masked(const Op& op, int tune) {
+  const long long t0 = wall_clock64();
+  const bool ok = run_op_masked_body<MASK>(op, tune);
+  put_start(op, t0);
+  return ok;
 }
 
 // The ready ops sit in two FIFO rings of one queue array: the low ring
