@@ -2538,13 +2538,14 @@ __device__ __forceinline__ void mvt_body(const Op& op) {
     }
     __syncthreads();
     if (r0 + 64 < nn) fetch(r0 + 64);
-    const int nq = (min(64, n - r0) + 3) >> 2;   // rows beyond n are zero
+    // all 16 steps of the chunk, straight-line (rows beyond n are zero)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int tt = w + 4 * j;
       if (tt < ntile) {
         const int a0 = 16 * (tt % nta), b0 = 16 * (tt / nta);
-        for (int q = 0; q < nq; ++q) {
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
           const int i = 4 * q + (l >> 4);
           acc[j] = mfma16x16x4(sx[i][b0 + (l & 15)], sv[i][a0 + (l & 15)], acc[j]);
         }
@@ -2715,10 +2716,14 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
         const bool in = c < kc;
         double bq[2];
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) bq[tj] = in ? sb[c][16 * tj + (lane & 15)] : 0.0;
+        for (int tj = 0; tj < 2; ++tj) {
+          const double v = sb[c][16 * tj + (lane & 15)];
+          bq[tj] = in ? v : 0.0;
+        }
 #pragma unroll
         for (int ti = 0; ti < 4; ++ti) {
-          const double aq = in ? sa[16 * ti + (lane & 15)][c] : 0.0;
+          const double av = sa[16 * ti + (lane & 15)][c];
+          const double aq = in ? av : 0.0;
 #pragma unroll
           for (int tj = 0; tj < 2; ++tj) acc[2 * ti + tj] = mfma16x16x4(aq, bq[tj], acc[2 * ti + tj]);
         }
@@ -2743,18 +2748,20 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
         for (int r = 0; r < 4; ++r)
           part[w][16 * ti + (lane >> 4) + 4 * r][16 * tj + (lane & 15)] = acc[2 * ti + tj][r];
     __syncthreads();
-    if (lane < rows) {
-      HLU_G double* y = gptr<double>(Y.ptr) + lane + (size_t)h0 * Y.ld;
+    {
+      // fused: every row and column of the group goes to sy, zero outside
+      // the rows and the live right-hand sides, so that the product with W
+      // below reads sy without selects
+      HLU_G double* y = gptr<double>(Y.ptr) + min(lane, rows - 1) + (size_t)h0 * Y.ld;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int c = 8 * w + v;
-        if (c < nh) {
-          const double sum = ((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) +
-                             part[3][lane][c];
-          const double val = yv[v] + d0 * sum;
-          if (fused) sy[lane][h0 + c] = val;
-          else y[(size_t)c * Y.ld] = val;
-        }
+        const bool ok = lane < rows && c < nh;
+        const double sum = ((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) +
+                           part[3][lane][c];
+        const double val = yv[v] + d0 * sum;
+        if (fused) sy[lane][h0 + c] = ok ? val : 0.0;
+        else if (ok) y[(size_t)c * Y.ld] = val;
       }
     }
     __syncthreads();
@@ -2765,7 +2772,7 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
     // hold consecutive rows; wavefront w takes rows 16w .. 16w + 15 and the
     // column tiles two at a time (one read of W per step, two independent
     // accumulation chains)
-    const int ntj = (nr + 15) >> 4, nq = (rows + 3) >> 2;
+    const int ntj = (nr + 15) >> 4;
     HLU_G double* gy = gptr<double>(Y.ptr);
     const int i0 = 16 * w;
     if (i0 < rows) {
@@ -2773,13 +2780,15 @@ __device__ __forceinline__ void mvrow_body(const Op& op) {
         const int j0 = 16 * jt, j1 = j0 + 16;
         const bool two = jt + 1 < ntj;
         v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        for (int q = 0; q < nq; ++q) {
+        // all 16 steps, straight-line: W and sy are zero beyond the rows,
+        // and sy beyond the live right-hand sides (a second tile past the
+        // last one reads zeros)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
           const int k = 4 * q + (lane >> 4);
           const double b = sw[i0 + (lane & 15)][k];
-          const double a0 = k < rows ? sy[k][j0 + (lane & 15)] : 0.0;
-          const double a1 = (two && k < rows) ? sy[k][j1 + (lane & 15)] : 0.0;
-          acc0 = mfma16x16x4(a0, b, acc0);
-          acc1 = mfma16x16x4(a1, b, acc1);
+          acc0 = mfma16x16x4(sy[k][j0 + (lane & 15)], b, acc0);
+          acc1 = mfma16x16x4(sy[k][j1 + (lane & 15)], b, acc1);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
