@@ -1730,12 +1730,18 @@ __device__ __forceinline__ void gram_step(const double (&cv)[NB], v4d (&acc)[5])
 template <int NB, int W>
 __device__ __forceinline__ void gram_tiles(double (*C)[KM + 1], int nq, v4d (&acc)[5]) {
   const int l = threadIdx.x & 63;
-  for (int q = 0; q < nq; ++q) {
-    const int i = 4 * q + (l >> 4);
-    double cv[NB];
+  // steps in groups of four, straight-line inside a group (the matrix-core
+  // builtins are convergent, so the compiler does not unroll a loop with a
+  // variable trip count); rows past the chunk's end are zero in LDS
+  for (int q0 = 0; q0 < nq; q0 += 4) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) cv[c] = C[i][16 * c + (l & 15)];
-    gram_step<NB, W, 0>(cv, acc);
+    for (int qq = 0; qq < 4; ++qq) {
+      const int i = 4 * (q0 + qq) + (l >> 4);
+      double cv[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) cv[c] = C[i][16 * c + (l & 15)];
+      gram_step<NB, W, 0>(cv, acc);
+    }
   }
 }
 
@@ -1930,14 +1936,26 @@ __device__ __forceinline__ void apply_tiles(double (*C)[KM + 1], double (*T)[KM 
                                             int w, v4d (&acc)[2][2]) {
   const int l = threadIdx.x & 63;
   const int nq = (K + 3) >> 2;
-  for (int q = 0; q < nq; ++q) {
-    const int kk = 4 * q + (l >> 4);
+  // steps in groups of four, straight-line inside a group (columns past K
+  // enter as zeros)
+  for (int q0 = 0; q0 < nq; q0 += 4)
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int kk = 4 * (q0 + qq) + (l >> 4);
     const bool in = kk < K;
     double cv[2], tv[NCT];
+    // read unconditionally (kk < KM), then select: a conditional read would
+    // become a branch with a wait of its own per read
 #pragma unroll
-    for (int u = 0; u < 2; ++u) cv[u] = in ? C[16 * (w + 2 * u) + (l & 15)][kk] : 0.0;
+    for (int u = 0; u < 2; ++u) {
+      const double v = C[16 * (w + 2 * u) + (l & 15)][min(kk, KM - 1)];
+      cv[u] = in ? v : 0.0;
+    }
 #pragma unroll
-    for (int c = 0; c < NCT; ++c) tv[c] = in ? T[kk][16 * c + (l & 15)] : 0.0;
+    for (int c = 0; c < NCT; ++c) {
+      const double v = T[min(kk, KM - 1)][16 * c + (l & 15)];
+      tv[c] = in ? v : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -2290,12 +2308,14 @@ __device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
       for (int t = wid; t < nbx * nby; t += 4) {
         const int i0 = 16 * (t % nbx), j0 = 16 * (t / nbx);
         v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int q = 0; q < nq; ++q) {
-          const int c = 4 * q + (l >> 4);
+        for (int q0 = 0; q0 < nq; q0 += 4)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int c = 4 * (q0 + qq) + (l >> 4);
           const bool in = c < K;
-          const double a = in ? sh.gx[i0 + (l & 15)][c] : 0.0;
-          const double b = in ? sh.gy[j0 + (l & 15)][c] : 0.0;
-          acc = mfma16x16x4(a, b, acc);
+          const int cc = min(c, KM - 1);
+          const double av = sh.gx[i0 + (l & 15)][cc], bv = sh.gy[j0 + (l & 15)][cc];
+          acc = mfma16x16x4(in ? av : 0.0, in ? bv : 0.0, acc);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -2326,13 +2346,14 @@ __device__ __forceinline__ void d_trunc(const Op& op, int tune = 0) {
         for (int t = wid; t < ntl; t += 4) {
           const int a0 = 16 * gram_tile_row(nb, t), b0 = 16 * gram_tile_col(nb, t);
           v4d acc = {0.0, 0.0, 0.0, 0.0};
-          for (int q = 0; q < nq; ++q) {
-            const int j = 4 * q + (l >> 4);
+          for (int q0 = 0; q0 < nq; q0 += 4)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int j = 4 * (q0 + qq) + (l >> 4);
             const bool in = j < ry;
             const int fj = jphys(min(j, KM - 1));
-            const double a = in ? sh.m[a0 + (l & 15)][fj] : 0.0;
-            const double b = in ? sh.m[b0 + (l & 15)][fj] : 0.0;
-            acc = mfma16x16x4(a, b, acc);
+            const double av = sh.m[a0 + (l & 15)][fj], bv = sh.m[b0 + (l & 15)][fj];
+            acc = mfma16x16x4(in ? av : 0.0, in ? bv : 0.0, acc);
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
