@@ -408,7 +408,7 @@ def test_block_tree_every_node_against_admissibility(level, leaf, eta):
 # leaves / dense blocks / low-rank blocks of the sphere workloads at eta 2,
 # counted by an independent throwaway implementation of Algorithms 1 and 2
 # (NumPy, written separately from this oracle before it existed)
-SURVEY_COUNTS = [
+INDEPENDENT_COUNTS = [
     (3, 32, 52, 418, 894),
     (4, 32, 217, 1845, 3922),
     (5, 32, 875, 7645, 18096),
@@ -416,7 +416,7 @@ SURVEY_COUNTS = [
 ]
 
 
-@pytest.mark.parametrize("level,leaf,nleaves,ndense,nlr", SURVEY_COUNTS)
+@pytest.mark.parametrize("level,leaf,nleaves,ndense,nlr", INDEPENDENT_COUNTS)
 def test_block_counts_match_independent_count(level, leaf, nleaves, ndense, nlr):
     xyz, _ = icosphere(level)
     root, _, leaves = O.cluster_tree(xyz, leaf)
