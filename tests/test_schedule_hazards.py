@@ -199,3 +199,49 @@ def test_scratch_is_written_before_it_is_read(operation):
             if w:
                 written[np.searchsorted(bounds, lo):np.searchsorted(bounds, hi)] = True
     assert unread == 0
+
+
+def test_solve_vtx_split_over_multi_leaf_sources():
+    """A V^T X product whose source cluster has several leaves is emitted as
+    two ops on the same T slot: the rows of every leaf but the one the sweep
+    solves last (writing T), then that leaf's rows alone, accumulating
+    (i2 = 1), ordered by a dependency path.  The two parts' rows of V (and of
+    X) are adjacent, the accumulating one after the first in the forward
+    sweep and before it in the backward sweep, and it covers one leaf."""
+    xyz, area = icosphere(3)
+    h = P.HLU(xyz, area, assemble=False, leaf=64, eta=2.0, eps=1e-5, cap=32,
+              precision=P.PREC_MIXED, max_nrhs=4, cap_mv=64, eps_mv=1e-12, refine_tol=0.0)
+    ops, waves, terms = h.schedule_ops(1)
+    off, su = h.schedule_graph(1)
+    n = len(ops)
+    mvt = np.flatnonzero(ops["type"] == OP_MVT)
+    acc = [k for k in mvt if ops["i2"][k] == 1]
+    assert acc, "no multi-leaf source in this schedule"
+    succ = [set(su[off[u]:off[u + 1]]) for u in range(n)]
+
+    def reaches(u, v):
+        seen, todo = {u}, [u]
+        while todo:
+            x = todo.pop()
+            for y in succ[x]:
+                if y == v:
+                    return True
+                if y not in seen and y < v:
+                    seen.add(y)
+                    todo.append(y)
+        return False
+
+    for k in acc:
+        t = int(ops["p"][k, 3]["ptr"])
+        rest = [r for r in mvt if r < k and ops["i2"][r] == 0 and int(ops["p"][r, 3]["ptr"]) == t]
+        assert rest, f"accumulating product {k} without a first part"
+        r = rest[-1]
+        assert 0 < int(ops["p"][k, 0]["rows"]) <= 64
+        assert int(ops["p"][k, 2]["rows"]) == int(ops["p"][k, 0]["rows"])
+        assert int(ops["p"][r, 2]["rows"]) == int(ops["p"][r, 0]["rows"])
+        assert reaches(r, k), f"no dependency path from {r} to {k}"
+        for q in (0, 2):
+            es = 8 if int(ops["p"][k, q]["dt"]) == 0 else 4
+            pa, ra = int(ops["p"][k, q]["ptr"]), int(ops["p"][k, q]["rows"])
+            pr, rr = int(ops["p"][r, q]["ptr"]), int(ops["p"][r, q]["rows"])
+            assert pa == pr + rr * es or pr == pa + ra * es, (k, r, q)
